@@ -1,0 +1,244 @@
+"""FP64 CPU oracle for the non-orthogonal local submatrix method (NOLSM).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library calls this module; only the
+tests, the smoke check and the benchmark's CPU-baseline leg do.  It shares no
+code with the GPU path: inputs come from the seeded generators in `workloads`,
+and every step below is a plain, slow restatement of the paper.
+
+What the method computes (paper, Sec. II "Overview of the Problem"):
+
+  * Eq. 5: at zero electronic temperature the density matrix is
+        D = 1/2 (I - sign(S^-1 H0 - mu I)) S^-1.
+  * Submatrix method, steps 1-3 (Sec. II, Fig. 1): for a column (here: the
+    column block of one molecule, the "one submatrix for several columns"
+    variant), keep the rows that are non-zero in that column, evaluate the
+    matrix function on the dense submatrix, and write the columns that belong
+    to the molecule back into a result with the pattern of the input.
+  * Eq. 8: the non-orthogonal variant combines the patterns of H0 and S, builds
+    T_i(H0) and T_i(S), and evaluates
+        T_i(D) = 1/2 (I - sign(T_i(S)^-1 T_i(H0) - mu I)) T_i(S)^-1.
+  * Eq. 4: E_elec = Tr(D H0).
+
+Because sign() of a diagonalisable matrix with real spectrum is defined through
+its eigen-decomposition, the oracle evaluates Eq. 8 exactly via the generalized
+symmetric eigenproblem H_k C = S_k C Lambda, C^T S_k C = I:
+    S_k^-1 H_k - mu I = C (Lambda - mu) C^-1,  C^-1 = C^T S_k,  S_k^-1 = C C^T,
+    T_k(D) = 1/2 C (I - sgn(Lambda - mu)) C^T S_k C C^T = C theta(mu - Lambda) C^T,
+with theta(x) = 1 for x > 0, 0 for x < 0 and 1/2 at x = 0 (sign(0) = 0).
+
+Eq. 6-7 (Newton-Schulz) is provided as `newton_schulz_sign`, used by tests and as
+the source of iteration-count labels; the oracle's density never depends on it.
+
+Readings of points the paper leaves open are listed in the design notes: the
+molecule-column grouping, mu = 0, no spin factor (Tr(DS) counts occupied
+orbitals), sign(0) = 0, and the scaling X0 = A / b with b >= rho(A) that puts the
+spectrum inside the Newton-Schulz basin.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.linalg
+
+
+# ----------------------------------------------------------------- step 1: submatrix
+
+def members(pattern, k: int) -> np.ndarray:
+    """Molecules whose block in column block k is stored (ascending, includes k).
+
+    Submatrix method step 1: the rows kept for column block k are those with
+    non-zero elements in that column block; H and S share one pattern here, so
+    this is already the combined pattern of Eq. 8.
+    """
+    return np.asarray(pattern.rowblk[pattern.colptr[k]:pattern.colptr[k + 1]])
+
+
+def _find_block(pattern, I: int, J: int) -> int:
+    """Index of stored block (I, J) or -1 (binary search of column J's rows)."""
+    lo, hi = int(pattern.colptr[J]), int(pattern.colptr[J + 1])
+    rows = pattern.rowblk[lo:hi]
+    p = int(np.searchsorted(rows, I))
+    if p < rows.shape[0] and int(rows[p]) == I:
+        return lo + p
+    return -1
+
+
+def _block(pattern, val: np.ndarray, t: int) -> np.ndarray:
+    """Stored block t as a dense dI x dJ array (column-major storage)."""
+    I = int(pattern.rowblk[t])
+    J = int(np.searchsorted(pattern.colptr, t, side="right") - 1)
+    dI, dJ = int(pattern.blk_dim[I]), int(pattern.blk_dim[J])
+    start = int(pattern.valoff[t])
+    return val[start:start + dI * dJ].reshape(dJ, dI).T
+
+
+def gather(pattern, val: np.ndarray, k: int):
+    """T_k(A): dense principal submatrix of A on the functions of members(k).
+
+    Returns (A_k, offsets) with offsets[a] the first row of member a in A_k.
+    Blocks absent from the pattern are zero.
+    """
+    mem = members(pattern, k)
+    dims = [int(pattern.blk_dim[J]) for J in mem]
+    offs = np.zeros(len(mem) + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(dims)
+    n = int(offs[-1])
+    A = np.zeros((n, n))
+    for b, J in enumerate(mem):
+        for a, I in enumerate(mem):
+            t = _find_block(pattern, int(I), int(J))
+            if t < 0:
+                continue
+            A[offs[a]:offs[a + 1], offs[b]:offs[b + 1]] = _block(pattern, val, t)
+    return A, offs
+
+
+def own_columns(pattern, k: int, offs: np.ndarray) -> np.ndarray:
+    """Local column indices of molecule k's own functions inside T_k."""
+    mem = members(pattern, k)
+    a = int(np.nonzero(mem == k)[0][0])
+    return np.arange(offs[a], offs[a + 1])
+
+
+# ----------------------------------------------------------------- step 2: matrix function
+
+def theta(x: np.ndarray) -> np.ndarray:
+    """Occupation 1/2 (1 - sgn(x_in)) written for x = mu - lambda."""
+    return np.where(x > 0, 1.0, np.where(x < 0, 0.0, 0.5))
+
+
+def density(Hk: np.ndarray, Sk: np.ndarray, mu: float):
+    """Eq. 8 evaluated exactly: T_k(D) = C theta(mu - Lambda) C^T.
+
+    Returns (D_k, eigenvalues).
+    """
+    lam, C = scipy.linalg.eigh(Hk, Sk)
+    occ = theta(mu - lam)
+    Dk = (C * occ[None, :]) @ C.T
+    return Dk, lam
+
+
+def density_literal(Hk: np.ndarray, Sk: np.ndarray, mu: float) -> np.ndarray:
+    """Eq. 8 typed as printed, with an explicit inverse and scipy's signm.
+
+    For small cross-checks only (signm works on the non-symmetric S^-1 H).
+    """
+    n = Hk.shape[0]
+    Sinv = np.linalg.inv(Sk)
+    sgn = scipy.linalg.signm(Sinv @ Hk - mu * np.eye(n))
+    return 0.5 * (np.eye(n) - np.real(sgn)) @ Sinv
+
+
+def newton_schulz_sign(A: np.ndarray, scale: float | None = None, tol: float = 1e-12,
+                       maxit: int = 100):
+    """Eq. 6-7: X0 = A / b, X_{k+1} = 1/2 X_k (3 I - X_k^2), sign(A) = lim X_k.
+
+    b defaults to the infinity norm (a Gershgorin bound on the spectral radius,
+    valid for the real spectra of S^-1 H - mu I), which keeps every eigenvalue of
+    X0 inside the convergence basin (0, sqrt(3)) in modulus.  Stops when
+    ||X^2 - I||_F / sqrt(n) <= tol.  Returns (X, iterations, residual history).
+    """
+    n = A.shape[0]
+    b = np.abs(A).sum(axis=1).max() if scale is None else scale
+    X = A / b
+    eye = np.eye(n)
+    hist = []
+    for it in range(maxit + 1):
+        X2 = X @ X
+        r = np.linalg.norm(X2 - eye) / math.sqrt(n)
+        hist.append(r)
+        if r <= tol or it == maxit:
+            return X, it, hist
+        X = 0.5 * X @ (3.0 * eye - X2)
+    return X, maxit, hist
+
+
+# ----------------------------------------------------------------- step 3: write back
+
+def scatter(pattern, D_val: np.ndarray, k: int, Dk: np.ndarray, offs: np.ndarray) -> None:
+    """Write the columns of molecule k from T_k(D) into block column k of D.
+
+    Submatrix method step 3: for every stored block (I, k), rows of member I in
+    T_k(D), columns of molecule k.  Nothing outside the pattern is written.
+    """
+    mem = members(pattern, k)
+    cols = own_columns(pattern, k, offs)
+    dk = int(pattern.blk_dim[k])
+    for a, I in enumerate(mem):
+        t = _find_block(pattern, int(I), k)
+        dI = int(pattern.blk_dim[I])
+        start = int(pattern.valoff[t])
+        # column-major block (I, k): element (r, c) at start + r + c * dI
+        D_val[start:start + dI * dk] = Dk[offs[a]:offs[a + 1], cols].T.reshape(-1)
+
+
+# ----------------------------------------------------------------- Eq. 4 and the electron count
+
+def column_traces(pattern, D_val, H_val, S_val, k: int):
+    """Contributions of block column k to Tr(D H) and Tr(D S).
+
+    Tr(D H) = sum_ij D_ij H_ji = sum_ij D_ij H_ij because H is symmetric; the
+    sum over block column k collects the terms with j in molecule k.
+    """
+    eh, es = [], []
+    for t in range(int(pattern.colptr[k]), int(pattern.colptr[k + 1])):
+        I = int(pattern.rowblk[t])
+        sz = int(pattern.blk_dim[I]) * int(pattern.blk_dim[k])
+        s = int(pattern.valoff[t])
+        eh.append(math.fsum((D_val[s:s + sz] * H_val[s:s + sz]).tolist()))
+        es.append(math.fsum((D_val[s:s + sz] * S_val[s:s + sz]).tolist()))
+    return math.fsum(eh), math.fsum(es)
+
+
+def traces(pattern, D_val, H_val, S_val):
+    """(Tr(D H), Tr(D S)) summed exactly-rounded over block columns (Eq. 4)."""
+    parts = [column_traces(pattern, D_val, H_val, S_val, k) for k in range(pattern.nmol)]
+    return math.fsum(p[0] for p in parts), math.fsum(p[1] for p in parts)
+
+
+# ----------------------------------------------------------------- drivers
+
+def submatrix_result(inst, k: int, mu: float | None = None) -> dict:
+    """Everything the oracle knows about molecule k's submatrix.
+
+    D_cols is T_k(D)[:, own columns] (n_k x m_k), i.e. exactly the values the
+    write-back step stores into block column k.
+    """
+    mu = inst.mu if mu is None else mu
+    Hk, offs = gather(inst, inst.H_val, k)
+    Sk, _ = gather(inst, inst.S_val, k)
+    Dk, lam = density(Hk, Sk, mu)
+    cols = own_columns(inst, k, offs)
+    Dc = Dk[:, cols]
+    e_h = math.fsum((Dc * Hk[:, cols]).ravel().tolist())
+    e_s = math.fsum((Dc * Sk[:, cols]).ravel().tolist())
+    return {"k": k, "n": Hk.shape[0], "members": members(inst, k), "offs": offs,
+            "cols": cols, "D_cols": Dc, "tr_dh": e_h, "tr_ds": e_s,
+            "gap": float(np.min(np.abs(lam - mu))), "rho": float(np.max(np.abs(lam - mu))),
+            "n_occ": int(np.sum(lam < mu)), "eigvals": lam}
+
+
+def density_matrix(inst, mu: float | None = None, mols=None):
+    """Scattered D (values aligned with H_val / S_val) and per-molecule stats.
+
+    mols: molecules to evaluate (default all).  Block columns of molecules not
+    evaluated stay zero.
+    """
+    mu = inst.mu if mu is None else mu
+    D_val = np.zeros_like(inst.H_val)
+    stats = []
+    for k in (range(inst.nmol) if mols is None else mols):
+        Hk, offs = gather(inst, inst.H_val, k)
+        Sk, _ = gather(inst, inst.S_val, k)
+        Dk, lam = density(Hk, Sk, mu)
+        scatter(inst, D_val, int(k), Dk, offs)
+        stats.append({"k": int(k), "n": Hk.shape[0],
+                      "gap": float(np.min(np.abs(lam - mu))),
+                      "rho": float(np.max(np.abs(lam - mu)))})
+    return D_val, stats
+
+
+def energy_per_atom_error(inst, e_a: float, e_b: float) -> float:
+    """|E_a - E_b| / N_atoms (sites count as atoms)."""
+    return abs(e_a - e_b) / inst.natoms

@@ -1,0 +1,59 @@
+"""Small hand-made block-sparse instances for the oracle pins."""
+import numpy as np
+
+from workloads.water import Instance
+
+
+def instance_from_dense(H, S, blk_dim, present, mu=0.0, atoms=None, name="hand"):
+    """Block-sparse Instance from dense H, S and a molecule-pair mask.
+
+    present[I, J] says whether block (I, J) is stored (the diagonal always is).
+    Values of absent blocks are dropped.
+    """
+    blk_dim = np.asarray(blk_dim, dtype=np.int32)
+    nmol = blk_dim.size
+    blk_off = np.zeros(nmol + 1, dtype=np.int64)
+    blk_off[1:] = np.cumsum(blk_dim)
+    present = np.array(present, dtype=bool) | np.eye(nmol, dtype=bool)
+    colptr = [0]
+    rowblk, valoff, Hv, Sv = [], [], [], []
+    off = 0
+    for J in range(nmol):
+        for I in range(nmol):
+            if not present[I, J]:
+                continue
+            rowblk.append(I)
+            valoff.append(off)
+            hb = H[blk_off[I]:blk_off[I + 1], blk_off[J]:blk_off[J + 1]]
+            sb = S[blk_off[I]:blk_off[I + 1], blk_off[J]:blk_off[J + 1]]
+            Hv.append(hb.T.reshape(-1))     # column major
+            Sv.append(sb.T.reshape(-1))
+            off += hb.size
+        colptr.append(len(rowblk))
+    atoms = np.ones(nmol, dtype=np.int32) if atoms is None else np.asarray(atoms, np.int32)
+    return Instance(name=name, nmol=nmol, blk_dim=blk_dim, blk_off=blk_off,
+                    colptr=np.array(colptr, dtype=np.int64),
+                    rowblk=np.array(rowblk, dtype=np.int32),
+                    valoff=np.array(valoff, dtype=np.int64),
+                    H_val=np.concatenate(Hv), S_val=np.concatenate(Sv), mu=mu, atoms=atoms,
+                    box=0.0, r_cut=0.0, shift=0.0, centres=np.zeros((nmol, 3)), meta={})
+
+
+def permuted(inst, perm):
+    """The same system with molecules renumbered: new molecule p is old perm[p]."""
+    from workloads import to_dense
+    blk = (inst.blk_dim, inst.blk_off, inst.colptr, inst.rowblk, inst.valoff)
+    H = to_dense(blk, inst.H_val)
+    S = to_dense(blk, inst.S_val)
+    present = np.zeros((inst.nmol, inst.nmol), dtype=bool)
+    for J in range(inst.nmol):
+        present[inst.rowblk[inst.colptr[J]:inst.colptr[J + 1]], J] = True
+    fidx = np.concatenate([np.arange(inst.blk_off[p], inst.blk_off[p + 1]) for p in perm])
+    return instance_from_dense(H[np.ix_(fidx, fidx)], S[np.ix_(fidx, fidx)],
+                               inst.blk_dim[perm], present[np.ix_(perm, perm)], mu=inst.mu,
+                               atoms=inst.atoms[perm]), fidx
+
+
+def dense(inst, val):
+    from workloads import to_dense
+    return to_dense((inst.blk_dim, inst.blk_off, inst.colptr, inst.rowblk, inst.valoff), val)

@@ -1,0 +1,379 @@
+"""Pins for the FP64 oracle: closed forms, invariants and brute force.
+
+Each check below rests on something other than the oracle itself: a closed form
+worked out by hand, a textbook identity of the matrix sign function, a different
+library route (signm, LDL^T inertia, eigenvalues only), or plain dense index
+arithmetic.  The planted-mistake tests at the end confirm that plausible slips in
+the oracle (a flipped occupation, a transposed operand, a wrong index) make at
+least one of these checks fail.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import nolsm_oracle as O
+from tests.helpers import dense, instance_from_dense, permuted
+from workloads import get_config
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ helpers
+
+def inertia_below(H, S, mu):
+    """Number of generalized eigenvalues below mu from an LDL^T of H - mu S.
+
+    Sylvester's law of inertia: H - mu S is congruent to the block-diagonal
+    factor D of its LDL^T, whose negative eigenvalues count eigenvalues < mu.
+    """
+    _, d, _ = scipy.linalg.ldl(H - mu * S)
+    return int(np.sum(np.linalg.eigvalsh(d) < 0))
+
+
+def dense_density_by_columns(inst, D_val_unused=None):
+    """Brute-force assembly of D from the oracle's per-molecule results using
+    global index arithmetic on dense matrices (no block storage involved)."""
+    H = dense(inst, inst.H_val)
+    S = dense(inst, inst.S_val)
+    n = inst.nfunc
+    D = np.zeros((n, n))
+    for k in range(inst.nmol):
+        mem = inst.rowblk[inst.colptr[k]:inst.colptr[k + 1]]
+        fidx = np.concatenate([np.arange(inst.blk_off[J], inst.blk_off[J + 1]) for J in mem])
+        Hk = H[np.ix_(fidx, fidx)]
+        Sk = S[np.ix_(fidx, fidx)]
+        Dk, _ = O.density(Hk, Sk, inst.mu)
+        own = np.nonzero((fidx >= inst.blk_off[k]) & (fidx < inst.blk_off[k + 1]))[0]
+        D[np.ix_(fidx, fidx[own])] = Dk[:, own]
+    return D, H, S
+
+
+# ------------------------------------------------------------------ pin checks
+# Each raises AssertionError on failure; the planted-mistake tests reuse them.
+
+def check_scalar_closed_form():
+    for h, s, mu in [(-0.7, 1.3, 0.0), (0.4, 0.8, 0.0), (0.4, 0.8, 1.0), (-2.0, 0.5, -3.0)]:
+        inst = instance_from_dense(np.array([[h]]), np.array([[s]]), [1], [[True]], mu=mu)
+        D, _ = O.density_matrix(inst)
+        want = (1.0 / s) if h / s < mu else 0.0          # 1/2 (1 - sign(h/s - mu)) / s
+        assert abs(D[0] - want) < 1e-14, (h, s, mu, D[0], want)
+
+
+def check_diagonal_orthogonal():
+    h = np.array([-1.5, 0.3, -0.2, 2.0, -0.01, 0.7])
+    inst = instance_from_dense(np.diag(h), np.eye(6), [2, 2, 2], np.ones((3, 3)), mu=0.0)
+    D, _ = O.density_matrix(inst)
+    want = np.diag((h < 0).astype(float))
+    assert np.allclose(dense(inst, D), want, atol=1e-14, rtol=0)
+
+
+def check_golden_2x2():
+    g = json.load(open(os.path.join(GOLDEN, "gen2x2.json")))
+    H, S = np.array(g["H"]), np.array(g["S"])
+    inst = instance_from_dense(H, S, [1, 1], np.ones((2, 2)), mu=g["mu"])
+    D, _ = O.density_matrix(inst)
+    Dd = dense(inst, D)
+    assert np.allclose(Dd, np.array(g["D"]), atol=1e-14, rtol=0)
+    e, ne = O.traces(inst, D, inst.H_val, inst.S_val)
+    assert abs(e - g["tr_DH"]) < 1e-14 and abs(ne - g["tr_DS"]) < 1e-14
+
+
+def check_general_2x2_closed_form(seed):
+    rng = np.random.default_rng(seed)
+    a, c, d = rng.uniform(-2, 2, 3)
+    s = rng.uniform(-0.6, 0.6)
+    H = np.array([[a, c], [c, d]])
+    S = np.array([[1.0, s], [s, 1.0]])
+    # det(H - l S) = (1 - s^2) l^2 - (a + d - 2 c s) l + (a d - c^2)
+    A2, A1, A0 = 1 - s * s, -(a + d - 2 * c * s), a * d - c * c
+    disc = math.sqrt(A1 * A1 - 4 * A2 * A0)
+    lm, lp = (-A1 - disc) / (2 * A2), (-A1 + disc) / (2 * A2)
+    mu = 0.5 * (lm + lp)
+    v = np.array([c - lm * s, -(a - lm)])
+    if np.linalg.norm(v) < 1e-8:
+        v = np.array([d - lm, -(c - lm * s)])
+    v = v / math.sqrt(v @ S @ v)
+    want = np.outer(v, v)
+    inst = instance_from_dense(H, S, [1, 1], np.ones((2, 2)), mu=mu)
+    D, _ = O.density_matrix(inst)
+    assert np.allclose(dense(inst, D), want, atol=1e-12, rtol=0)
+
+
+def check_tiny_bruteforce(seed):
+    """Eigen route == literal Eq. 8 via signm == Newton-Schulz (Eq. 6-7) route."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(2, 9))
+    B = rng.standard_normal((n, n))
+    S = B @ B.T / n + 0.5 * np.eye(n)
+    H = rng.standard_normal((n, n))
+    H = 0.5 * (H + H.T)
+    lam = scipy.linalg.eigvalsh(H, S)
+    mu = 0.5 * (lam[n // 2 - 1] + lam[n // 2]) if n > 1 else lam[0] + 1
+    D_eig, _ = O.density(H, S, mu)
+    D_lit = O.density_literal(H, S, mu)
+    Sinv = np.linalg.inv(S)
+    X, it, hist = O.newton_schulz_sign(Sinv @ H - mu * np.eye(n), tol=1e-13, maxit=200)
+    D_ns = 0.5 * (np.eye(n) - X) @ Sinv
+    assert np.allclose(D_eig, D_lit, atol=1e-9, rtol=0)
+    assert np.allclose(D_eig, D_ns, atol=1e-8, rtol=0)
+
+
+def check_sign_invariants(seed):
+    rng = np.random.default_rng(seed)
+    n = 24
+    A = rng.standard_normal((n, n))
+    A = 0.5 * (A + A.T)
+    X, it, hist = O.newton_schulz_sign(A)
+    eye = np.eye(n)
+    assert np.abs(X @ X - eye).max() < 1e-10                         # sign(A)^2 = I
+    assert np.abs(A @ X - X @ A).max() < 1e-9                        # commutes with A
+    lam = np.linalg.eigvalsh(A)
+    assert abs(np.trace(X) - (np.sum(lam > 0) - np.sum(lam < 0))) < 1e-9
+    X3, _, _ = O.newton_schulz_sign(3.7 * A)
+    assert np.abs(X3 - X).max() < 1e-9                               # sign(cA) = sign(A)
+    assert hist[-1] <= 1e-12 and it < 100
+
+
+def check_whole_system():
+    """Each submatrix is the whole system: the assembled D is the exact D."""
+    inst = get_config("c1_whole")
+    D_val, _ = O.density_matrix(inst)
+    D = dense(inst, D_val)
+    H = dense(inst, inst.H_val)
+    S = dense(inst, inst.S_val)
+    assert np.abs(D @ S @ D - D).max() < 1e-12                       # idempotency
+    n_occ = inertia_below(H, S, inst.mu)
+    e, ne = O.traces(inst, D_val, inst.H_val, inst.S_val)
+    assert n_occ == 96 and abs(ne - n_occ) < 1e-10                   # Tr(DS) = N_occ
+    lam = scipy.linalg.eigh(H, S, eigvals_only=True)
+    assert abs(e - math.fsum(lam[lam < inst.mu].tolist())) < 1e-10   # Tr(DH) = sum occupied
+    D_lit = O.density_literal(H, S, inst.mu)
+    assert np.abs(D - D_lit).max() < 1e-9                            # literal Eq. 5
+
+
+def check_submatrices(name="c1"):
+    inst = get_config(name)
+    for k in range(0, inst.nmol, max(1, inst.nmol // 8)):
+        Hk, offs = O.gather(inst, inst.H_val, k)
+        Sk, _ = O.gather(inst, inst.S_val, k)
+        Dk, lam = O.density(Hk, Sk, inst.mu)
+        assert np.abs(Dk @ Sk @ Dk - Dk).max() < 1e-11
+        assert abs(np.trace(Dk @ Sk) - inertia_below(Hk, Sk, inst.mu)) < 1e-9
+
+
+def check_gather(name="t_small"):
+    inst = get_config(name)
+    H = dense(inst, inst.H_val)
+    for k in [0, 1, inst.nmol // 2, inst.nmol - 1]:
+        mem = inst.rowblk[inst.colptr[k]:inst.colptr[k + 1]]
+        fidx = np.concatenate([np.arange(inst.blk_off[J], inst.blk_off[J + 1]) for J in mem])
+        Hk, offs = O.gather(inst, inst.H_val, k)
+        # blocks (I, J) with both in mem but not stored are zero in T_k
+        want = H[np.ix_(fidx, fidx)]
+        assert np.array_equal(Hk, want)
+        cols = O.own_columns(inst, k, offs)
+        assert np.array_equal(fidx[cols], np.arange(inst.blk_off[k], inst.blk_off[k + 1]))
+
+
+def check_scatter_and_traces(name="c1"):
+    inst = get_config(name)
+    D_val, _ = O.density_matrix(inst)
+    Dref, H, S = dense_density_by_columns(inst)
+    assert np.array_equal(dense(inst, D_val), Dref)
+    e, ne = O.traces(inst, D_val, inst.H_val, inst.S_val)
+    assert abs(e - np.trace(Dref @ H)) < 1e-10
+    assert abs(ne - np.trace(Dref @ S)) < 1e-10
+
+
+def check_chain_truncation(t=0.45):
+    """Three molecules with one function each, block (0, 2) absent.
+
+    Columns 0 and 2 come from 2x2 submatrices, column 1 from the full 3x3; both
+    have closed forms (see the comments).
+    """
+    H = np.array([[-1.0, t, 0.0], [t, 1.0, t], [0.0, t, -1.0]])
+    present = np.array([[1, 1, 0], [1, 1, 1], [0, 1, 1]], dtype=bool)
+    inst = instance_from_dense(H, np.eye(3), [1, 1, 1], present, mu=0.0)
+    D_val, _ = O.density_matrix(inst)
+    D = dense(inst, D_val)
+    s = math.sqrt(1 + t * t)          # 2x2 [[-1, t], [t, 1]]: eigenvalues -+s
+    r = math.sqrt(1 + 2 * t * t)      # 3x3: antisymmetric -1, symmetric block -+r
+    want = np.array([[(1 + s) / (2 * s), -t / (2 * r), 0.0],
+                     [-t / (2 * s), (r - 1) / (2 * r), -t / (2 * s)],
+                     [0.0, -t / (2 * r), (1 + s) / (2 * s)]])
+    assert np.allclose(D, want, atol=1e-14, rtol=0), (D, want)
+    e, _ = O.traces(inst, D_val, inst.H_val, inst.S_val)
+    assert abs(e - float(np.sum(want * H))) < 1e-14
+
+
+def check_mu_in_gap():
+    inst = get_config("c1")
+    D0, st = O.density_matrix(inst)
+    gap = min(s["gap"] for s in st)
+    for dmu in (-0.5 * gap, 0.5 * gap):
+        D1, _ = O.density_matrix(inst, mu=inst.mu + dmu)
+        assert np.abs(D1 - D0).max() < 1e-10
+
+
+def check_permutation(name="t_small"):
+    inst = get_config(name)
+    perm = np.random.default_rng(11).permutation(inst.nmol)
+    pinst, fidx = permuted(inst, perm)
+    D_val, _ = O.density_matrix(inst)
+    P_val, _ = O.density_matrix(pinst)
+    e0, n0 = O.traces(inst, D_val, inst.H_val, inst.S_val)
+    e1, n1 = O.traces(pinst, P_val, pinst.H_val, pinst.S_val)
+    assert abs(e0 - e1) < 1e-9 and abs(n0 - n1) < 1e-9
+    assert np.abs(dense(inst, D_val)[np.ix_(fidx, fidx)] - dense(pinst, P_val)).max() < 1e-10
+
+
+# ------------------------------------------------------------------ tests
+
+def test_scalar_closed_form():
+    check_scalar_closed_form()
+
+
+def test_diagonal_orthogonal():
+    check_diagonal_orthogonal()
+
+
+def test_golden_2x2():
+    check_golden_2x2()
+
+
+@pytest.mark.parametrize("seed", range(20))
+def test_general_2x2_closed_form(seed):
+    check_general_2x2_closed_form(seed)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_tiny_bruteforce(seed):
+    check_tiny_bruteforce(seed)
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_sign_invariants(seed):
+    check_sign_invariants(seed)
+
+
+def test_whole_system():
+    check_whole_system()
+
+
+def test_submatrices_idempotent_and_inertia():
+    check_submatrices("c1")
+    check_submatrices("t_23")
+
+
+def test_gather_against_dense():
+    check_gather("t_small")
+    check_gather("t_slab")
+
+
+def test_scatter_and_traces_against_dense():
+    check_scatter_and_traces("c1")
+
+
+def test_chain_truncation():
+    check_chain_truncation()
+
+
+def test_mu_inside_gap():
+    check_mu_in_gap()
+
+
+def test_permutation_invariance():
+    check_permutation()
+
+
+def test_gaps_open_at_mu():
+    """mu = 0 sits in a gap of every submatrix (no occupation 1/2 cases)."""
+    for name in ("c1", "t_small", "t_23"):
+        inst = get_config(name)
+        _, st = O.density_matrix(inst, mols=range(0, inst.nmol, 4))
+        assert min(s["gap"] for s in st) > 1e-3
+
+
+# ------------------------------------------------------------------ planted mistakes
+
+def _fails(check, *args):
+    try:
+        check(*args)
+    except (AssertionError, np.linalg.LinAlgError, ValueError, IndexError):
+        return True
+    return False
+
+
+def test_planted_flipped_occupation(monkeypatch):
+    monkeypatch.setattr(O, "theta", lambda x: np.where(x < 0, 1.0, np.where(x > 0, 0.0, 0.5)))
+    assert _fails(check_whole_system) and _fails(check_golden_2x2)
+
+
+def test_planted_transposed_eigvecs(monkeypatch):
+    def bad(Hk, Sk, mu):
+        lam, C = scipy.linalg.eigh(Hk, Sk)
+        return (C.T * O.theta(mu - lam)[None, :]) @ C, lam
+    monkeypatch.setattr(O, "density", bad)
+    assert _fails(check_general_2x2_closed_form, 3) and _fails(check_whole_system)
+
+
+def test_planted_missing_overlap_metric(monkeypatch):
+    def bad(Hk, Sk, mu):          # ordinary eigenproblem: drops S
+        lam, C = np.linalg.eigh(Hk)
+        return (C * O.theta(mu - lam)[None, :]) @ C.T, lam
+    monkeypatch.setattr(O, "density", bad)
+    assert _fails(check_golden_2x2) and _fails(check_whole_system)
+
+
+def test_planted_transposed_block_gather(monkeypatch):
+    def bad_block(pattern, val, t):
+        I = int(pattern.rowblk[t])
+        J = int(np.searchsorted(pattern.colptr, t, side="right") - 1)
+        dI, dJ = int(pattern.blk_dim[I]), int(pattern.blk_dim[J])
+        s = int(pattern.valoff[t])
+        return val[s:s + dI * dJ].reshape(dI, dJ)          # row-major read of a col-major block
+    monkeypatch.setattr(O, "_block", bad_block)
+    assert _fails(check_gather, "t_small")
+
+
+def test_planted_wrong_own_columns(monkeypatch):
+    def bad(pattern, k, offs):
+        return np.arange(offs[0], offs[1])                  # first member, not molecule k
+    monkeypatch.setattr(O, "own_columns", bad)
+    assert _fails(check_scatter_and_traces, "c1") or _fails(check_gather, "t_small")
+
+
+def test_planted_ns_missing_half(monkeypatch):
+    orig = O.newton_schulz_sign
+
+    def bad(A, scale=None, tol=1e-12, maxit=100):
+        n = A.shape[0]
+        b = np.abs(A).sum(axis=1).max() if scale is None else scale
+        X = A / b
+        for it in range(maxit):
+            X = X @ (3.0 * np.eye(n) - X @ X)               # the 1/2 is dropped
+            if not np.all(np.isfinite(X)):
+                break
+        r = np.linalg.norm(X @ X - np.eye(n)) / math.sqrt(n)
+        return X, maxit, [r]
+    monkeypatch.setattr(O, "newton_schulz_sign", bad)
+    assert _fails(check_sign_invariants, 0)
+    monkeypatch.setattr(O, "newton_schulz_sign", orig)
+
+
+def test_planted_trace_wrong_matrix(monkeypatch):
+    def bad(pattern, D_val, H_val, S_val, k):
+        eh, es = [], []
+        for t in range(int(pattern.colptr[k]), int(pattern.colptr[k + 1])):
+            I = int(pattern.rowblk[t])
+            sz = int(pattern.blk_dim[I]) * int(pattern.blk_dim[k])
+            s = int(pattern.valoff[t])
+            eh.append(math.fsum((D_val[s:s + sz] * S_val[s:s + sz]).tolist()))   # H <-> S swapped
+            es.append(math.fsum((D_val[s:s + sz] * H_val[s:s + sz]).tolist()))
+        return math.fsum(eh), math.fsum(es)
+    monkeypatch.setattr(O, "column_traces", bad)
+    assert _fails(check_whole_system) and _fails(check_chain_truncation)
