@@ -1,0 +1,229 @@
+#!/usr/bin/env python3
+"""Benchmark of the NOLSM hot path on one MI355X.
+
+One step = the whole path for every molecule of the workload at one chemical
+potential: gather T_k(H0), T_k(S) -> FP64 set-up -> batched sign iteration ->
+panel refinement and density columns -> scatter into D -> Tr(DH), Tr(DS).
+Inputs are resident in HBM before the timed region starts.
+
+The reported value follows the paper's accounting (Sec. IV, "FLOPs in the NOLSM
+method" and "Node-Performance"): FLOPs are 2 n^3 per n x n x n product of the
+matrix iterations (two products per Newton-Schulz step), O(n^2) work is not
+counted, and the time is the wall time of the whole step.  The roofline entry is
+for the dominant kernel (the sign-iteration GEMM) on the MFMA flops it executes.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--batch B]
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "sign-iteration TFLOP/s & submatrices/s at <=1e-5 Ha/atom, mixed vs plain FP32"
+FP16_PEAK = 2516.6            # TFLOP/s, MI355X dense FP16 MFMA
+FP32_PEAK = 157.3             # TFLOP/s, MI355X FP32
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def paper_flops(stats):
+    """2 n^3 per product, two products per iteration (Eq. 6)."""
+    n3 = stats["n"].astype(np.float64) ** 3
+    return float((4.0 * n3 * (stats["iters_lo"] + stats["iters_fb"])).sum())
+
+
+def timed_steps(runner, sched, steps, L, torch):
+    for p in runner.plans:
+        L.nolsm_plan_get_timings(p, reset=True)
+        L.nolsm_plan_set_timing(p, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        runner.run(sched=sched)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    tot = {}
+    for p in runner.plans:
+        t = L.nolsm_plan_get_timings(p, reset=True).as_dict()
+        for k, v in t.items():
+            tot[k] = tot.get(k, 0) + v
+        L.nolsm_plan_set_timing(p, False)
+    return wall, tot
+
+
+def sampled_parity(inst, runner, O, ks):
+    """Oracle one submatrix at a time; compare the written columns and traces."""
+    D = runner.D.cpu().numpy()
+    st = runner.stats_host()
+    pos = {int(k): i for i, k in enumerate(runner.mols)}
+    dmax, demax = 0.0, 0.0
+    for k in ks:
+        ref = O.submatrix_result(inst, int(k))
+        got = np.zeros_like(ref["D_cols"])
+        # read block column k of the GPU's D back into T_k layout
+        for a, I in enumerate(ref["members"]):
+            t = int(inst.colptr[k]) + a
+            dI = int(inst.blk_dim[I])
+            m = int(inst.blk_dim[k])
+            blk = D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
+            got[ref["offs"][a]:ref["offs"][a + 1], :] = blk
+        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
+        de = abs(float(st["tr_dh"][pos[int(k)]]) - ref["tr_dh"]) / int(inst.atoms[k])
+        demax = max(demax, de)
+    return dmax, demax
+
+
+def cpu_baseline(inst, O, sample, flops_per_sub):
+    """Time the oracle on `sample` molecules (one submatrix each)."""
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    ks = np.linspace(0, inst.nmol - 1, sample).astype(int)
+    t0 = time.perf_counter()
+    for k in ks:
+        O.submatrix_result(inst, int(k))
+    dt = time.perf_counter() - t0
+    subs_per_s = len(ks) / dt
+    return {"value": round(subs_per_s * flops_per_sub / 1e12, 6), "unit": "TFLOP/s",
+            "cores": int(cores), "kind": "oracle",
+            "submatrices_per_s": round(subs_per_s, 4),
+            "sample": f"{len(ks)} evenly spaced submatrices of the same workload "
+                      f"({dt:.1f} s); TFLOP/s = the paper-convention sign-iteration FLOPs "
+                      f"the GPU schedule counts for those submatrices / oracle time"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--batch", type=int, default=1024)
+    ap.add_argument("--iters", type=int, default=0, help="fixed FP16 iterations (0: to tolerance)")
+    ap.add_argument("--prec", default="fp16")
+    ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of plain FP32 (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=12)
+    ap.add_argument("--parity-sample", type=int, default=4)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the method's submatrices are independent, so the "
+              "multi-GPU path is a design note, not part of this build (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2205_12182_amd import _lib as L
+    from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, plain_fp32_schedule
+    from workloads import get_config
+    if not torch.cuda.is_available():
+        print("no GPU: the benchmark needs an MI355X", file=sys.stderr)
+        sys.exit(1)
+    L.lib()
+
+    t = time.perf_counter()
+    inst = get_config(args.workload)
+    dims = inst.submatrix_dims()
+    log(f"workload {args.workload}: {inst.nmol} molecules, n_k {dims.min()}-{dims.max()}, "
+        f"built in {time.perf_counter() - t:.1f} s")
+    runner = Runner(inst, batch=args.batch)
+    log(f"{len(runner.plans)} batches, workspace {runner.workspace.numel() / 2**30:.1f} GiB")
+
+    mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec)
+    for w in range(args.warmup):
+        runner.run(sched=mixed)
+        torch.cuda.synchronize()
+        log(f"warmup {w} done")
+    wall, tm = timed_steps(runner, mixed, args.steps, L, torch)
+    log(f"mixed: {wall * 1e3:.1f} ms/step  phases {json.dumps({k: round(v, 1) for k, v in tm.items()})}")
+    st = runner.stats_host()
+    e_mixed, n_mixed = runner.energy_host()
+    flops = paper_flops(st)
+    K = len(st)
+    gemm_ms = tm["ms_gemm"] / args.steps
+    sign_ms = tm["ms_sign"] / args.steps
+    exec_flop_step = tm["gemm_flop"] / args.steps
+
+    from oracle import nolsm_oracle as O
+    ks = np.linspace(0, inst.nmol - 1, args.parity_sample).astype(int)
+    dmax, demax = sampled_parity(inst, runner, O, ks)
+    log(f"sampled parity ({len(ks)} submatrices): max|dD| {dmax:.2e}  max|dE|/atom {demax:.2e}")
+
+    plain = None
+    if args.plain_steps > 0:
+        pl = plain_fp32_schedule()
+        wall_p, tm_p = timed_steps(runner, pl, args.plain_steps, L, torch)
+        st_p = runner.stats_host()
+        e_plain, _ = runner.energy_host()
+        fl_p = paper_flops(st_p)
+        plain = {"ms_per_step": round(wall_p * 1e3, 2),
+                 "tflops": round(fl_p / wall_p / 1e12, 3),
+                 "sign_phase_tflops": round(fl_p / (tm_p["ms_sign"] / args.plain_steps * 1e-3) / 1e12, 3),
+                 "submatrices_per_s": round(K / wall_p, 2),
+                 "iters_mean": round(float(st_p["iters_lo"].mean()), 2),
+                 "gemm_roofline_frac_fp32": round(tm_p["gemm_flop"] / (tm_p["ms_gemm"] * 1e-3) / 1e12 / FP32_PEAK, 4)
+                 if tm_p["ms_gemm"] > 0 else None,
+                 "energy_per_atom_diff_vs_mixed": abs(e_plain - e_mixed) / inst.natoms}
+        log(f"plain fp32: {json.dumps(plain)}")
+
+    cpu = None
+    if args.cpu_sample > 0:
+        cpu = cpu_baseline(inst, O, args.cpu_sample, flops / K)
+        log(f"cpu baseline: {json.dumps(cpu)}")
+
+    achieved = exec_flop_step / (gemm_ms * 1e-3) / 1e12
+    n_gemm = tm["n_gemm"] / args.steps
+    out = {
+        "metric": METRIC,
+        "value": round(flops / wall / 1e12, 3),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3, 2),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.prec,
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {inst.nmol} water-like molecules, "
+                               f"{int(inst.blk_dim[0])} functions each, r_c {inst.r_cut} A, "
+                               f"submatrices n {dims.min()}-{dims.max()}",
+                   "batch": args.batch,
+                   "schedule": (f"{args.prec} Newton-Schulz " +
+                                (f"x{args.iters}" if args.iters else "to ||X^2-I||_F<=0.1 +1") +
+                                ", Gershgorin scale, FP32 panel step, FP64 set-up/traces"),
+                   "iters_mean": round(float(st["iters_lo"].mean()), 2),
+                   "fallbacks": int(st["fell_back"].sum()),
+                   "parallelism": "none (1 GPU)"},
+        "submatrices_per_s": round(K / wall, 2),
+        "sign_phase_tflops": round(flops / (sign_ms * 1e-3) / 1e12, 3),
+        "phase_ms": {k[3:]: round(v / args.steps, 2) for k, v in tm.items() if k.startswith("ms_")},
+        "energy": e_mixed, "electrons": n_mixed,
+        "error_vs_oracle": {"max_abs_dD": dmax, "max_dE_per_atom": demax,
+                            "sampled_submatrices": int(len(ks))},
+        "plain_fp32": plain,
+        "speedup_vs_plain_fp32": round(plain["ms_per_step"] / (wall * 1e3), 3) if plain else None,
+        "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_PEAK,
+                     "unit": "TFLOP/s", "frac": round(achieved / FP16_PEAK, 4), "traffic": None,
+                     "kernel": "ns_gemm_kernel (symmetric upper-tile FP16 product)",
+                     "launches_per_step": n_gemm,
+                     "avg_launch_ms": round(gemm_ms / max(n_gemm, 1), 4),
+                     "executed_flop_per_launch": exec_flop_step / max(n_gemm, 1)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,213 @@
+/*
+ * nolsm.h -- C ABI of the MI355X (gfx950) non-orthogonal local submatrix method.
+ *
+ * The library evaluates, for a batch of molecules k, the submatrix density
+ *     T_k(D) = 1/2 (I - sign(T_k(S)^-1 T_k(H0) - mu I)) T_k(S)^-1      (paper, Eq. 8)
+ * with a matmul-only Newton-Schulz sign iteration (Eq. 6-7), writes molecule k's
+ * columns back into a density matrix that has the pattern of H0 and S (Sec. II,
+ * submatrix method step 3), and reduces E = Tr(D H0) (Eq. 4) and Tr(D S).
+ *
+ * Conventions shared by every entry point
+ *  - Pointers are DEVICE pointers unless the argument says "(host)".
+ *  - The caller owns every buffer.  The library never allocates device memory:
+ *    per-batch state lives in a caller-provided workspace whose size comes from
+ *    nolsm_plan_workspace_bytes().  A plan itself is a small host object.
+ *  - Work is enqueued asynchronously on `stream`; nothing synchronises the host
+ *    except nolsm_check().  Return codes report argument and launch errors only;
+ *    data-dependent failures (a submatrix of S that is not positive definite, a
+ *    sign iteration that did not converge) are recorded per submatrix in
+ *    nolsm_stats and folded into a code by nolsm_check() after a stream sync.
+ *  - nolsm_last_error() returns a thread-local message for the last non-OK return.
+ *  - Calls on one plan must not overlap in time (they share its workspace).
+ *
+ * Matrix storage: a symmetric molecule-block-sparse matrix, compressed sparse
+ * column over block columns (both triangles stored).  H0, S and D share one
+ * pattern and one value layout.
+ */
+#ifndef NOLSM_H
+#define NOLSM_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NOLSM_OK = 0,
+  NOLSM_EINVAL = 1,      /* bad argument (sizes, null pointers, unbound plan)        */
+  NOLSM_ENOTSPD = 2,     /* a submatrix T_k(S) is not positive definite              */
+  NOLSM_ENOCONV = 3,     /* a sign iteration failed its residual test after fallback */
+  NOLSM_EHIP = 4,        /* a HIP launch or runtime call failed                      */
+  NOLSM_EWORKSPACE = 5,  /* workspace too small or misaligned                        */
+  NOLSM_ENOMEM = 6       /* host allocation failed while planning                    */
+} nolsm_status;
+
+/* Block pattern (paper, Sec. II: the combined pattern of H0 and S).
+ * blk_dim[I]   basis functions of molecule I                         [nmol]
+ * blk_off[I]   first global basis function of molecule I             [nmol+1]
+ * colptr[J]    stored blocks of block column J are colptr[J]..colptr[J+1]-1  [nmol+1]
+ * rowblk[t]    block row of stored block t, strictly ascending within a column,
+ *              and every diagonal block (J, J) is stored              [nnzb]
+ * valoff[t]    offset (elements) of block t in a value array; the block is dense
+ *              column major, blk_dim[rowblk[t]] x blk_dim[J]           [nnzb]
+ * Value arrays of H0, S and D have nval doubles and use this layout. */
+typedef struct {
+  int32_t nmol;
+  int64_t nnzb;
+  int64_t nval;
+  const int32_t *blk_dim;
+  const int64_t *blk_off;
+  const int64_t *colptr;
+  const int32_t *rowblk;
+  const int64_t *valoff;
+} nolsm_pattern;
+
+/* Arithmetic of a sign-iteration phase. */
+typedef enum {
+  NOLSM_PREC_FP32 = 0,   /* FP32 operands, FP32 MFMA accumulate               */
+  NOLSM_PREC_FP16 = 1,   /* FP16 operands, FP32 MFMA accumulate               */
+  NOLSM_PREC_BF16 = 2    /* BF16 operands, FP32 MFMA accumulate               */
+} nolsm_prec;
+
+/* Iteration schedule for nolsm_sign_batched.
+ *
+ * The argument of sign() is formed in the congruent symmetric form
+ *   M_k = L^-1 (H_k - mu S_k) L^-T,  S_k = L L^T (FP64 Cholesky),
+ * which has the spectrum of S_k^-1 H_k - mu I (Eq. 8) and gives the same density
+ * in exact arithmetic: T_k(D) = 1/2 L^-T (I - sign(M_k)) L^-1.
+ * X_0 = M_k / b_k with b_k >= rho(M_k) (Gershgorin bound unless `scale` is given).
+ *
+ * Phases run in order.  A phase with tol > 0 stops a submatrix once
+ * ||X^2 - I||_F <= tol (then runs `extra` more iterations); with
+ * tol == 0 it runs exactly `iters` iterations.  Every phase uses the step
+ *   X <- c1 X + c3 X X^2,  (c1, c3) = (3/2 a, -1/2 a^3)
+ * with a = 1 (Newton-Schulz, Eq. 6) unless `lower` gives l_k, a lower bound on
+ * min |eig(X_0)|, in which case a = sqrt(3 / (1 + l + l^2)) and l is advanced by
+ * the same map each iteration (spectrum-interval scaling of Newton-Schulz).
+ *
+ * After the phases, submatrices whose residual exceeds `fallback_tol` continue in
+ * FP32 (at most `fallback_iters` iterations, a = 1).  Finally `panel_steps`
+ * Newton-Schulz steps are applied in FP32 to the n x m panel of molecule k's own
+ * columns only, and the density columns are formed in FP64. */
+typedef struct {
+  int32_t prec;      /* nolsm_prec */
+  int32_t iters;     /* iteration count (tol == 0) or cap (tol > 0) */
+  float tol;         /* convergence threshold on ||X^2 - I||_F, 0 = fixed count */
+  int32_t extra;     /* iterations after reaching tol */
+} nolsm_phase;
+
+typedef struct {
+  int32_t nphase;           /* 1..4 */
+  nolsm_phase phase[4];
+  float fallback_tol;       /* residual above which a submatrix falls back to FP32 */
+  int32_t fallback_iters;   /* FP32 continuation cap (0 disables the fallback) */
+  int32_t panel_steps;      /* FP32 Newton-Schulz steps on the own-column panel (>= 0) */
+  const double *scale;      /* device [K] spectral bounds b_k, or NULL (Gershgorin) */
+  const double *lower;      /* device [K] lower bounds l_k in (0, 1], or NULL (a = 1) */
+} nolsm_schedule;
+
+/* Per-submatrix record written by nolsm_sign_batched / nolsm_scatter_density. */
+typedef struct {
+  int32_t n;            /* submatrix dimension n_k */
+  int32_t status;       /* 0 ok, NOLSM_ENOTSPD, NOLSM_ENOCONV */
+  int32_t iters_lo;     /* iterations run in the phases */
+  int32_t iters_fb;     /* FP32 fallback iterations */
+  float resid;          /* last measured ||X^2 - I||_F (bounds |1 - x^2| on eig(X)) */
+  int32_t fell_back;    /* 1 if the FP32 fallback ran */
+  double scale;         /* b_k used */
+  double tr_dh;         /* sum over molecule k's columns of D_ij H_ij (scatter) */
+  double tr_ds;         /* same with S */
+} nolsm_stats;
+
+/* Where a submatrix lives inside the workspace (for inspection by tests). */
+typedef struct {
+  int32_t n, npad, mol, m;        /* dimension, leading dimension, molecule, own columns */
+  int32_t own_lo, nmem, pad0, pad1;
+  int64_t off_h;                  /* bytes: FP64 npad x npad, H_k then M_k (col major) */
+  int64_t off_s;                  /* bytes: FP64 npad x npad, S_k then L^-1 (lower)    */
+  int64_t off_lo;                 /* bytes: three npad x npad low-precision buffers     */
+  int64_t off_dcol;               /* bytes: FP64 npad x m density columns               */
+} nolsm_sub_info;
+
+typedef struct nolsm_plan nolsm_plan;
+
+/* Plan a batch: the submatrices of molecules mols[0..K-1] of the pattern.
+ * pattern_host must hold HOST copies of the pattern arrays.  The plan records
+ * sizes, member lists and the GEMM tile work lists (host memory). */
+nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
+                               int32_t K, nolsm_plan **plan /*host out*/);
+void nolsm_plan_destroy(nolsm_plan *plan);
+
+/* Device workspace bytes the plan needs (256-byte aligned base required). */
+size_t nolsm_plan_workspace_bytes(const nolsm_plan *plan);
+
+/* Attach a device workspace and upload the plan's tables into it (async on stream). */
+nolsm_status nolsm_plan_bind(nolsm_plan *plan, void *workspace, size_t bytes, hipStream_t stream);
+
+/* Layout of submatrix i (0 <= i < K) inside the bound workspace. */
+nolsm_status nolsm_plan_query(const nolsm_plan *plan, int32_t i, nolsm_sub_info *info /*host*/);
+
+/* Step 1 of the submatrix method for H0 and S (Sec. II; Eq. 8 builds both from the
+ * combined pattern): for every planned molecule k, gather the dense principal
+ * submatrices T_k(H0), T_k(S) (FP64, column major) on the functions of the
+ * molecules stored in block column k, in ascending molecule order.  Blocks absent
+ * from the pattern are zero.  pattern_dev holds DEVICE copies of the arrays. */
+nolsm_status nolsm_build_submatrices(nolsm_plan *plan, const nolsm_pattern *pattern_dev,
+                                     const double *H_val, const double *S_val,
+                                     hipStream_t stream);
+
+/* Step 2 (Eq. 8 via Eq. 6-7): FP64 Cholesky and transform, scaling, the batched
+ * sign iteration under `sched` (NULL = plain FP32 Newton-Schulz to convergence),
+ * the FP32 fallback and the own-column panel refinement, and the FP64 density
+ * columns T_k(D)[:, own columns].  stats: device [K] (may be NULL). */
+nolsm_status nolsm_sign_batched(nolsm_plan *plan, double mu, const nolsm_schedule *sched /*host*/,
+                                nolsm_stats *stats, hipStream_t stream);
+
+/* Step 3 (Sec. II): write molecule k's density columns into block column k of D
+ * (same pattern and layout as H0, S), and record each column's contribution to
+ * Tr(D H0) and Tr(D S) in stats[i].tr_dh / tr_ds.  Only block columns of planned
+ * molecules are written. */
+nolsm_status nolsm_scatter_density(nolsm_plan *plan, const nolsm_pattern *pattern_dev,
+                                   double *D_val, const double *H_val, const double *S_val,
+                                   nolsm_stats *stats, hipStream_t stream);
+
+/* Eq. 4 and the electron count: out2[0] = Tr(D H0) = sum_ij D_ij H0_ij (H0 is
+ * symmetric), out2[1] = Tr(D S).  col_traces: device [2*nmol] scratch that
+ * receives the per-block-column sums; the final sum runs over block columns in
+ * ascending order, so the result is bitwise reproducible. */
+nolsm_status nolsm_energy(const nolsm_pattern *pattern_dev, int32_t nmol, const double *D_val,
+                          const double *H_val, const double *S_val, double *col_traces,
+                          double *out2, hipStream_t stream);
+
+/* Measurement (not needed for results).  With timing enabled, the plan records a
+ * pair of HIP events on `stream` around every launch group below, and
+ * nolsm_plan_get_timings() (which synchronises on those events) returns the
+ * accumulated milliseconds since the last reset.  The sign-iteration GEMM launches
+ * are timed one by one, so ms_gemm / n_gemm is their average duration. */
+typedef struct {
+  double ms_gather;      /* nolsm_build_submatrices                                  */
+  double ms_setup;       /* FP64 Cholesky, inverse and transform                     */
+  double ms_sign;        /* scaling and every sign-iteration launch (incl. GEMMs)    */
+  double ms_gemm;        /* sign-iteration GEMM launches only                        */
+  double ms_panel;       /* panel refinement and density columns                     */
+  double ms_scatter;     /* nolsm_scatter_density                                    */
+  int64_t n_gemm;        /* GEMM launches timed                                      */
+  double gemm_flop;      /* executed MFMA flops of those launches (all tiles of the plan) */
+} nolsm_timings;
+
+nolsm_status nolsm_plan_set_timing(nolsm_plan *plan, int enable);
+nolsm_status nolsm_plan_get_timings(nolsm_plan *plan, nolsm_timings *out /*host*/, int reset);
+
+/* Synchronise `stream`, read the plan's device status words, and return
+ * NOLSM_ENOTSPD / NOLSM_ENOCONV if any submatrix failed (else NOLSM_OK). */
+nolsm_status nolsm_check(nolsm_plan *plan, hipStream_t stream);
+
+const char *nolsm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NOLSM_H */

@@ -1,0 +1,245 @@
+"""ctypes binding of libnolsm.so (argument marshalling only).
+
+Every entry point of include/nolsm.h has a function of the same name here.  Device
+memory and streams come from PyTorch (tensors' data_ptr() and the current HIP
+stream); all arithmetic happens in the library's kernels.  If the shared library
+is missing this module raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnolsm.so")
+
+# status codes (nolsm_status)
+OK, EINVAL, ENOTSPD, ENOCONV, EHIP, EWORKSPACE, ENOMEM = range(7)
+PREC_FP32, PREC_FP16, PREC_BF16 = 0, 1, 2
+PREC_NAMES = {"fp32": PREC_FP32, "fp16": PREC_FP16, "bf16": PREC_BF16}
+
+
+class NolsmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nolsm error {code}: {msg}")
+        self.code = code
+
+
+class Pattern(ctypes.Structure):
+    _fields_ = [("nmol", ctypes.c_int32), ("nnzb", ctypes.c_int64), ("nval", ctypes.c_int64),
+                ("blk_dim", ctypes.c_void_p), ("blk_off", ctypes.c_void_p),
+                ("colptr", ctypes.c_void_p), ("rowblk", ctypes.c_void_p),
+                ("valoff", ctypes.c_void_p)]
+
+
+class Phase(ctypes.Structure):
+    _fields_ = [("prec", ctypes.c_int32), ("iters", ctypes.c_int32), ("tol", ctypes.c_float),
+                ("extra", ctypes.c_int32)]
+
+
+class Schedule(ctypes.Structure):
+    _fields_ = [("nphase", ctypes.c_int32), ("phase", Phase * 4),
+                ("fallback_tol", ctypes.c_float), ("fallback_iters", ctypes.c_int32),
+                ("panel_steps", ctypes.c_int32), ("scale", ctypes.c_void_p),
+                ("lower", ctypes.c_void_p)]
+
+
+class SubInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("npad", ctypes.c_int32), ("mol", ctypes.c_int32),
+                ("m", ctypes.c_int32), ("own_lo", ctypes.c_int32), ("nmem", ctypes.c_int32),
+                ("pad0", ctypes.c_int32), ("pad1", ctypes.c_int32), ("off_h", ctypes.c_int64),
+                ("off_s", ctypes.c_int64), ("off_lo", ctypes.c_int64),
+                ("off_dcol", ctypes.c_int64)]
+
+
+class Timings(ctypes.Structure):
+    _fields_ = [("ms_gather", ctypes.c_double), ("ms_setup", ctypes.c_double),
+                ("ms_sign", ctypes.c_double), ("ms_gemm", ctypes.c_double),
+                ("ms_panel", ctypes.c_double), ("ms_scatter", ctypes.c_double),
+                ("n_gemm", ctypes.c_int64), ("gemm_flop", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+# nolsm_stats as a numpy record (48 bytes)
+STATS_DTYPE = np.dtype([("n", "<i4"), ("status", "<i4"), ("iters_lo", "<i4"),
+                        ("iters_fb", "<i4"), ("resid", "<f4"), ("fell_back", "<i4"),
+                        ("scale", "<f8"), ("tr_dh", "<f8"), ("tr_ds", "<f8")])
+assert STATS_DTYPE.itemsize == 48
+
+_lib = None
+
+
+def lib():
+    """Load libnolsm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2205_12182_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_size_t)
+    P = ctypes.POINTER
+    sigs = {
+        "nolsm_plan_create": (i32, [P(Pattern), vp, i32, P(vp)]),
+        "nolsm_plan_destroy": (None, [vp]),
+        "nolsm_plan_workspace_bytes": (sz, [vp]),
+        "nolsm_plan_bind": (i32, [vp, vp, sz, vp]),
+        "nolsm_plan_query": (i32, [vp, i32, P(SubInfo)]),
+        "nolsm_build_submatrices": (i32, [vp, P(Pattern), vp, vp, vp]),
+        "nolsm_sign_batched": (i32, [vp, dbl, P(Schedule), vp, vp]),
+        "nolsm_scatter_density": (i32, [vp, P(Pattern), vp, vp, vp, vp, vp]),
+        "nolsm_energy": (i32, [P(Pattern), i32, vp, vp, vp, vp, vp, vp]),
+        "nolsm_check": (i32, [vp, vp]),
+        "nolsm_plan_set_timing": (i32, [vp, i32]),
+        "nolsm_plan_get_timings": (i32, [vp, P(Timings), i32]),
+        "nolsm_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+EXPORTED = ("nolsm_plan_create", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
+            "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
+            "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_check",
+            "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings")
+
+
+def _ok(code):
+    if code != OK:
+        raise NolsmError(code, lib().nolsm_last_error().decode())
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+# ----------------------------------------------------------------------------- patterns
+
+class HostPattern:
+    """nolsm_pattern over host (numpy) copies of an instance's pattern arrays."""
+
+    def __init__(self, inst):
+        self.arrays = [np.ascontiguousarray(inst.blk_dim, dtype=np.int32),
+                       np.ascontiguousarray(inst.blk_off, dtype=np.int64),
+                       np.ascontiguousarray(inst.colptr, dtype=np.int64),
+                       np.ascontiguousarray(inst.rowblk, dtype=np.int32),
+                       np.ascontiguousarray(inst.valoff, dtype=np.int64)]
+        a = self.arrays
+        self.struct = Pattern(inst.nmol, inst.nnzb, inst.nval, *[x.ctypes.data for x in a])
+
+
+class DevicePattern:
+    """nolsm_pattern over device (torch) copies of an instance's pattern arrays."""
+
+    def __init__(self, inst, device="cuda"):
+        import torch
+        self.tensors = [torch.from_numpy(np.ascontiguousarray(x, dtype=dt)).to(device)
+                        for x, dt in ((inst.blk_dim, np.int32), (inst.blk_off, np.int64),
+                                      (inst.colptr, np.int64), (inst.rowblk, np.int32),
+                                      (inst.valoff, np.int64))]
+        self.nmol = inst.nmol
+        self.struct = Pattern(inst.nmol, inst.nnzb, inst.nval,
+                              *[t.data_ptr() for t in self.tensors])
+
+
+def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=None,
+             lower=None):
+    """nolsm_schedule from [(prec, iters, tol, extra), ...]; scale/lower: device tensors."""
+    s = Schedule()
+    s.nphase = len(phases)
+    for i, (prec, iters, tol, extra) in enumerate(phases):
+        p = PREC_NAMES[prec] if isinstance(prec, str) else prec
+        s.phase[i] = Phase(p, iters, tol, extra)
+    s.fallback_tol = fallback_tol
+    s.fallback_iters = fallback_iters
+    s.panel_steps = panel_steps
+    s.scale = None if scale is None else scale.data_ptr()
+    s.lower = None if lower is None else lower.data_ptr()
+    s._keep = (scale, lower)
+    return s
+
+
+# ----------------------------------------------------------------------------- entry points
+
+def nolsm_plan_create(host_pattern: HostPattern, mols) -> ctypes.c_void_p:
+    mols = np.ascontiguousarray(mols, dtype=np.int32)
+    out = ctypes.c_void_p()
+    _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
+                                int(mols.size), ctypes.byref(out)))
+    return out
+
+
+def nolsm_plan_destroy(plan):
+    lib().nolsm_plan_destroy(plan)
+
+
+def nolsm_plan_workspace_bytes(plan) -> int:
+    return int(lib().nolsm_plan_workspace_bytes(plan))
+
+
+def nolsm_plan_bind(plan, workspace, stream=None):
+    _ok(lib().nolsm_plan_bind(plan, _ptr(workspace), workspace.numel() * workspace.element_size(),
+                              _stream(stream)))
+
+
+def nolsm_plan_query(plan, i) -> SubInfo:
+    info = SubInfo()
+    _ok(lib().nolsm_plan_query(plan, int(i), ctypes.byref(info)))
+    return info
+
+
+def nolsm_build_submatrices(plan, dev_pattern: DevicePattern, H_val, S_val, stream=None):
+    _ok(lib().nolsm_build_submatrices(plan, ctypes.byref(dev_pattern.struct), _ptr(H_val),
+                                      _ptr(S_val), _stream(stream)))
+
+
+def nolsm_sign_batched(plan, mu, sched=None, stats=None, stream=None):
+    _ok(lib().nolsm_sign_batched(plan, float(mu), None if sched is None else ctypes.byref(sched),
+                                 _ptr(stats), _stream(stream)))
+
+
+def nolsm_scatter_density(plan, dev_pattern: DevicePattern, D_val, H_val, S_val, stats=None,
+                          stream=None):
+    _ok(lib().nolsm_scatter_density(plan, ctypes.byref(dev_pattern.struct), _ptr(D_val),
+                                    _ptr(H_val), _ptr(S_val), _ptr(stats), _stream(stream)))
+
+
+def nolsm_energy(dev_pattern: DevicePattern, D_val, H_val, S_val, col_traces, out2, stream=None):
+    _ok(lib().nolsm_energy(ctypes.byref(dev_pattern.struct), dev_pattern.nmol, _ptr(D_val),
+                           _ptr(H_val), _ptr(S_val), _ptr(col_traces), _ptr(out2),
+                           _stream(stream)))
+
+
+def nolsm_check(plan, stream=None) -> int:
+    code = lib().nolsm_check(plan, _stream(stream))
+    return int(code)
+
+
+def nolsm_plan_set_timing(plan, enable=True):
+    _ok(lib().nolsm_plan_set_timing(plan, 1 if enable else 0))
+
+
+def nolsm_plan_get_timings(plan, reset=True) -> Timings:
+    t = Timings()
+    _ok(lib().nolsm_plan_get_timings(plan, ctypes.byref(t), 1 if reset else 0))
+    return t
+
+
+def nolsm_last_error() -> str:
+    return lib().nolsm_last_error().decode()

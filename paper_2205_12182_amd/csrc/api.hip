@@ -1,0 +1,358 @@
+// C ABI of the NOLSM library: planning, workspace layout and the entry points.
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.h"
+
+namespace nolsm {
+void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
+                   const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
+                   const double *S_val, char *ws, hipStream_t stream);
+void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws, hipStream_t s);
+void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const Tile *tiles,
+                 int ntiles, char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
+                 double flop, hipStream_t s);
+void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
+                            char *ws, int panel_steps, hipStream_t s);
+void launch_scatter(const SubDesc *desc, const SubState *st, int K, const int32_t *mem_mol,
+                    const int32_t *mem_loc, const nolsm_pattern *pat, double *D_val,
+                    const double *H_val, const double *S_val, const char *ws,
+                    nolsm_stats *stats, hipStream_t s);
+void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, const double *H_val,
+                   const double *S_val, double *col_traces, double *out2, hipStream_t s);
+void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
+                  hipStream_t s);
+void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
+}  // namespace nolsm
+
+using namespace nolsm;
+
+struct nolsm_plan {
+  int32_t K = 0;
+  int32_t nmol = 0;
+  int32_t maxmem = 0;
+  int32_t max_npad = 0;
+  std::vector<SubDesc> desc;
+  std::vector<int32_t> mem_mol, mem_loc;
+  std::vector<Tile> tiles;
+  size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
+  size_t bytes = 0;
+  char *ws = nullptr;
+  bool bound = false;
+  double gemm_flop = 0.0;       // executed MFMA flops of one sign GEMM launch (all tiles)
+  EventLog log;
+};
+
+static thread_local std::string g_err;
+
+static nolsm_status fail(nolsm_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+static nolsm_status fail(nolsm_status code, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static nolsm_status hip_check(const char *where) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(NOLSM_EHIP, "%s: %s", where, hipGetErrorString(e));
+  return NOLSM_OK;
+}
+
+static inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+extern "C" {
+
+const char *nolsm_last_error(void) { return g_err.c_str(); }
+
+nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, int32_t K,
+                               nolsm_plan **out) {
+  if (!pat || !out || (K > 0 && !mols) || K < 0)
+    return fail(NOLSM_EINVAL, "nolsm_plan_create: null argument or K < 0");
+  if (!pat->blk_dim || !pat->blk_off || !pat->colptr || !pat->rowblk || !pat->valoff)
+    return fail(NOLSM_EINVAL, "nolsm_plan_create: pattern arrays must be set (host copies)");
+  nolsm_plan *p = new (std::nothrow) nolsm_plan;
+  if (!p) return fail(NOLSM_ENOMEM, "nolsm_plan_create: out of host memory");
+  p->K = K;
+  p->nmol = pat->nmol;
+  p->desc.resize(K);
+  size_t off = 0;
+  off += 0;  // offsets of tables are fixed after the member lists are known
+  for (int i = 0; i < K; ++i) {
+    const int k = mols[i];
+    if (k < 0 || k >= pat->nmol) {
+      delete p;
+      return fail(NOLSM_EINVAL, "nolsm_plan_create: mols[%d] = %d out of range", i, k);
+    }
+    const int64_t c0 = pat->colptr[k], c1 = pat->colptr[k + 1];
+    SubDesc &d = p->desc[i];
+    std::memset(&d, 0, sizeof d);
+    d.mol = k;
+    d.mem_off = (int32_t)p->mem_mol.size();
+    d.nmem = (int32_t)(c1 - c0);
+    int loc = 0, own = -1;
+    for (int64_t t = c0; t < c1; ++t) {
+      const int J = pat->rowblk[t];
+      if (t > c0 && J <= pat->rowblk[t - 1]) {
+        delete p;
+        return fail(NOLSM_EINVAL, "nolsm_plan_create: rows of block column %d not ascending", k);
+      }
+      if (J == k) own = loc;
+      p->mem_mol.push_back(J);
+      p->mem_loc.push_back(loc);
+      loc += pat->blk_dim[J];
+    }
+    if (own < 0) {
+      delete p;
+      return fail(NOLSM_EINVAL, "nolsm_plan_create: diagonal block (%d, %d) not stored", k, k);
+    }
+    d.n = loc;
+    d.npad = (loc + PAD - 1) / PAD * PAD;
+    d.own_lo = own;
+    d.m = pat->blk_dim[k];
+    if (d.m > MAXM || d.nmem > 1024 || d.npad > 8192) {
+      delete p;
+      return fail(NOLSM_EINVAL,
+                  "nolsm_plan_create: molecule %d exceeds limits (m=%d<=%d, members=%d<=1024, "
+                  "n=%d<=8192)", k, d.m, MAXM, d.nmem, d.n);
+    }
+    p->maxmem = std::max(p->maxmem, d.nmem);
+    p->max_npad = std::max(p->max_npad, d.npad);
+  }
+  // tiles of the symmetric sign-iteration products: upper triangle, ST x ST
+  for (int i = 0; i < K; ++i) {
+    const int nt = (p->desc[i].npad + ST - 1) / ST;
+    for (int ti = 0; ti < nt; ++ti)
+      for (int tj = ti; tj < nt; ++tj) p->tiles.push_back(Tile{i, ti, tj, 0});
+  }
+  for (const Tile &t : p->tiles) p->gemm_flop += 2.0 * ST * ST * (double)p->desc[t.sub].npad;
+  // workspace layout
+  off = 0;
+  p->off_desc = off;
+  off = align256(off + sizeof(SubDesc) * (size_t)K);
+  p->off_mem_mol = off;
+  off = align256(off + sizeof(int32_t) * p->mem_mol.size());
+  p->off_mem_loc = off;
+  off = align256(off + sizeof(int32_t) * p->mem_loc.size());
+  p->off_tiles = off;
+  off = align256(off + sizeof(Tile) * p->tiles.size());
+  p->off_state = off;
+  off = align256(off + sizeof(SubState) * (size_t)K);
+  for (int i = 0; i < K; ++i) {
+    SubDesc &d = p->desc[i];
+    const size_t np = (size_t)d.npad;
+    d.off_h = (int64_t)off;
+    off = align256(off + 8 * np * np);
+    d.off_s = (int64_t)off;
+    off = align256(off + 8 * np * np);
+    d.off_lo = (int64_t)off;
+    off = align256(off + 3 * 4 * np * np);
+    d.off_diag = (int64_t)off;
+    off = align256(off + 8 * 2 * np * NB);
+    d.off_panel = (int64_t)off;
+    off = align256(off + 4 * (size_t)NPANEL * np * d.m);
+    d.off_dcol = (int64_t)off;
+    off = align256(off + 8 * np * d.m);
+  }
+  p->bytes = off;
+  *out = p;
+  return NOLSM_OK;
+}
+
+void nolsm_plan_destroy(nolsm_plan *p) { delete p; }
+
+size_t nolsm_plan_workspace_bytes(const nolsm_plan *p) { return p ? p->bytes : 0; }
+
+nolsm_status nolsm_plan_bind(nolsm_plan *p, void *workspace, size_t bytes, hipStream_t s) {
+  if (!p || !workspace) return fail(NOLSM_EINVAL, "nolsm_plan_bind: null argument");
+  if (bytes < p->bytes)
+    return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: workspace %zu bytes < %zu needed", bytes,
+                p->bytes);
+  if (reinterpret_cast<uintptr_t>(workspace) & 255)
+    return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: workspace must be 256-byte aligned");
+  p->ws = static_cast<char *>(workspace);
+  hipError_t e = hipSuccess;
+  if (p->K > 0) {
+    e = hipMemcpyAsync(p->ws + p->off_desc, p->desc.data(), sizeof(SubDesc) * p->K,
+                       hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + p->off_mem_mol, p->mem_mol.data(),
+                         sizeof(int32_t) * p->mem_mol.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + p->off_mem_loc, p->mem_loc.data(),
+                         sizeof(int32_t) * p->mem_loc.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(p->ws + p->off_tiles, p->tiles.data(), sizeof(Tile) * p->tiles.size(),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->off_state, 0, sizeof(SubState) * p->K, s);
+    // the host copies must stay alive until the copies complete
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_plan_bind: %s", hipGetErrorString(e));
+  p->bound = true;
+  return NOLSM_OK;
+}
+
+nolsm_status nolsm_plan_query(const nolsm_plan *p, int32_t i, nolsm_sub_info *info) {
+  if (!p || !info || i < 0 || i >= p->K) return fail(NOLSM_EINVAL, "nolsm_plan_query: bad index");
+  const SubDesc &d = p->desc[i];
+  info->n = d.n;
+  info->npad = d.npad;
+  info->mol = d.mol;
+  info->m = d.m;
+  info->own_lo = d.own_lo;
+  info->nmem = d.nmem;
+  info->pad0 = info->pad1 = 0;
+  info->off_h = d.off_h;
+  info->off_s = d.off_s;
+  info->off_lo = d.off_lo;
+  info->off_dcol = d.off_dcol;
+  return NOLSM_OK;
+}
+
+#define PLAN_PTRS                                                                          \
+  const SubDesc *desc = reinterpret_cast<const SubDesc *>(p->ws + p->off_desc);            \
+  const int32_t *mem_mol = reinterpret_cast<const int32_t *>(p->ws + p->off_mem_mol);      \
+  const int32_t *mem_loc = reinterpret_cast<const int32_t *>(p->ws + p->off_mem_loc);      \
+  const Tile *tiles = reinterpret_cast<const Tile *>(p->ws + p->off_tiles);                \
+  SubState *st = reinterpret_cast<SubState *>(p->ws + p->off_state);                       \
+  (void)desc; (void)mem_mol; (void)mem_loc; (void)tiles; (void)st;
+
+nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, const double *H_val,
+                                     const double *S_val, hipStream_t s) {
+  if (!p || !pat || !H_val || !S_val) return fail(NOLSM_EINVAL, "nolsm_build_submatrices: null argument");
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_build_submatrices: plan not bound");
+  if (pat->nmol != p->nmol) return fail(NOLSM_EINVAL, "nolsm_build_submatrices: pattern mismatch");
+  if (p->K == 0) return NOLSM_OK;
+  PLAN_PTRS
+  const int ev = p->log.begin(T_GATHER, s);
+  launch_gather(desc, p->K, p->maxmem, mem_mol, mem_loc, pat, H_val, S_val, p->ws, s);
+  p->log.end(ev, s);
+  return hip_check("nolsm_build_submatrices");
+}
+
+nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *sched,
+                                nolsm_stats *stats, hipStream_t s) {
+  if (!p) return fail(NOLSM_EINVAL, "nolsm_sign_batched: null plan");
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_sign_batched: plan not bound");
+  if (!std::isfinite(mu)) return fail(NOLSM_EINVAL, "nolsm_sign_batched: mu not finite");
+  nolsm_schedule sch;
+  if (sched) {
+    sch = *sched;
+    if (sch.nphase < 1 || sch.nphase > 4) return fail(NOLSM_EINVAL, "nolsm_sign_batched: nphase");
+    for (int q = 0; q < sch.nphase; ++q) {
+      const nolsm_phase &ph = sch.phase[q];
+      if (ph.prec < 0 || ph.prec > 2 || ph.iters < 0 || ph.iters > 1000 || ph.extra < 0 ||
+          !(ph.tol >= 0.0f))
+        return fail(NOLSM_EINVAL, "nolsm_sign_batched: bad phase %d", q);
+    }
+    if (sch.panel_steps < 0 || sch.panel_steps > 2)
+      return fail(NOLSM_EINVAL, "nolsm_sign_batched: panel_steps must be 0..2");
+    if (sch.fallback_iters < 0 || sch.fallback_iters > 1000)
+      return fail(NOLSM_EINVAL, "nolsm_sign_batched: fallback_iters");
+  } else {
+    std::memset(&sch, 0, sizeof sch);
+    sch.nphase = 1;
+    sch.phase[0].prec = NOLSM_PREC_FP32;
+    sch.phase[0].iters = 100;
+    sch.phase[0].tol = 1.0e-3f;
+    sch.phase[0].extra = 2;
+    sch.panel_steps = 0;
+    sch.fallback_iters = 0;
+  }
+  if (p->K == 0) return NOLSM_OK;
+  PLAN_PTRS
+  int ev = p->log.begin(T_SETUP, s);
+  launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
+  p->log.end(ev, s);
+  ev = p->log.begin(T_SIGN, s);
+  launch_sign(desc, st, p->K, p->max_npad, tiles, (int)p->tiles.size(), p->ws, mu, sch, &p->log,
+              p->gemm_flop, s);
+  const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
+  launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
+  p->log.end(ev, s);
+  ev = p->log.begin(T_PANEL, s);
+  launch_density_columns(desc, st, p->K, p->max_npad, p->ws, sch.panel_steps, s);
+  p->log.end(ev, s);
+  if (stats) launch_stats(desc, st, p->K, stats, s);
+  return hip_check("nolsm_sign_batched");
+}
+
+nolsm_status nolsm_scatter_density(nolsm_plan *p, const nolsm_pattern *pat, double *D_val,
+                                   const double *H_val, const double *S_val, nolsm_stats *stats,
+                                   hipStream_t s) {
+  if (!p || !pat || !D_val || !H_val || !S_val)
+    return fail(NOLSM_EINVAL, "nolsm_scatter_density: null argument");
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_scatter_density: plan not bound");
+  if (pat->nmol != p->nmol) return fail(NOLSM_EINVAL, "nolsm_scatter_density: pattern mismatch");
+  if (p->K == 0) return NOLSM_OK;
+  PLAN_PTRS
+  const int ev = p->log.begin(T_SCATTER, s);
+  launch_scatter(desc, st, p->K, mem_mol, mem_loc, pat, D_val, H_val, S_val, p->ws, stats, s);
+  p->log.end(ev, s);
+  return hip_check("nolsm_scatter_density");
+}
+
+nolsm_status nolsm_energy(const nolsm_pattern *pat, int32_t nmol, const double *D_val,
+                          const double *H_val, const double *S_val, double *col_traces,
+                          double *out2, hipStream_t s) {
+  if (!pat || !D_val || !H_val || !S_val || !col_traces || !out2 || nmol < 0 || nmol != pat->nmol)
+    return fail(NOLSM_EINVAL, "nolsm_energy: bad argument");
+  launch_energy(pat, nmol, D_val, H_val, S_val, col_traces, out2, s);
+  return hip_check("nolsm_energy");
+}
+
+nolsm_status nolsm_plan_set_timing(nolsm_plan *p, int enable) {
+  if (!p) return fail(NOLSM_EINVAL, "nolsm_plan_set_timing: null plan");
+  p->log.on = enable != 0;
+  return NOLSM_OK;
+}
+
+nolsm_status nolsm_plan_get_timings(nolsm_plan *p, nolsm_timings *out, int reset) {
+  if (!p || !out) return fail(NOLSM_EINVAL, "nolsm_plan_get_timings: null argument");
+  p->log.collect();
+  out->ms_gather = p->log.ms[T_GATHER];
+  out->ms_setup = p->log.ms[T_SETUP];
+  out->ms_sign = p->log.ms[T_SIGN];
+  out->ms_gemm = p->log.ms[T_GEMM];
+  out->ms_panel = p->log.ms[T_PANEL];
+  out->ms_scatter = p->log.ms[T_SCATTER];
+  out->n_gemm = p->log.n_gemm;
+  out->gemm_flop = p->log.gemm_flop;
+  if (reset) {
+    for (double &m : p->log.ms) m = 0.0;
+    p->log.n_gemm = 0;
+    p->log.gemm_flop = 0.0;
+  }
+  return hip_check("nolsm_plan_get_timings");
+}
+
+nolsm_status nolsm_check(nolsm_plan *p, hipStream_t s) {
+  if (!p || !p->bound) return fail(NOLSM_EINVAL, "nolsm_check: plan not bound");
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_check: %s", hipGetErrorString(e));
+  std::vector<SubState> host(p->K);
+  if (p->K > 0) {
+    e = hipMemcpy(host.data(), p->ws + p->off_state, sizeof(SubState) * p->K, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_check: %s", hipGetErrorString(e));
+  }
+  int nspd = 0, nconv = 0, first = -1;
+  for (int i = 0; i < p->K; ++i) {
+    if (host[i].status == NOLSM_ENOTSPD) { ++nspd; if (first < 0) first = i; }
+    if (host[i].status == NOLSM_ENOCONV) { ++nconv; if (first < 0) first = i; }
+  }
+  if (nspd) return fail(NOLSM_ENOTSPD, "%d submatrices not positive definite (first: batch index %d)", nspd, first);
+  if (nconv) return fail(NOLSM_ENOCONV, "%d submatrices did not converge (first: batch index %d)", nconv, first);
+  return NOLSM_OK;
+}
+
+}  // extern "C"

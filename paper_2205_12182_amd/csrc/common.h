@@ -1,0 +1,158 @@
+// Internal definitions shared by the NOLSM HIP kernels (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "nolsm.h"
+
+namespace nolsm {
+
+// Submatrix dimensions are padded to a multiple of PAD.  The padding of T_k(S)
+// is the identity and the padding of T_k(H0) is zero, so the padded matrices
+// factor as diag(L, I) and every padded iterate stays zero outside the n x n
+// block.
+constexpr int PAD = 64;
+constexpr int NB = 64;             // FP64 Cholesky / inverse block size
+constexpr int ST = 128;            // sign-iteration output tile (ST x ST)
+constexpr int RESID_SHIFT = 40;    // fixed-point scale of the residual accumulator
+constexpr float RESID_CLAMP = 1.0e4f;
+constexpr int NPANEL = 8;         // n x m FP32 panel slots per submatrix
+constexpr int MAXM = 32;          // own columns per molecule handled by the panel kernels
+
+enum Prec : int32_t { P_FP32 = 0, P_FP16 = 1, P_BF16 = 2 };
+
+// Per-submatrix description (device, read-only after bind).
+struct SubDesc {
+  int32_t n, npad, mol, m;          // dimension, leading dimension, molecule, own columns
+  int32_t own_lo, nmem, mem_off, pad0;
+  int64_t off_h;                    // bytes from workspace base: FP64 npad^2 (H_k -> M_k)
+  int64_t off_s;                    // FP64 npad^2 (S_k -> L -> L^-1)
+  int64_t off_lo;                   // 3 x (4 npad^2) bytes: sign-iteration buffers / FP64 scratch
+  int64_t off_diag;                 // FP64 2 x npad x NB: inverted diagonal blocks + panel temp
+  int64_t off_panel;                // FP32 NPANEL x npad x m panels
+  int64_t off_dcol;                 // FP64 npad x m density columns
+};
+
+// Per-submatrix mutable state (device).
+struct SubState {
+  double scale;                     // b_k
+  double lower;                     // current lower bound l on |eig(X)| (scaled iteration)
+  unsigned long long racc;          // fixed-point sum of (X^2 - I)^2
+  unsigned long long scale_bits;    // Gershgorin max as ordered bits (positive doubles)
+  float resid;                      // last ||X^2 - I||_F
+  int32_t status;                   // 0, NOLSM_ENOTSPD, NOLSM_ENOCONV
+  int32_t active;                   // iterating in the current phase
+  int32_t cur;                      // buffer (0..2) holding the current X
+  int32_t prec;                     // precision of the buffers (Prec)
+  int32_t iters_lo, iters_fb, fell_back;
+  int32_t extra_left;               // iterations still to run after reaching tol (-1: not reached)
+  int32_t converged;
+  float c1, c3;                     // coefficients of the next update X <- c1 X + c3 X Y
+  float pad_[2];
+};
+
+struct Tile { int32_t sub, ti, tj, pad; };
+
+// Host-side record of HIP event pairs around launch groups (measurement only).
+enum TimeCat { T_GATHER = 0, T_SETUP, T_SIGN, T_GEMM, T_PANEL, T_SCATTER, T_NCAT };
+
+struct EventLog {
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+  struct Rec { int cat; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  int64_t n_gemm = 0;
+  double gemm_flop = 0.0;
+  double ms[T_NCAT] = {0, 0, 0, 0, 0, 0};
+
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e;
+      (void)hipEventCreate(&e);
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+  int begin(int cat, hipStream_t s) {
+    if (!on) return -1;
+    Rec r{cat, next(), next()};
+    (void)hipEventRecord(r.a, s);
+    recs.push_back(r);
+    return (int)recs.size() - 1;
+  }
+  void end(int idx, hipStream_t s) {
+    if (idx >= 0) (void)hipEventRecord(recs[idx].b, s);
+  }
+  // Fold completed records into ms[] (waits for the events), recycle the pool.
+  void collect() {
+    for (const Rec &r : recs) {
+      (void)hipEventSynchronize(r.b);
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) ms[r.cat] += t;
+    }
+    recs.clear();
+    used = 0;
+  }
+  ~EventLog() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+
+// ------------------------------------------------------------------ small helpers
+
+template <typename T> __device__ __forceinline__ float to_f32(T v);
+template <> __device__ __forceinline__ float to_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ float to_f32<_Float16>(_Float16 v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f32<__bf16>(__bf16 v) { return (float)v; }
+
+template <typename T> __device__ __forceinline__ T from_f32(float v);
+template <> __device__ __forceinline__ float from_f32<float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 from_f32<_Float16>(float v) { return (_Float16)v; }
+template <> __device__ __forceinline__ __bf16 from_f32<__bf16>(float v) { return (__bf16)v; }
+
+template <typename T> __device__ __forceinline__ T from_f64(double v);
+template <> __device__ __forceinline__ float from_f64<float>(double v) { return (float)v; }
+template <> __device__ __forceinline__ _Float16 from_f64<_Float16>(double v) { return (_Float16)(float)v; }
+template <> __device__ __forceinline__ __bf16 from_f64<__bf16>(double v) { return (__bf16)(float)v; }
+
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Block-wide sum in a fixed order (deterministic); blockDim.x == 256.
+template <typename T>
+__device__ __forceinline__ T block_sum256(T v, T *red /* LDS [4] */) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  T r = (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+  return r;
+}
+
+__device__ __forceinline__ unsigned long long resid_fixed(float partial) {
+  if (!(partial <= RESID_CLAMP)) partial = RESID_CLAMP;    // also catches NaN
+  return (unsigned long long)((double)partial * (double)(1ull << RESID_SHIFT) + 0.5);
+}
+
+// Map a flat workgroup id onto a logical tile id so that consecutive logical
+// tiles (the tiles of one submatrix) land on the same XCD: workgroups are
+// dispatched round-robin over the 8 XCDs, so XCD x runs ids b with b % 8 == x.
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7, i = b >> 3;
+  return x * q + (x < r ? x : r) + i;
+}
+
+}  // namespace nolsm

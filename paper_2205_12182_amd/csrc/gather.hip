@@ -1,0 +1,91 @@
+// Submatrix method, step 1 (paper, Sec. II; Eq. 8 for the non-orthogonal pair):
+// gather the dense principal submatrices T_k(H0), T_k(S) of every planned molecule.
+//
+// One workgroup per (submatrix, member block column b).  It locates every block
+// (J_a, J_b) of the submatrix in block column J_b by binary search, then streams
+// the column-major block column into the dense column-major submatrix: each
+// output column is a contiguous run of n doubles, so writes are coalesced, and
+// each stored block is read contiguously.  The padding rows/columns (n..npad) are
+// written as well: zero for H, the identity for S.
+#include "common.h"
+
+namespace nolsm {
+
+constexpr int GATHER_MAXMEM = 1024;     // members per submatrix held in LDS
+constexpr int GATHER_MAXN = 8192;       // submatrix dimension held in the LDS row map
+
+__global__ __launch_bounds__(256) void gather_kernel(
+    const SubDesc *__restrict__ desc, const int32_t *__restrict__ mem_mol,
+    const int32_t *__restrict__ mem_loc, const int32_t *__restrict__ blk_dim,
+    const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowblk,
+    const int64_t *__restrict__ valoff, const double *__restrict__ H_val,
+    const double *__restrict__ S_val, char *__restrict__ ws) {
+  const SubDesc d = desc[blockIdx.y];
+  const int b = blockIdx.x;
+  if (b > d.nmem) return;                       // b == nmem: padding columns
+  __shared__ int64_t s_t[GATHER_MAXMEM];        // block index of (J_a, J_b) or -1
+  __shared__ int32_t s_loc[GATHER_MAXMEM + 1];
+  __shared__ int32_t s_dim[GATHER_MAXMEM];
+  __shared__ uint16_t s_rowmem[GATHER_MAXN];    // row -> member
+  double *Hk = reinterpret_cast<double *>(ws + d.off_h);
+  double *Sk = reinterpret_cast<double *>(ws + d.off_s);
+  const int n = d.n, ld = d.npad;
+
+  if (b == d.nmem) {                            // columns n..npad: zero / identity
+    for (int c = n; c < ld; ++c)
+      for (int r = threadIdx.x; r < ld; r += blockDim.x) {
+        Hk[(int64_t)c * ld + r] = 0.0;
+        Sk[(int64_t)c * ld + r] = (r == c) ? 1.0 : 0.0;
+      }
+    return;
+  }
+
+  const int Jb = mem_mol[d.mem_off + b];
+  const int locb = mem_loc[d.mem_off + b];
+  const int dJ = blk_dim[Jb];
+  const int64_t c0 = colptr[Jb], c1 = colptr[Jb + 1];
+  for (int a = threadIdx.x; a < d.nmem; a += blockDim.x) {
+    const int Ja = mem_mol[d.mem_off + a];
+    int64_t lo = c0, hi = c1;                   // first row >= Ja
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (rowblk[mid] < Ja) lo = mid + 1; else hi = mid;
+    }
+    s_t[a] = (lo < c1 && rowblk[lo] == Ja) ? lo : -1;
+    s_loc[a] = mem_loc[d.mem_off + a];
+    s_dim[a] = blk_dim[Ja];
+  }
+  __syncthreads();
+  for (int a = 0; a < d.nmem; ++a)
+    for (int r = threadIdx.x; r < s_dim[a]; r += blockDim.x) s_rowmem[s_loc[a] + r] = (uint16_t)a;
+  __syncthreads();
+
+  const int64_t total = (int64_t)ld * dJ;
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
+    const int c = (int)(e / ld);
+    const int i = (int)(e - (int64_t)c * ld);
+    const int64_t dst = (int64_t)(locb + c) * ld + i;
+    double h = 0.0, s = 0.0;
+    if (i < n) {
+      const int a = s_rowmem[i];
+      const int64_t t = s_t[a];
+      if (t >= 0) {
+        const int64_t src = valoff[t] + (int64_t)(i - s_loc[a]) + (int64_t)c * s_dim[a];
+        h = H_val[src];
+        s = S_val[src];
+      }
+    }
+    Hk[dst] = h;
+    Sk[dst] = s;
+  }
+}
+
+void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
+                   const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
+                   const double *S_val, char *ws, hipStream_t stream) {
+  dim3 grid(maxmem + 1, K);
+  gather_kernel<<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim, pat->colptr,
+                                          pat->rowblk, pat->valoff, H_val, S_val, ws);
+}
+
+}  // namespace nolsm

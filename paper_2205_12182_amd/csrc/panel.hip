@@ -1,0 +1,327 @@
+// Density columns, write-back and traces.
+//
+// Only molecule k's own m columns of T_k(D) are written back (paper, Sec. II,
+// submatrix method step 3), and in the symmetric form
+//   T_k(D)[:, own] = 1/2 L^-T (I - X) L^-1[:, own] = 1/2 L^-T (V - X V),  V = L^-1[:, own],
+// so the final refinement of X only has to act on the n x m panel V: s
+// Newton-Schulz steps f(X) = 1/2 X (3I - X^2) applied to V cost 3^s panel
+// products X P (n^2 m each) instead of full n^3 GEMMs.
+//
+//   panel_v_kernel     V = L^-1[:, own]                    (FP64 -> FP32)
+//   panel_mul_kernel   O = alpha X P + beta Q              (X in its iteration precision, FP32 math)
+//   dcol_kernel        Dcol = 1/2 L^-T (V - W)             (FP64)
+//   scatter_kernel     block column k of D <- Dcol; per-column Tr contributions (FP64)
+//   coltrace / final   Tr(D H), Tr(D S) over the whole pattern, fixed reduction order
+#include "common.h"
+
+namespace nolsm {
+
+__device__ __forceinline__ float *panel_ptr(char *ws, const SubDesc &d, int q) {
+  return reinterpret_cast<float *>(ws + d.off_panel) + (int64_t)q * d.npad * d.m;
+}
+
+__global__ __launch_bounds__(256) void panel_v_kernel(const SubDesc *__restrict__ desc,
+                                                      const SubState *__restrict__ st, char *ws,
+                                                      int qv) {
+  const SubDesc d = desc[blockIdx.y];
+  if (st[blockIdx.y].status != 0) return;
+  const double *Li = reinterpret_cast<const double *>(ws + d.off_s);
+  float *V = panel_ptr(ws, d, qv);
+  const int total = d.npad * d.m;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256) {
+    const int c = e / d.npad, r = e - c * d.npad;
+    V[e] = (float)Li[(int64_t)(d.own_lo + c) * d.npad + r];
+  }
+}
+
+// O[:, c] = alpha * X P[:, c] + beta * Q[:, c] for 64 rows per workgroup.
+// X is symmetric, so X(i, k) is read as column i: contiguous in k for the LDS tile.
+template <typename TI>
+__device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict__ P,
+                               const float *__restrict__ Q, float *__restrict__ O, int ld, int m,
+                               float alpha, float beta) {
+  __shared__ float sX[64][65];      // sX[i][k]
+  __shared__ float sP[64][33];      // sP[k][c], m <= 32
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * 64;
+  const int il = tid & 63, cg = tid >> 6;       // row, column group (c = cg + 4 q)
+  float acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
+  for (int k0 = 0; k0 < ld; k0 += 64) {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int kk = e & 63, ii = e >> 6;
+      sX[ii][kk] = (i0 + ii < ld) ? to_f32<TI>(X[(int64_t)(i0 + ii) * ld + k0 + kk]) : 0.0f;
+    }
+    for (int e = tid; e < 64 * m; e += 256) {
+      const int kk = e & 63, c = e >> 6;
+      sP[kk][c] = P[(int64_t)c * ld + k0 + kk];
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < 64; ++kk) {
+      const float x = sX[il][kk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = cg + 4 * q;
+        if (c < m) acc[q] += x * sP[kk][c];
+      }
+    }
+    __syncthreads();
+  }
+  const int i = i0 + il;
+  if (i >= ld) return;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = cg + 4 * q;
+    if (c >= m) continue;
+    float v = alpha * acc[q];
+    if (beta != 0.0f) v += beta * Q[(int64_t)c * ld + i];
+    O[(int64_t)c * ld + i] = v;
+  }
+}
+
+__global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restrict__ desc,
+                                                        const SubState *__restrict__ st, char *ws,
+                                                        int qp, int qq, int qo, float alpha,
+                                                        float beta) {
+  const SubDesc d = desc[blockIdx.y];
+  const SubState &s = st[blockIdx.y];
+  if (s.status != 0 || blockIdx.x * 64 >= (unsigned)d.npad) return;
+  const float *P = panel_ptr(ws, d, qp);
+  const float *Q = panel_ptr(ws, d, qq);
+  float *O = panel_ptr(ws, d, qo);
+  const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
+  if (s.prec == P_FP32)
+    panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, d.m, alpha, beta);
+  else if (s.prec == P_FP16)
+    panel_mul_body<_Float16>(reinterpret_cast<const _Float16 *>(xb), P, Q, O, d.npad, d.m, alpha,
+                             beta);
+  else
+    panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, d.m, alpha,
+                           beta);
+}
+
+// Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c])
+__global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ desc,
+                                                   const SubState *__restrict__ st, char *ws,
+                                                   int qv, int qw) {
+  const SubDesc d = desc[blockIdx.y];
+  if (st[blockIdx.y].status != 0) return;
+  const int ld = d.npad, m = d.m;
+  const int i0 = blockIdx.x * 64;
+  if (i0 >= ld) return;
+  const double *Li = reinterpret_cast<const double *>(ws + d.off_s);
+  const float *V = panel_ptr(ws, d, qv);
+  const float *W = panel_ptr(ws, d, qw);
+  double *Dc = reinterpret_cast<double *>(ws + d.off_dcol);
+  __shared__ double sL[64][65];     // sL[i][k] = Linv[k0 + k, i0 + i]
+  __shared__ double sU[64][33];
+  const int tid = threadIdx.x, il = tid & 63, cg = tid >> 6;
+  double acc[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  for (int k0 = i0; k0 < ld; k0 += 64) {
+    for (int e = tid; e < 64 * 64; e += 256) {
+      const int kk = e & 63, ii = e >> 6;
+      sL[ii][kk] = Li[(int64_t)(i0 + ii) * ld + k0 + kk];
+    }
+    for (int e = tid; e < 64 * m; e += 256) {
+      const int kk = e & 63, c = e >> 6;
+      const int64_t x = (int64_t)c * ld + k0 + kk;
+      sU[kk][c] = (double)V[x] - (double)W[x];
+    }
+    __syncthreads();
+    for (int kk = 0; kk < 64; ++kk) {
+      const double l = sL[il][kk];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int c = cg + 4 * q;
+        if (c < m) acc[q] += l * sU[kk][c];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int c = cg + 4 * q;
+    if (c < m) Dc[(int64_t)c * ld + i0 + il] = 0.5 * acc[q];
+  }
+}
+
+// Write block column `mol` of D and sum its contributions to Tr(DH), Tr(DS).
+__global__ __launch_bounds__(256) void scatter_kernel(
+    const SubDesc *__restrict__ desc, const SubState *__restrict__ st,
+    const int32_t *__restrict__ mem_mol, const int32_t *__restrict__ mem_loc,
+    const int32_t *__restrict__ blk_dim, const int64_t *__restrict__ colptr,
+    const int64_t *__restrict__ valoff, double *__restrict__ D_val,
+    const double *__restrict__ H_val, const double *__restrict__ S_val, const char *ws,
+    nolsm_stats *__restrict__ stats) {
+  const SubDesc d = desc[blockIdx.x];
+  __shared__ double red[4];
+  const double *Dc = reinterpret_cast<const double *>(ws + d.off_dcol);
+  const bool ok = st[blockIdx.x].status == 0;
+  double eh = 0.0, es = 0.0;
+  const int64_t t0 = colptr[d.mol];
+  for (int a = 0; a < d.nmem; ++a) {
+    const int I = mem_mol[d.mem_off + a];
+    const int loc = mem_loc[d.mem_off + a];
+    const int dI = blk_dim[I];
+    const int64_t base = valoff[t0 + a];
+    for (int e = threadIdx.x; e < dI * d.m; e += 256) {
+      const int c = e / dI, r = e - c * dI;
+      const double v = ok ? Dc[(int64_t)c * d.npad + loc + r] : 0.0;
+      D_val[base + e] = v;
+      eh += v * H_val[base + e];
+      es += v * S_val[base + e];
+    }
+  }
+  eh = block_sum256(eh, red);
+  es = block_sum256(es, red);
+  if (threadIdx.x == 0 && stats) {
+    stats[blockIdx.x].tr_dh = eh;
+    stats[blockIdx.x].tr_ds = es;
+  }
+}
+
+__global__ __launch_bounds__(256) void coltrace_kernel(const int32_t *__restrict__ blk_dim,
+                                                       const int64_t *__restrict__ colptr,
+                                                       const int32_t *__restrict__ rowblk,
+                                                       const int64_t *__restrict__ valoff,
+                                                       const double *__restrict__ D_val,
+                                                       const double *__restrict__ H_val,
+                                                       const double *__restrict__ S_val,
+                                                       double *__restrict__ col_traces) {
+  const int k = blockIdx.x;
+  __shared__ double red[4];
+  double eh = 0.0, es = 0.0;
+  const int dk = blk_dim[k];
+  for (int64_t t = colptr[k]; t < colptr[k + 1]; ++t) {
+    const int sz = blk_dim[rowblk[t]] * dk;
+    const int64_t b = valoff[t];
+    for (int e = threadIdx.x; e < sz; e += 256) {
+      const double v = D_val[b + e];
+      eh += v * H_val[b + e];
+      es += v * S_val[b + e];
+    }
+  }
+  eh = block_sum256(eh, red);
+  es = block_sum256(es, red);
+  if (threadIdx.x == 0) {
+    col_traces[2 * k] = eh;
+    col_traces[2 * k + 1] = es;
+  }
+}
+
+__global__ __launch_bounds__(256) void final_trace_kernel(const double *__restrict__ col_traces,
+                                                          int nmol, double *__restrict__ out2) {
+  __shared__ double red[4];
+  double eh = 0.0, es = 0.0;
+  for (int k = threadIdx.x; k < nmol; k += 256) {
+    eh += col_traces[2 * k];
+    es += col_traces[2 * k + 1];
+  }
+  eh = block_sum256(eh, red);
+  es = block_sum256(es, red);
+  if (threadIdx.x == 0) {
+    out2[0] = eh;
+    out2[1] = es;
+  }
+}
+
+// Copy the per-submatrix record to the caller's stats array.
+__global__ void stats_kernel(const SubDesc *__restrict__ desc, const SubState *__restrict__ st,
+                             int K, nolsm_stats *__restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  const SubState &s = st[i];
+  nolsm_stats r;
+  r.n = desc[i].n;
+  r.status = s.status;
+  r.iters_lo = s.iters_lo;
+  r.iters_fb = s.iters_fb;
+  r.resid = s.resid;
+  r.fell_back = s.fell_back;
+  r.scale = s.scale;
+  r.tr_dh = 0.0;
+  r.tr_ds = 0.0;
+  out[i] = r;
+}
+
+// ------------------------------------------------------------------ host side
+
+__global__ __launch_bounds__(256) void panel_axpby_kernel(const SubDesc *__restrict__ desc,
+                                                          const SubState *__restrict__ st,
+                                                          char *ws, int qa, int qb, float alpha,
+                                                          float beta) {
+  const SubDesc d = desc[blockIdx.y];
+  if (st[blockIdx.y].status != 0) return;
+  float *A = panel_ptr(ws, d, qa);
+  const float *B = panel_ptr(ws, d, qb);
+  const int total = d.npad * d.m;
+  for (int e = blockIdx.x * 256 + threadIdx.x; e < total; e += gridDim.x * 256)
+    A[e] = alpha * A[e] + beta * B[e];
+}
+
+// g_s(P) = F_s P with F_0 = X, F_s = f(F_{s-1}), f(X) = 1/2 X (3I - X^2):
+//   g_0(P) = X P,   g_s(P) = 3/2 g_{s-1}(P) - 1/2 g_{s-1}(g_{s-1}(g_{s-1}(P))).
+// 3^s panel products.  Slots are panel buffers; returns the slot holding g_s(P).
+struct PanelCtx {
+  const SubDesc *desc;
+  const SubState *st;
+  int K, max_npad;
+  char *ws;
+  hipStream_t s;
+  unsigned used;
+  int alloc() {
+    for (int q = 0; q < NPANEL; ++q)
+      if (!(used & (1u << q))) { used |= 1u << q; return q; }
+    return -1;
+  }
+  void release(int q) { used &= ~(1u << q); }
+  int apply(int steps, int qin) {
+    const dim3 grid(max_npad / 64, K);
+    if (steps == 0) {
+      const int qo = alloc();
+      panel_mul_kernel<<<grid, 256, 0, s>>>(desc, st, ws, qin, qin, qo, 1.0f, 0.0f);
+      return qo;
+    }
+    const int q1 = apply(steps - 1, qin);
+    const int q2 = apply(steps - 1, q1);
+    const int q3 = apply(steps - 1, q2);
+    release(q2);
+    panel_axpby_kernel<<<dim3(64, K), 256, 0, s>>>(desc, st, ws, q1, q3, 1.5f, -0.5f);
+    release(q3);
+    return q1;
+  }
+};
+
+void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
+                            char *ws, int panel_steps, hipStream_t s) {
+  PanelCtx c{desc, st, K, max_npad, ws, s, 1u};   // slot 0 holds V
+  panel_v_kernel<<<dim3(64, K), 256, 0, s>>>(desc, st, ws, 0);
+  const int qw = c.apply(panel_steps, 0);
+  dcol_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, 0, qw);
+}
+
+void launch_scatter(const SubDesc *desc, const SubState *st, int K, const int32_t *mem_mol,
+                    const int32_t *mem_loc, const nolsm_pattern *pat, double *D_val,
+                    const double *H_val, const double *S_val, const char *ws,
+                    nolsm_stats *stats, hipStream_t s) {
+  scatter_kernel<<<K, 256, 0, s>>>(desc, st, mem_mol, mem_loc, pat->blk_dim, pat->colptr,
+                                   pat->valoff, D_val, H_val, S_val, ws, stats);
+}
+
+void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, const double *H_val,
+                   const double *S_val, double *col_traces, double *out2, hipStream_t s) {
+  coltrace_kernel<<<nmol, 256, 0, s>>>(pat->blk_dim, pat->colptr, pat->rowblk, pat->valoff,
+                                       D_val, H_val, S_val, col_traces);
+  final_trace_kernel<<<1, 256, 0, s>>>(col_traces, nmol, out2);
+}
+
+void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
+                  hipStream_t s) {
+  stats_kernel<<<(K + 255) / 256, 256, 0, s>>>(desc, st, K, out);
+}
+
+}  // namespace nolsm

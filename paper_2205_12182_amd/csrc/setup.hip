@@ -1,0 +1,318 @@
+// FP64 set-up of the sign argument for Eq. 8.
+//
+// T_k(S)^-1 T_k(H0) - mu I has the same spectrum as the symmetric matrix
+//   M_k - mu I,  M_k = L^-1 T_k(H0) L^-T,  T_k(S) = L L^T,
+// and sign(S^-1 H - mu I) = L^-T sign(M - mu I) L^T, so Eq. 8 becomes
+//   T_k(D) = 1/2 L^-T (I - sign(M_k - mu I)) L^-1.
+// M_k does not depend on mu; mu is applied when the first iterate is formed.
+//
+// Kernels (all batched over the planned submatrices, one launch per block step):
+//   chol_diag    unblocked Cholesky of a 64x64 diagonal block in LDS, plus its inverse
+//   chol_panel   A[j+64:, j] <- A[j+64:, j] L_jj^-T                  (FP64 MFMA)
+//   chol_update  A[j+64:, j+64:] -= P P^T, lower tiles                 (FP64 MFMA)
+//   trtri_*      L^-1 in place, block columns right to left            (FP64 MFMA)
+//   trmm_left    T = L^-1 H                                             (FP64 MFMA)
+//   trmm_right   M = T L^-T, lower tiles mirrored (M exactly symmetric) (FP64 MFMA)
+#include "common.h"
+
+namespace nolsm {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int KS64 = 16;           // k per LDS stage
+constexpr int LDP = 64 + 1;        // padded LDS row (doubles)
+
+// acc += A[i0:i0+64, k0:k1] * opB(B)[k0:k1, j0:j0+64]   (A column major, lda)
+// TRANSB = false: B(k, n) at B[n * ldb + k];  true: B(k, n) at B[k * ldb + n].
+// Wave w owns rows (w >> 1) * 32, cols (w & 1) * 32 as 2 x 2 blocks of 16 x 16.
+// v_mfma_f64_16x16x4_f64 takes A(i, k) from lane i + 16 k and B(k, j) from lane
+// j + 16 k, and returns D(i, j) in lane j + 16 (i % 4), register i / 4; so
+// acc[bm][bn][q] is element (row 16 bm + (lane >> 4) + 4 q, col 16 bn + (lane & 15)).
+template <bool TRANSB>
+__device__ __forceinline__ void gemm64_f64(const double *__restrict__ A, int64_t lda,
+                                           const double *__restrict__ B, int64_t ldb, int k0,
+                                           int k1, d4 acc[2][2], double *sA, double *sB) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  for (int k = k0; k < k1; k += KS64) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {                      // A: 64 rows x 16 k
+      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
+      sA[kk * LDP + m] = A[(int64_t)(k + kk) * lda + m];
+    }
+    if (!TRANSB) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {                    // B: contiguous in k
+        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
+        sB[kk * LDP + nn] = B[(int64_t)nn * ldb + k + kk];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {                    // B: contiguous in n
+        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
+        sB[kk * LDP + nn] = B[(int64_t)(k + kk) * ldb + nn];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KS64; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        a[t] = sA[kr * LDP + wm + 16 * t + (lane & 15)];
+        b[t] = sB[kr * LDP + wn + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+          acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+}
+
+__device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = d4{0.0, 0.0, 0.0, 0.0};
+}
+
+// Visit the 64x64 tile owned by this thread: f(r, c, value).
+template <typename F>
+__device__ __forceinline__ void acc_foreach(d4 acc[2][2], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        f(wm + 16 * bm + (lane >> 4) + 4 * q, wn + 16 * bn + (lane & 15), acc[bm][bn][q]);
+}
+
+__device__ __forceinline__ void tri_index(int x, int &ti, int &tj) {   // x -> (ti >= tj)
+  int t = (int)((sqrtf(8.0f * (float)x + 1.0f) - 1.0f) * 0.5f);
+  while ((t + 1) * (t + 2) / 2 <= x) ++t;
+  while (t * (t + 1) / 2 > x) --t;
+  ti = t;
+  tj = x - t * (t + 1) / 2;
+}
+
+#define SUB_PTRS                                                               \
+  const SubDesc d = desc[blockIdx.y];                                          \
+  const int ld = d.npad;                                                       \
+  double *Hb = reinterpret_cast<double *>(ws + d.off_h);                       \
+  double *Sb = reinterpret_cast<double *>(ws + d.off_s);                       \
+  double *Dinv = reinterpret_cast<double *>(ws + d.off_diag);                  \
+  double *Tmp = Dinv + (int64_t)ld * NB;                                       \
+  (void)Hb; (void)Sb; (void)Dinv; (void)Tmp;
+
+// ------------------------------------------------------------------ Cholesky
+
+__global__ __launch_bounds__(256) void chol_diag_kernel(const SubDesc *__restrict__ desc,
+                                                        SubState *__restrict__ st, char *ws,
+                                                        int jb) {
+  SUB_PTRS
+  const int j = jb * NB;
+  if (j >= ld) return;
+  __shared__ double sL[NB * LDP];
+  __shared__ double sI[NB * LDP];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    sL[r * LDP + c] = Sb[(int64_t)(j + c) * ld + j + r];
+  }
+  __syncthreads();
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+  for (int c = 0; c < NB; ++c) {
+    if (tid == 0) {
+      double p = sL[c * LDP + c];
+      if (!(p > 0.0)) { bad = 1; p = 1.0; }
+      sL[c * LDP + c] = sqrt(p);
+    }
+    __syncthreads();
+    if (tid > c && tid < NB) sL[tid * LDP + c] /= sL[c * LDP + c];
+    __syncthreads();
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e >> 6, s = e & 63;
+      if (s > c && r >= s) sL[r * LDP + s] -= sL[r * LDP + c] * sL[s * LDP + c];
+    }
+    __syncthreads();
+  }
+  if (tid < NB) {                                   // column tid of L_jj^-1
+    const int c = tid;
+    for (int r = 0; r < NB; ++r) {
+      if (r < c) { sI[r * LDP + c] = 0.0; continue; }
+      double s = (r == c) ? 1.0 : 0.0;
+      for (int q = c; q < r; ++q) s -= sL[r * LDP + q] * sI[q * LDP + c];
+      sI[r * LDP + c] = s / sL[r * LDP + r];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    Sb[(int64_t)(j + c) * ld + j + r] = (r >= c) ? sL[r * LDP + c] : 0.0;
+    Dinv[(int64_t)jb * NB * NB + r + c * NB] = sI[r * LDP + c];
+  }
+  if (tid == 0 && bad) st[blockIdx.y].status = NOLSM_ENOTSPD;
+}
+
+__global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restrict__ desc,
+                                                         char *ws, int jb) {
+  SUB_PTRS
+  const int j = jb * NB;
+  const int i0 = j + NB + blockIdx.x * 64;
+  if (i0 >= ld) return;
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  // out(r, c) = sum_s P(r, s) Linv_jj(c, s);  B(k=s, n=c) = Dinv[c + s*64]
+  gemm64_f64<true>(Sb + (int64_t)j * ld + i0, ld, Dinv + (int64_t)jb * NB * NB, NB, 0, NB, acc,
+                   sA, sB);
+  acc_foreach(acc, [&](int r, int c, double v) { Sb[(int64_t)(j + c) * ld + i0 + r] = v; });
+}
+
+__global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restrict__ desc,
+                                                          char *ws, int jb) {
+  SUB_PTRS
+  const int j = jb * NB, m0 = j + NB;
+  if (m0 >= ld) return;
+  const int T = (ld - m0) / 64;
+  int ti, tj;
+  tri_index(blockIdx.x, ti, tj);
+  if (ti >= T) return;
+  const int r0 = m0 + ti * 64, c0 = m0 + tj * 64;
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  // C(r, c) -= sum_s P(r0 + r, s) P(c0 + c, s);  B(k=s, n=c) = S[(j+s)*ld + c0 + c]
+  gemm64_f64<true>(Sb + (int64_t)j * ld + r0, ld, Sb + (int64_t)j * ld + c0, ld, 0, NB, acc, sA,
+                   sB);
+  acc_foreach(acc, [&](int r, int c, double v) {
+    double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
+    *p = *p - v;
+  });
+}
+
+// ------------------------------------------------------------------ L^-1 in place
+
+__global__ __launch_bounds__(256) void trtri_diag_kernel(const SubDesc *__restrict__ desc,
+                                                         char *ws) {
+  SUB_PTRS
+  const int jb = blockIdx.x;
+  const int j = jb * NB;
+  if (j >= ld) return;
+  for (int e = threadIdx.x; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    Sb[(int64_t)(j + c) * ld + j + r] = Dinv[(int64_t)jb * NB * NB + r + c * NB];
+  }
+}
+
+// Tmp[i, c] = sum_s L[i, j + s] Linv_jj[s, c]  for rows i >= j + 64
+__global__ __launch_bounds__(256) void trtri_panel_kernel(const SubDesc *__restrict__ desc,
+                                                          char *ws, int jb) {
+  SUB_PTRS
+  const int j = jb * NB;
+  const int i0 = j + NB + blockIdx.x * 64;
+  if (i0 >= ld) return;
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  gemm64_f64<false>(Sb + (int64_t)j * ld + i0, ld, Dinv + (int64_t)jb * NB * NB, NB, 0, NB, acc,
+                    sA, sB);
+  acc_foreach(acc, [&](int r, int c, double v) { Tmp[(int64_t)c * ld + i0 + r] = v; });
+}
+
+// Linv[i, j-block] = - sum_{k = j+64}^{i-block end} Linv[i, k] Tmp[k, :]
+__global__ __launch_bounds__(256) void trtri_update_kernel(const SubDesc *__restrict__ desc,
+                                                           char *ws, int jb) {
+  SUB_PTRS
+  const int j = jb * NB;
+  const int i0 = j + NB + blockIdx.x * 64;
+  if (i0 >= ld) return;
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  gemm64_f64<false>(Sb + i0, ld, Tmp, ld, j + NB, i0 + 64, acc, sA, sB);
+  acc_foreach(acc, [&](int r, int c, double v) { Sb[(int64_t)(j + c) * ld + i0 + r] = -v; });
+}
+
+__global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restrict__ desc,
+                                                         char *ws) {
+  SUB_PTRS
+  const int c = blockIdx.x;
+  if (c >= ld) return;
+  for (int r = threadIdx.x; r < c; r += 256) Sb[(int64_t)c * ld + r] = 0.0;
+}
+
+// ------------------------------------------------------------------ M = L^-1 H L^-T
+
+// T = Linv H into the low-precision arena (used as FP64 scratch before the iteration)
+__global__ __launch_bounds__(256) void trmm_left_kernel(const SubDesc *__restrict__ desc,
+                                                        char *ws) {
+  SUB_PTRS
+  const int nt = ld / 64;
+  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;   // blockIdx.x < ntmax^2
+  if (blockIdx.x >= nt * nt) return;
+  double *Tb = reinterpret_cast<double *>(ws + d.off_lo);
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  gemm64_f64<false>(Sb + ti * 64, ld, Hb + (int64_t)tj * 64 * ld, ld, 0, (ti + 1) * 64, acc, sA,
+                    sB);
+  acc_foreach(acc,
+              [&](int r, int c, double v) { Tb[(int64_t)(tj * 64 + c) * ld + ti * 64 + r] = v; });
+}
+
+// M = T Linv^T, lower tiles, written to both triangles of the H buffer
+__global__ __launch_bounds__(256) void trmm_right_kernel(const SubDesc *__restrict__ desc,
+                                                         char *ws) {
+  SUB_PTRS
+  const int nt = ld / 64;
+  int ti, tj;
+  tri_index(blockIdx.x, ti, tj);
+  if (ti >= nt) return;
+  const double *Tb = reinterpret_cast<const double *>(ws + d.off_lo);
+  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  // M(r, c) = sum_k T(ti*64 + r, k) Linv(tj*64 + c, k);  B(k, n) = Linv[k*ld + tj*64 + n]
+  gemm64_f64<true>(Tb + ti * 64, ld, Sb + tj * 64, ld, 0, (tj + 1) * 64, acc, sA, sB);
+  acc_foreach(acc, [&](int r, int c, double v) {
+    const int gi = ti * 64 + r, gj = tj * 64 + c;
+    if (gi < gj) return;            // diagonal tiles: the lower half writes both triangles
+    Hb[(int64_t)gj * ld + gi] = v;
+    Hb[(int64_t)gi * ld + gj] = v;
+  });
+}
+
+// ------------------------------------------------------------------ host launcher
+
+void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
+                  hipStream_t s) {
+  const int nbmax = max_npad / NB;
+  for (int jb = 0; jb < nbmax; ++jb) {
+    chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
+    const int rem = nbmax - jb - 1;
+    if (rem > 0) {
+      chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
+      chol_update_kernel<<<dim3(rem * (rem + 1) / 2, K), 256, 0, s>>>(desc, ws, jb);
+    }
+  }
+  trtri_diag_kernel<<<dim3(nbmax, K), 256, 0, s>>>(desc, ws);
+  for (int jb = nbmax - 2; jb >= 0; --jb) {
+    const int rem = nbmax - jb - 1;
+    trtri_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
+    trtri_update_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
+  }
+  zero_upper_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, ws);
+  trmm_left_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
+  trmm_right_kernel<<<dim3(nbmax * (nbmax + 1) / 2, K), 256, 0, s>>>(desc, ws);
+}
+
+}  // namespace nolsm

@@ -1,0 +1,527 @@
+// Batched Newton-Schulz sign iteration (paper, Eq. 6-7) on MFMA.
+//
+// Every iterate X_k is a polynomial in the symmetric M_k, so X_k, Y_k = X_k^2 and
+// X_k Y_k are symmetric: each product is formed only on the upper-triangle
+// ST x ST output tiles and mirrored into the lower triangle (this also keeps the
+// iterates exactly symmetric).  One launch covers the tiles of every active
+// submatrix of the batch (a grouped GEMM over submatrices of different n); a
+// per-submatrix state word decides which submatrices still iterate.
+//
+// Per iteration:
+//   ns_gemm<SQUARE>   Y = X X                and sum (Y - I)^2 for the residual
+//   ns_check          residual, stop rule, coefficients (c1, c3)
+//   ns_gemm<UPDATE>   X' = c1 X + c3 X Y     (Newton-Schulz: c1 = 3/2, c3 = -1/2)
+//   ns_advance        X <- X', advance the spectral lower bound
+//
+// Operands: both factors are read as column panels (A(m, k) = X(k, m) by
+// symmetry), so every lane's MFMA fragment is a run of consecutive k.  The k
+// order inside an LDS stage is permuted identically for A and B, which leaves the
+// contraction unchanged and lets each lane read its whole stage slice as one
+// 32-byte LDS access.
+#include "common.h"
+
+namespace nolsm {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef float f16x __attribute__((ext_vector_type(16)));
+
+enum { EPI_SQUARE = 0, EPI_UPDATE = 1 };
+
+constexpr int LROW16 = 5;          // LDS row: 80 bytes = 5 x uint4 (64 data + 16 pad)
+constexpr int STAGE_U4 = ST * LROW16;
+
+template <typename TI> struct KStage;
+template <> struct KStage<_Float16> { static constexpr int KS = 32; };
+template <> struct KStage<__bf16> { static constexpr int KS = 32; };
+template <> struct KStage<float> { static constexpr int KS = 16; };
+
+template <typename TI>
+__device__ __forceinline__ void mfma_stage(const uint4 a[2][2], const uint4 b[2][2],
+                                           f16x acc[2][2]);
+
+template <>
+__device__ __forceinline__ void mfma_stage<_Float16>(const uint4 a[2][2], const uint4 b[2][2],
+                                                     f16x acc[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        h8 av = __builtin_bit_cast(h8, a[bm][s]);
+        h8 bv = __builtin_bit_cast(h8, b[bn][s]);
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[bm][bn], 0, 0, 0);
+      }
+}
+
+template <>
+__device__ __forceinline__ void mfma_stage<__bf16>(const uint4 a[2][2], const uint4 b[2][2],
+                                                   f16x acc[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        b8 av = __builtin_bit_cast(b8, a[bm][s]);
+        b8 bv = __builtin_bit_cast(b8, b[bn][s]);
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bm][bn], 0, 0, 0);
+      }
+}
+
+template <>
+__device__ __forceinline__ void mfma_stage<float>(const uint4 a[2][2], const uint4 b[2][2],
+                                                  f16x acc[2][2]) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) {
+        const uint4 &av = a[bm][s >> 2];
+        const uint4 &bv = b[bn][s >> 2];
+        const unsigned ai = (s & 3) == 0 ? av.x : (s & 3) == 1 ? av.y : (s & 3) == 2 ? av.z : av.w;
+        const unsigned bi = (s & 3) == 0 ? bv.x : (s & 3) == 1 ? bv.y : (s & 3) == 2 ? bv.z : bv.w;
+        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, ai),
+                                                          __builtin_bit_cast(float, bi),
+                                                          acc[bm][bn], 0, 0, 0);
+      }
+}
+
+template <typename TI>
+__device__ __forceinline__ TI *buf_ptr(char *ws, const SubDesc &d, int q) {
+  return reinterpret_cast<TI *>(ws + d.off_lo + (int64_t)q * 4 * d.npad * d.npad);
+}
+
+// 256 threads, tile ST x ST = 128 x 128, wave w owns rows (w >> 1) * 64, cols (w & 1) * 64.
+template <typename TI, int EPI>
+__global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ tiles,
+                                                      const SubDesc *__restrict__ desc,
+                                                      SubState *__restrict__ st, char *ws,
+                                                      int prec) {
+  constexpr int KS = KStage<TI>::KS;
+  const Tile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  SubState &S = st[t.sub];
+  if (!S.active || S.prec != prec) return;
+  const SubDesc d = desc[t.sub];
+  const int ld = d.npad, n = d.n;
+  const int cur = S.cur;
+  const TI *A = buf_ptr<TI>(ws, d, cur);
+  const TI *B = (EPI == EPI_SQUARE) ? A : buf_ptr<TI>(ws, d, (cur + 1) % 3);
+  TI *Out = buf_ptr<TI>(ws, d, (cur + (EPI == EPI_SQUARE ? 1 : 2)) % 3);
+  const int i0 = t.ti * ST, j0 = t.tj * ST;
+
+  __shared__ uint4 sA[2][STAGE_U4];
+  __shared__ uint4 sB[2][STAGE_U4];
+  __shared__ float red[4];
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int lrow = tid >> 1, lpart = tid & 1;           // loader: row, 32-byte half
+  const bool arow_ok = (i0 + lrow) < ld, brow_ok = (j0 + lrow) < ld;
+  const uint4 *gA = reinterpret_cast<const uint4 *>(A + (int64_t)(i0 + lrow) * ld) + lpart * 2;
+  const uint4 *gB = reinterpret_cast<const uint4 *>(B + (int64_t)(j0 + lrow) * ld) + lpart * 2;
+  const int kstep_u4 = KS * (int)sizeof(TI) / 16;       // uint4 per row per stage (= 4)
+  const uint4 zero = {0u, 0u, 0u, 0u};
+
+  f16x acc[2][2];
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[bm][bn][q] = 0.0f;
+
+  const int nk = ld / KS;
+  uint4 ra0, ra1, rb0, rb1;
+  ra0 = arow_ok ? gA[0] : zero;
+  ra1 = arow_ok ? gA[1] : zero;
+  rb0 = brow_ok ? gB[0] : zero;
+  rb1 = brow_ok ? gB[1] : zero;
+  sA[0][lrow * LROW16 + lpart * 2] = ra0;
+  sA[0][lrow * LROW16 + lpart * 2 + 1] = ra1;
+  sB[0][lrow * LROW16 + lpart * 2] = rb0;
+  sB[0][lrow * LROW16 + lpart * 2 + 1] = rb1;
+  __syncthreads();
+
+  const int h = lane >> 5, l32 = lane & 31;
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) {
+      const int o = (kt + 1) * kstep_u4;
+      ra0 = arow_ok ? gA[o] : zero;
+      ra1 = arow_ok ? gA[o + 1] : zero;
+      rb0 = brow_ok ? gB[o] : zero;
+      rb1 = brow_ok ? gB[o + 1] : zero;
+    }
+    uint4 af[2][2], bf[2][2];
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm) {
+      const int r = wm + bm * 32 + l32;
+      af[bm][0] = sA[buf][r * LROW16 + h * 2];
+      af[bm][1] = sA[buf][r * LROW16 + h * 2 + 1];
+    }
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) {
+      const int r = wn + bn * 32 + l32;
+      bf[bn][0] = sB[buf][r * LROW16 + h * 2];
+      bf[bn][1] = sB[buf][r * LROW16 + h * 2 + 1];
+    }
+    mfma_stage<TI>(af, bf, acc);
+    if (kt + 1 < nk) {
+      sA[buf ^ 1][lrow * LROW16 + lpart * 2] = ra0;
+      sA[buf ^ 1][lrow * LROW16 + lpart * 2 + 1] = ra1;
+      sB[buf ^ 1][lrow * LROW16 + lpart * 2] = rb0;
+      sB[buf ^ 1][lrow * LROW16 + lpart * 2 + 1] = rb1;
+    }
+    __syncthreads();
+  }
+
+  // epilogue: element (r, c) of block (bm, bn), register q:
+  //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32
+  const float c1 = S.c1, c3 = S.c3;
+  float rs = 0.0f;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const int gr = i0 + wm + 32 * bm + 8 * (q >> 2) + 4 * h + (q & 3);
+        const int gc = j0 + wn + 32 * bn + l32;
+        if (gr > gc || gc >= ld) continue;
+        float v = acc[bm][bn][q];
+        if (EPI == EPI_SQUARE) {
+          if (gc < n) {
+            const float e = v - (gr == gc ? 1.0f : 0.0f);
+            rs += (gr == gc ? 1.0f : 2.0f) * e * e;
+          }
+        } else {
+          v = c3 * v + c1 * to_f32<TI>(A[(int64_t)gc * ld + gr]);
+        }
+        const TI o = from_f32<TI>(v);
+        Out[(int64_t)gc * ld + gr] = o;
+        Out[(int64_t)gr * ld + gc] = o;
+      }
+  if (EPI == EPI_SQUARE) {
+    const float tot = block_sum256(rs, red);
+    if (tid == 0) atomicAdd(&S.racc, resid_fixed(tot));
+  }
+}
+
+// ------------------------------------------------------------------ per-submatrix control
+
+struct PhaseArgs {
+  int prec, t, iters, extra, use_lower;
+  float tol;
+};
+
+__device__ __forceinline__ void set_coeffs(SubState &s, int use_lower) {
+  if (use_lower && s.lower < 1.0) {
+    const double l = s.lower;
+    const double a = sqrt(3.0 / (1.0 + l + l * l));
+    s.c1 = (float)(1.5 * a);
+    s.c3 = (float)(-0.5 * a * a * a);
+  } else {
+    s.c1 = 1.5f;
+    s.c3 = -0.5f;
+  }
+}
+
+__global__ void ns_check_kernel(const SubDesc *__restrict__ desc, SubState *__restrict__ st,
+                                int K, PhaseArgs p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (!s.active || s.prec != p.prec) return;
+  // r = ||X^2 - I||_F bounds |1 - x^2| for every eigenvalue x of X, so r <= tol
+  // certifies the whole spectrum (a mean-square measure would let a few slow
+  // eigenvalues near the gap pass).
+  const double sum = (double)s.racc * (1.0 / (double)(1ull << RESID_SHIFT));
+  s.racc = 0ull;
+  const float r = (float)sqrt(sum);
+  (void)desc;
+  s.resid = r;
+  bool go;
+  if (!(r < 1.0e3f)) {
+    go = false;                                    // diverged or NaN
+  } else if (p.tol > 0.0f) {
+    if (s.extra_left < 0 && r <= p.tol) { s.extra_left = p.extra; s.converged = 1; }
+    if (s.extra_left == 0) go = false;
+    else {
+      go = p.t < p.iters;
+      if (s.extra_left > 0) --s.extra_left;
+    }
+  } else {
+    go = p.t < p.iters;
+  }
+  if (!go) s.active = 0;
+  else set_coeffs(s, p.use_lower);
+}
+
+__global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, int use_lower,
+                                  int fallback) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (!s.active || s.prec != prec) return;
+  s.cur = (s.cur + 2) % 3;
+  if (fallback) ++s.iters_fb; else ++s.iters_lo;
+  if (use_lower && s.lower < 1.0) {
+    const double l = s.lower;
+    const double a = sqrt(3.0 / (1.0 + l + l * l));
+    double ln = 0.5 * a * l * (3.0 - a * a * l * l);
+    s.lower = ln > 1.0 ? 1.0 : ln;
+  }
+}
+
+// Start a phase: every healthy submatrix iterates; convert the current iterate
+// if the phase changes precision (handled by convert_kernel on the host side).
+__global__ void phase_start_kernel(SubState *__restrict__ st, int K, int prec, int only_fb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (s.status != 0) { s.active = 0; return; }
+  if (only_fb && !s.fell_back) { s.active = 0; return; }
+  s.active = 1;
+  s.extra_left = -1;
+  s.converged = 0;
+  s.racc = 0ull;
+  (void)prec;
+}
+
+__global__ void phase_end_kernel(SubState *__restrict__ st, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  st[i].active = 0;
+}
+
+// Convert the current iterate to precision `to` (one column per workgroup).
+template <typename TF, typename TT>
+__device__ void convert_col(const TF *src, TT *dst, int ld, int c) {
+  for (int r = threadIdx.x; r < ld; r += blockDim.x)
+    dst[(int64_t)c * ld + r] = from_f32<TT>(to_f32<TF>(src[(int64_t)c * ld + r]));
+}
+
+__global__ __launch_bounds__(256) void convert_kernel(const SubDesc *__restrict__ desc,
+                                                      const SubState *__restrict__ st, char *ws,
+                                                      int to) {
+  const SubDesc d = desc[blockIdx.y];
+  const SubState &s = st[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.npad || s.status != 0 || s.prec == to) return;
+  const int q = s.cur, qn = (s.cur + 1) % 3;
+#define CV(TF, TT) convert_col<TF, TT>(buf_ptr<TF>(ws, d, q), buf_ptr<TT>(ws, d, qn), d.npad, c)
+  if (s.prec == P_FP32 && to == P_FP16) CV(float, _Float16);
+  else if (s.prec == P_FP32 && to == P_BF16) CV(float, __bf16);
+  else if (s.prec == P_FP16 && to == P_FP32) CV(_Float16, float);
+  else if (s.prec == P_FP16 && to == P_BF16) CV(_Float16, __bf16);
+  else if (s.prec == P_BF16 && to == P_FP32) CV(__bf16, float);
+  else if (s.prec == P_BF16 && to == P_FP16) CV(__bf16, _Float16);
+#undef CV
+}
+
+__global__ void convert_commit_kernel(SubState *__restrict__ st, int K, int to) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (s.status != 0 || s.prec == to) return;
+  s.cur = (s.cur + 1) % 3;
+  s.prec = to;
+}
+
+// ------------------------------------------------------------------ scaling and X_0
+
+// Gershgorin bound of M - mu I (symmetric: row sums = column sums), one wave per column.
+__global__ __launch_bounds__(256) void gersh_kernel(const SubDesc *__restrict__ desc,
+                                                    SubState *__restrict__ st, const char *ws,
+                                                    double mu) {
+  const SubDesc d = desc[blockIdx.y];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  double best = 0.0;
+  for (int c = blockIdx.x * 64 + w * 16; c < blockIdx.x * 64 + w * 16 + 16; ++c) {
+    if (c >= d.n) break;
+    double s = 0.0;
+    for (int r = lane; r < d.n; r += 64) {
+      const double v = M[(int64_t)c * d.npad + r];
+      s += (r == c) ? fabs(v - mu) : fabs(v);
+    }
+    s = wave_sum(s);
+    best = s > best ? s : best;
+  }
+  if (lane == 0 && best > 0.0)
+    atomicMax(&st[blockIdx.y].scale_bits, (unsigned long long)__double_as_longlong(best));
+}
+
+// Pick b_k and l_k, reset the iteration state.  only_fb: restart fallback submatrices.
+__global__ void scale_init_kernel(const SubDesc *__restrict__ desc, SubState *__restrict__ st,
+                                  int K, const double *__restrict__ user_scale,
+                                  const double *__restrict__ user_lower, int prec, int only_fb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (only_fb && !s.fell_back) return;
+  double g = __longlong_as_double((long long)s.scale_bits);
+  if (!(g > 0.0)) g = 1.0;
+  s.scale = (user_scale && !only_fb) ? user_scale[i] : g;
+  s.lower = (user_lower && !only_fb) ? user_lower[i] : 1.0;
+  s.prec = prec;
+  s.cur = 0;
+  s.racc = 0ull;
+  s.active = (s.status == 0);
+  s.extra_left = -1;
+  s.converged = 0;
+  if (!only_fb) { s.iters_lo = 0; s.iters_fb = 0; s.fell_back = 0; s.resid = 0.0f; }
+}
+
+// X_0 = (M - mu I) / b in the submatrix's precision; zero outside n x n.
+template <typename TI>
+__device__ void cast_col(const double *M, TI *X, int n, int ld, int c, double mu, double inv_b) {
+  for (int r = threadIdx.x; r < ld; r += blockDim.x) {
+    double v = 0.0;
+    if (r < n && c < n) v = (M[(int64_t)c * ld + r] - (r == c ? mu : 0.0)) * inv_b;
+    X[(int64_t)c * ld + r] = from_f64<TI>(v);
+  }
+}
+
+__global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ desc,
+                                                   const SubState *__restrict__ st, char *ws,
+                                                   double mu, int only_fb) {
+  const SubDesc d = desc[blockIdx.y];
+  const SubState &s = st[blockIdx.y];
+  const int c = blockIdx.x;
+  if (c >= d.npad || s.status != 0) return;
+  if (only_fb && !s.fell_back) return;
+  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  const double inv_b = 1.0 / s.scale;
+  if (s.prec == P_FP32) cast_col<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+  else if (s.prec == P_FP16)
+    cast_col<_Float16>(M, buf_ptr<_Float16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+  else cast_col<__bf16>(M, buf_ptr<__bf16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+}
+
+// Fallback selection: not converged in a tolerance phase and residual above tol
+// (or non-finite) -> restart from X_0 in FP32 with the Gershgorin scale.
+__global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  s.active = 0;
+  if (s.status != 0) return;
+  if (!s.converged && !(s.resid <= tol)) s.fell_back = 1;
+}
+
+__global__ void fb_finish_kernel(SubState *__restrict__ st, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  s.active = 0;
+  if (s.status == 0 && s.fell_back && !s.converged) s.status = NOLSM_ENOCONV;
+}
+
+__global__ void final_status_kernel(SubState *__restrict__ st, int K, int check_conv) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  s.active = 0;
+  if (check_conv && s.status == 0 && !s.converged) s.status = NOLSM_ENOCONV;
+}
+
+__global__ void clear_scale_kernel(SubState *__restrict__ st, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  st[i].scale_bits = 0ull;
+}
+
+// ------------------------------------------------------------------ host side
+
+static inline int nblk(int K) { return (K + 255) / 256; }
+
+template <typename TI>
+static void launch_ns_gemm(int epi, const Tile *tiles, int ntiles, const SubDesc *desc,
+                           SubState *st, char *ws, int prec, hipStream_t s) {
+  if (epi == EPI_SQUARE)
+    ns_gemm_kernel<TI, EPI_SQUARE><<<ntiles, 256, 0, s>>>(tiles, desc, st, ws, prec);
+  else
+    ns_gemm_kernel<TI, EPI_UPDATE><<<ntiles, 256, 0, s>>>(tiles, desc, st, ws, prec);
+}
+
+static void ns_gemm(int epi, int prec, const Tile *tiles, int ntiles, const SubDesc *desc,
+                    SubState *st, char *ws, hipStream_t s) {
+  if (prec == P_FP32) launch_ns_gemm<float>(epi, tiles, ntiles, desc, st, ws, prec, s);
+  else if (prec == P_FP16) launch_ns_gemm<_Float16>(epi, tiles, ntiles, desc, st, ws, prec, s);
+  else launch_ns_gemm<__bf16>(epi, tiles, ntiles, desc, st, ws, prec, s);
+}
+
+void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s) {
+  final_status_kernel<<<nblk(K), 256, 0, s>>>(st, K, check_conv);
+}
+
+// One phase of the iteration (host loop of launches; no host synchronisation).
+static void timed_gemm(int epi, int prec, const Tile *tiles, int ntiles, const SubDesc *desc,
+                       SubState *st, char *ws, EventLog *log, double flop, hipStream_t s) {
+  const int e = log ? log->begin(T_GEMM, s) : -1;
+  ns_gemm(epi, prec, tiles, ntiles, desc, st, ws, s);
+  if (log && log->on) {
+    log->end(e, s);
+    ++log->n_gemm;
+    log->gemm_flop += flop;
+  }
+}
+
+void launch_phase(const SubDesc *desc, SubState *st, int K, const Tile *tiles, int ntiles,
+                  char *ws, const nolsm_phase &ph, int use_lower, int fallback, EventLog *log,
+                  double flop, hipStream_t s) {
+  PhaseArgs p;
+  p.prec = ph.prec;
+  p.iters = ph.iters;
+  p.extra = ph.extra;
+  p.tol = ph.tol;
+  p.use_lower = use_lower;
+  const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
+  for (int t = 0; t <= last; ++t) {
+    p.t = t;
+    timed_gemm(EPI_SQUARE, ph.prec, tiles, ntiles, desc, st, ws, log, flop, s);
+    ns_check_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, p);
+    timed_gemm(EPI_UPDATE, ph.prec, tiles, ntiles, desc, st, ws, log, flop, s);
+    ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback);
+  }
+  phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
+}
+
+// flop: executed MFMA flops of one GEMM launch over every tile of the plan.
+void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const Tile *tiles,
+                 int ntiles, char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
+                 double flop, hipStream_t s) {
+  clear_scale_kernel<<<nblk(K), 256, 0, s>>>(st, K);
+  gersh_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, mu);
+  scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower,
+                                            sch.phase[0].prec, 0);
+  cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 0);
+  for (int q = 0; q < sch.nphase; ++q) {
+    const nolsm_phase &ph = sch.phase[q];
+    if (q > 0 && ph.prec != sch.phase[q - 1].prec) {
+      convert_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, ph.prec);
+      convert_commit_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
+    }
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, 0);
+    launch_phase(desc, st, K, tiles, ntiles, ws, ph, sch.lower != nullptr, 0, log, flop, s);
+  }
+  if (sch.fallback_iters > 0) {
+    fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol);
+    scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, P_FP32, 1);
+    cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 1);
+    nolsm_phase fb;
+    fb.prec = P_FP32;
+    fb.iters = sch.fallback_iters;
+    fb.tol = 1.0e-3f;
+    fb.extra = 2;
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, P_FP32, 1);
+    launch_phase(desc, st, K, tiles, ntiles, ws, fb, 0, 1, nullptr, 0.0, s);
+    fb_finish_kernel<<<nblk(K), 256, 0, s>>>(st, K);
+  }
+}
+
+}  // namespace nolsm

@@ -1,0 +1,110 @@
+"""Drive the C ABI over a whole instance (device buffers from PyTorch).
+
+The runner owns device copies of H0, S and D, the device pattern, and one plan
+per batch of molecules.  All batches share one workspace (sized for the largest
+batch) and are bound in turn; nothing here computes on the data.
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallback_iters=60,
+                           tol=0.1, cap=40, scale=None, lower=None):
+    """Low-precision bulk, then one FP32 Newton-Schulz step on the own-column panel.
+
+    By default the bulk runs until ||X^2 - I||_F <= tol (every eigenvalue within
+    |1 - x^2| <= 0.1) plus one more iteration; with fixed_iters it runs exactly
+    that many.  Submatrices that miss the tolerance restart in plain FP32.
+    """
+    phase = (prec, fixed_iters, 0.0, 0) if fixed_iters else (prec, cap, tol, 1)
+    return L.schedule([phase], fallback_tol=tol, fallback_iters=fallback_iters,
+                      panel_steps=panel_steps, scale=scale, lower=lower)
+
+
+def plain_fp32_schedule(tol=1e-3, extra=2, cap=100):
+    """Plain FP32 Newton-Schulz to convergence (no panel step, no fallback)."""
+    return L.schedule([("fp32", cap, tol, extra)], fallback_iters=0, panel_steps=0)
+
+
+class Runner:
+    def __init__(self, inst, batch: int | None = None, mols=None, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the NOLSM path runs on the GPU only")
+        L.lib()
+        self.inst = inst
+        self.device = device
+        self.H = torch.from_numpy(inst.H_val).to(device)
+        self.S = torch.from_numpy(inst.S_val).to(device)
+        self.D = torch.zeros_like(self.H)
+        self.hpat = L.HostPattern(inst)
+        self.dpat = L.DevicePattern(inst, device)
+        mols = np.arange(inst.nmol, dtype=np.int32) if mols is None else np.asarray(mols, np.int32)
+        self.mols = mols
+        batch = len(mols) if batch is None else batch
+        self.batches = [mols[i:i + batch] for i in range(0, len(mols), batch)]
+        self.plans = [L.nolsm_plan_create(self.hpat, b) for b in self.batches]
+        need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
+        self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        self.stats = [torch.zeros(len(b) * L.STATS_DTYPE.itemsize, dtype=torch.uint8,
+                                  device=device) for b in self.batches]
+        self.col_traces = torch.zeros(2 * inst.nmol, dtype=torch.float64, device=device)
+        self.out2 = torch.zeros(2, dtype=torch.float64, device=device)
+        self.bound = None
+        if len(self.plans) == 1:
+            self._bind(0)
+
+    def __del__(self):
+        try:
+            for p in getattr(self, "plans", []):
+                L.nolsm_plan_destroy(p)
+        except Exception:     # interpreter shutdown
+            pass
+
+    def _bind(self, i):
+        if self.bound != i:
+            L.nolsm_plan_bind(self.plans[i], self.workspace)
+            self.bound = i
+
+    def run_batch(self, i, mu, sched):
+        self._bind(i)
+        p = self.plans[i]
+        L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
+        L.nolsm_sign_batched(p, mu, sched, self.stats[i])
+        L.nolsm_scatter_density(p, self.dpat, self.D, self.H, self.S, self.stats[i])
+
+    def run(self, mu=None, sched=None, energy=True):
+        mu = self.inst.mu if mu is None else mu
+        for i in range(len(self.plans)):
+            self.run_batch(i, mu, sched)
+        if energy:
+            L.nolsm_energy(self.dpat, self.D, self.H, self.S, self.col_traces, self.out2)
+
+    def check(self):
+        """Status of every batch (after the last run): first failing code or OK."""
+        codes = [L.nolsm_check(p) for p in self.plans[-1:]]
+        return max(codes)
+
+    def stats_host(self, i=None):
+        torch.cuda.synchronize()
+        idx = range(len(self.plans)) if i is None else [i]
+        recs = [np.frombuffer(self.stats[j].cpu().numpy().tobytes(), dtype=L.STATS_DTYPE)
+                for j in idx]
+        return np.concatenate(recs)
+
+    def energy_host(self):
+        torch.cuda.synchronize()
+        e = self.out2.cpu().numpy()
+        return float(e[0]), float(e[1])
+
+    # ------------------------------------------------------------- inspection (tests)
+    def sub_info(self, batch, i):
+        return L.nolsm_plan_query(self.plans[batch], i)
+
+    def ws_view(self, off, count, dtype):
+        """View `count` elements of `dtype` at byte offset `off` of the workspace."""
+        itemsize = torch.tensor([], dtype=dtype).element_size()
+        return self.workspace[off:off + count * itemsize].view(dtype)

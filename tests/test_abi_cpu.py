@@ -1,0 +1,86 @@
+"""The C ABI without a GPU: the library loads, exports what include/nolsm.h
+declares, and the host-side planning validates its arguments."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2205_12182_amd import _lib as L
+from workloads import get_config
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "nolsm.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nolsm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    lib = L.lib()
+    names = declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTED)
+
+
+def test_struct_sizes_match_header():
+    assert ctypes.sizeof(L.SubInfo) == 64
+    assert ctypes.sizeof(L.Phase) == 16
+    assert L.STATS_DTYPE.itemsize == 48
+    assert ctypes.sizeof(L.Pattern) == 8 * 8
+
+
+def test_plan_layout_c1():
+    inst = get_config("c1")
+    hp = L.HostPattern(inst)
+    mols = np.arange(inst.nmol, dtype=np.int32)
+    plan = L.nolsm_plan_create(hp, mols)
+    try:
+        nb = L.nolsm_plan_workspace_bytes(plan)
+        dims = inst.submatrix_dims()
+        # per submatrix: two FP64 n^2, three 4-byte n^2, plus small panels
+        npad = (dims + 63) // 64 * 64
+        assert nb >= int((8 * 2 + 12) * (npad.astype(np.int64) ** 2).sum())
+        # the query API needs a bound plan only for device pointers; sizes are host-side
+    finally:
+        L.nolsm_plan_destroy(plan)
+
+
+def test_plan_rejects_bad_molecule():
+    inst = get_config("c1")
+    hp = L.HostPattern(inst)
+    with pytest.raises(L.NolsmError) as e:
+        L.nolsm_plan_create(hp, np.array([0, 99], dtype=np.int32))
+    assert e.value.code == L.EINVAL
+    assert "out of range" in L.nolsm_last_error()
+
+
+def test_plan_rejects_missing_diagonal():
+    from tests.helpers import instance_from_dense
+    inst = instance_from_dense(np.eye(2), np.eye(2), [1, 1], np.ones((2, 2)))
+    # drop the diagonal block of column 0
+    keep = np.ones(inst.nnzb, dtype=bool)
+    keep[0] = False
+    inst.rowblk = inst.rowblk[keep]
+    inst.valoff = inst.valoff[keep]
+    inst.colptr = np.array([0, 1, 3], dtype=np.int64)
+    hp = L.HostPattern(inst)
+    with pytest.raises(L.NolsmError) as e:
+        L.nolsm_plan_create(hp, np.array([0], dtype=np.int32))
+    assert e.value.code == L.EINVAL
+
+
+def test_sign_rejects_unbound_plan():
+    inst = get_config("c1")
+    plan = L.nolsm_plan_create(L.HostPattern(inst), np.array([0], dtype=np.int32))
+    try:
+        code = L.lib().nolsm_sign_batched(plan, 0.0, None, None, None)
+        assert code == L.EINVAL
+        assert "not bound" in L.nolsm_last_error()
+    finally:
+        L.nolsm_plan_destroy(plan)

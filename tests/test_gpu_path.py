@@ -1,0 +1,193 @@
+"""Parity of the HIP path with the FP64 oracle (needs an MI355X).
+
+Tolerances follow the accuracy target of the method: every stored density element
+within 1e-3 of the oracle, and |E - E_oracle| / N_atoms within 1e-5 Ha.  The
+plain FP32 form is held to tighter bounds that follow from FP32 arithmetic.
+Intermediate buffers (gathered submatrices, L^-1, M) are read back from the
+workspace and checked against exact index arithmetic or FP64 identities.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import nolsm_oracle as O
+from paper_2205_12182_amd import _lib as L
+from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, plain_fp32_schedule
+from workloads import get_config
+
+pytestmark = pytest.mark.gpu
+
+D_TOL = 1e-3          # max |D - D_oracle| over stored elements
+E_TOL = 1e-5          # |E - E_oracle| / N_atoms (Ha)
+
+_cache = {}
+
+
+def oracle(name):
+    if name not in _cache:
+        inst = get_config(name)
+        D, st = O.density_matrix(inst)
+        e, ne = O.traces(inst, D, inst.H_val, inst.S_val)
+        _cache[name] = (inst, D, e, ne, st)
+    return _cache[name]
+
+
+def col_major(t, npad):
+    return t.reshape(npad, npad).T.cpu().numpy()
+
+
+def errors(inst, r, D_ref, e_ref):
+    D = r.D.cpu().numpy()
+    e, ne = r.energy_host()
+    return float(np.abs(D - D_ref).max()), abs(e - e_ref) / inst.natoms, e, ne
+
+
+def print_case(*a):
+    print("[case]", *a, flush=True)
+
+
+def test_gather_bit_exact(gpu_ok):
+    inst = get_config("t_slab")
+    print_case("gather t_slab")
+    r = Runner(inst)
+    L.nolsm_build_submatrices(r.plans[0], r.dpat, r.H, r.S)
+    torch.cuda.synchronize()
+    for i in [0, 1, inst.nmol // 2, inst.nmol - 1]:
+        info = r.sub_info(0, i)
+        npad, n = info.npad, info.n
+        Hk = col_major(r.ws_view(info.off_h, npad * npad, torch.float64), npad)
+        Sk = col_major(r.ws_view(info.off_s, npad * npad, torch.float64), npad)
+        Href, offs = O.gather(inst, inst.H_val, info.mol)
+        Sref, _ = O.gather(inst, inst.S_val, info.mol)
+        assert n == Href.shape[0]
+        assert np.array_equal(Hk[:n, :n], Href)
+        assert np.array_equal(Sk[:n, :n], Sref)
+        assert not Hk[n:, :].any() and not Hk[:, n:].any()
+        assert np.array_equal(Sk[n:, n:], np.eye(npad - n)) and not Sk[n:, :n].any()
+        assert info.own_lo == int(O.own_columns(inst, info.mol, offs)[0])
+
+
+def test_fp64_setup_identities(gpu_ok):
+    """L^-1 S L^-T = I and M = L^-1 H L^-T (exactly symmetric) in FP64."""
+    inst = get_config("t_23")
+    print_case("setup t_23")
+    r = Runner(inst)
+    r.run(sched=plain_fp32_schedule(), energy=False)
+    torch.cuda.synchronize()
+    for i in [0, inst.nmol // 3, inst.nmol - 1]:
+        info = r.sub_info(0, i)
+        npad, n = info.npad, info.n
+        Li = col_major(r.ws_view(info.off_s, npad * npad, torch.float64), npad)[:n, :n]
+        M = col_major(r.ws_view(info.off_h, npad * npad, torch.float64), npad)
+        Hk, _ = O.gather(inst, inst.H_val, info.mol)
+        Sk, _ = O.gather(inst, inst.S_val, info.mol)
+        assert np.array_equal(Li, np.tril(Li))
+        assert np.abs(Li @ Sk @ Li.T - np.eye(n)).max() < 1e-11
+        assert np.array_equal(M, M.T)
+        assert np.abs(M[:n, :n] - Li @ Hk @ Li.T).max() < 1e-11
+        assert not M[n:, :].any()
+
+
+@pytest.mark.parametrize("name", ["c1", "t_tiles", "t_23"])
+def test_parity_plain_fp32(gpu_ok, name):
+    inst, D_ref, e_ref, ne_ref, _ = oracle(name)
+    print_case("plain fp32", name)
+    r = Runner(inst)
+    r.run(sched=plain_fp32_schedule())
+    assert r.check() == L.OK, L.nolsm_last_error()
+    dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+    print_case(name, "plain dD", dmax, "dE/atom", de)
+    assert dmax < 1e-4 and de < 1e-6
+    assert abs(ne - ne_ref) < 1e-3
+    st = r.stats_host()
+    assert np.all(st["status"] == 0) and np.all(st["iters_lo"] > 5)
+
+
+@pytest.mark.parametrize("name", ["c1", "t_tiles", "t_23", "t_slab"])
+def test_parity_mixed_fp16(gpu_ok, name):
+    inst, D_ref, e_ref, ne_ref, _ = oracle(name)
+    print_case("mixed fp16", name)
+    r = Runner(inst)
+    r.run(sched=default_mixed_schedule())
+    assert r.check() == L.OK, L.nolsm_last_error()
+    dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+    st = r.stats_host()
+    print_case(name, "mixed dD", dmax, "dE/atom", de, "fallbacks", int(st["fell_back"].sum()),
+               "resid max", float(st["resid"].max()))
+    assert dmax < D_TOL and de < E_TOL
+
+
+def test_per_column_traces_match_oracle(gpu_ok):
+    inst, D_ref, e_ref, ne_ref, _ = oracle("c1")
+    r = Runner(inst)
+    r.run(sched=plain_fp32_schedule())
+    st = r.stats_host()
+    for i, k in enumerate(r.mols):
+        eh, es = O.column_traces(inst, D_ref, inst.H_val, inst.S_val, int(k))
+        assert abs(st["tr_dh"][i] - eh) < 1e-5
+        assert abs(st["tr_ds"][i] - es) < 1e-5
+    e, ne = r.energy_host()
+    assert abs(math.fsum(st["tr_dh"].tolist()) - e) < 1e-9
+
+
+def test_energy_kernel_against_cpu_sum(gpu_ok):
+    inst = get_config("t_tiles")
+    r = Runner(inst)
+    D = torch.from_numpy(np.random.default_rng(0).standard_normal(inst.nval)).cuda()
+    L.nolsm_energy(r.dpat, D, r.H, r.S, r.col_traces, r.out2)
+    torch.cuda.synchronize()
+    got = r.out2.cpu().numpy()
+    Dh = D.cpu().numpy()
+    want = O.traces(inst, Dh, inst.H_val, inst.S_val)
+    assert abs(got[0] - want[0]) <= 1e-12 * np.abs(Dh * inst.H_val).sum()
+    assert abs(got[1] - want[1]) <= 1e-12 * np.abs(Dh * inst.S_val).sum()
+
+
+def test_deterministic_and_batch_invariant(gpu_ok):
+    inst = get_config("t_tiles")
+    r1 = Runner(inst)
+    r1.run(sched=default_mixed_schedule())
+    D1 = r1.D.clone()
+    E1 = r1.out2.clone()
+    r1.run(sched=default_mixed_schedule())
+    assert torch.equal(D1, r1.D) and torch.equal(E1, r1.out2)
+    r2 = Runner(inst, batch=100)
+    r2.run(sched=default_mixed_schedule())
+    assert torch.equal(D1, r2.D) and torch.equal(E1, r2.out2)
+
+
+def test_not_spd_is_reported(gpu_ok):
+    inst = get_config("c1")
+    S = inst.S_val.copy()
+    # make S_00 negative: every submatrix containing molecule 0 is indefinite
+    S[inst.valoff[inst.colptr[0]]] = -1.0
+    inst.S_val = S
+    r = Runner(inst)
+    r.run(sched=plain_fp32_schedule())
+    code = r.check()
+    assert code == L.ENOTSPD
+    st = r.stats_host()
+    bad = st["status"] == L.ENOTSPD
+    assert bad[0] and bad.sum() < inst.nmol
+
+
+def test_fallback_recovers(gpu_ok):
+    """Too few low-precision iterations: the residual check sends every
+    submatrix to the FP32 continuation, which converges to the oracle."""
+    inst, D_ref, e_ref, _, _ = oracle("c1")
+    r = Runner(inst)
+    r.run(sched=default_mixed_schedule(fixed_iters=3, fallback_iters=80))
+    assert r.check() == L.OK, L.nolsm_last_error()
+    st = r.stats_host()
+    assert np.all(st["fell_back"] == 1) and np.all(st["iters_fb"] > 5)
+    dmax, de, _, _ = errors(inst, r, D_ref, e_ref)
+    assert dmax < 1e-4 and de < 1e-6
+
+
+def test_nonconvergence_is_reported(gpu_ok):
+    inst = get_config("c1")
+    r = Runner(inst)
+    r.run(sched=L.schedule([("fp32", 3, 1e-4, 2)], fallback_iters=0, panel_steps=0))
+    assert r.check() == L.ENOCONV
