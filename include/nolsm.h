@@ -107,6 +107,10 @@ typedef struct {
   int32_t panel_steps;      /* FP32 Newton-Schulz steps on the own-column panel (>= 0) */
   const double *scale;      /* device [K] spectral bounds b_k, or NULL (Gershgorin) */
   const double *lower;      /* device [K] lower bounds l_k in (0, 1], or NULL (a = 1) */
+  const float *lower_log10; /* device [K] log10 of l_k (e.g. a learned prediction), or NULL;
+                               used when lower == NULL: l_k = lower_factor * 10^lower_log10[k],
+                               clamped to [1e-7, 1] */
+  float lower_factor;
 } nolsm_schedule;
 
 /* Per-submatrix record written by nolsm_sign_batched / nolsm_scatter_density. */
@@ -159,6 +163,22 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *plan, const nolsm_pattern *patt
                                      const double *H_val, const double *S_val,
                                      hipStream_t stream);
 
+/* The mu-independent part of step 2 alone: FP64 Cholesky T_k(S) = L L^T, L^-1 and
+ * M_k = L^-1 T_k(H0) L^-T for every planned submatrix.  A following
+ * nolsm_sign_batched (for any mu) reuses it instead of repeating it, until the
+ * next nolsm_build_submatrices; this is how a chemical-potential search shares
+ * one set-up between its mu values, since the argument is M_k - mu I. */
+nolsm_status nolsm_setup_batched(nolsm_plan *plan, hipStream_t stream);
+
+/* Per-submatrix descriptors of A_k = M_k - mu I for the learned schedule
+ * (requires the set-up; runs it if needed).  feat: device [K * NOLSM_NFEAT] FP32,
+ * row k = (log n, members/100, m/32, log b, Gershgorin lower and upper edge / b,
+ * Tr A/(n b), ||A||_F/(sqrt(n) b), std diag/b, min|A_ii|/b, mean and max
+ * off-diagonal row sum / b, fraction of negative diagonal entries,
+ * mean|A_ii|/b, min|A_ii| / (||A||_F/sqrt(n)), 1), with b the Gershgorin bound. */
+#define NOLSM_NFEAT 16
+nolsm_status nolsm_features(nolsm_plan *plan, double mu, float *feat, hipStream_t stream);
+
 /* Step 2 (Eq. 8 via Eq. 6-7): FP64 Cholesky and transform, scaling, the batched
  * sign iteration under `sched` (NULL = plain FP32 Newton-Schulz to convergence),
  * the FP32 fallback and the own-column panel refinement, and the FP64 density
@@ -181,6 +201,33 @@ nolsm_status nolsm_scatter_density(nolsm_plan *plan, const nolsm_pattern *patter
 nolsm_status nolsm_energy(const nolsm_pattern *pattern_dev, int32_t nmol, const double *D_val,
                           const double *H_val, const double *S_val, double *col_traces,
                           double *out2, hipStream_t stream);
+
+/* Learned schedule: a multilayer perceptron NOLSM_NFEAT -> 64 -> 64 -> nout
+ * (SiLU hidden activations, linear output, FP32) with hand-written training
+ * kernels.  Parameters are one FP32 array, in order W1[64][16], b1[64],
+ * W2[64][64], b2[64], W3[nout][64], b3[nout] (row major, y = W x + b).
+ * x: [B][16], y and targets: [B][nout], all row major, device memory.
+ * Reductions over the batch run in a fixed order (bitwise reproducible). */
+#define NOLSM_MLP_HIDDEN 64
+#define NOLSM_MLP_MAXOUT 4
+int64_t nolsm_mlp_param_count(int32_t nout);
+/* Device scratch floats needed by nolsm_mlp_backward / nolsm_mlp_mse for batch B. */
+int64_t nolsm_mlp_scratch_floats(int64_t B, int32_t nout);
+
+/* y = MLP(x).  act (nullable): [B][2*64] pre-activations saved for the backward. */
+nolsm_status nolsm_mlp_forward(const float *params, int32_t nout, const float *x, int64_t B,
+                               float *y, float *act, hipStream_t stream);
+/* grad = d(loss)/d(params) given dy = d(loss)/dy and the saved pre-activations. */
+nolsm_status nolsm_mlp_backward(const float *params, int32_t nout, const float *x,
+                                const float *act, const float *dy, int64_t B, float *grad,
+                                float *scratch, hipStream_t stream);
+/* Mean squared error over the batch: loss[0] = sum (y - t)^2 / (B nout), dy = its gradient. */
+nolsm_status nolsm_mlp_mse(const float *y, const float *t, int64_t B, int32_t nout, float *dy,
+                           float *loss, float *scratch, hipStream_t stream);
+/* One Adam step (Kingma and Ba, 2015) with bias correction; step counts from 1. */
+nolsm_status nolsm_mlp_adam(float *params, const float *grad, float *m, float *v, int64_t P,
+                            float lr, float beta1, float beta2, float eps, int32_t step,
+                            hipStream_t stream);
 
 /* Measurement (not needed for results).  With timing enabled, the plan records a
  * pair of HIP events on `stream` around every launch group below, and

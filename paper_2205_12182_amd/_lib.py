@@ -43,7 +43,8 @@ class Schedule(ctypes.Structure):
     _fields_ = [("nphase", ctypes.c_int32), ("phase", Phase * 4),
                 ("fallback_tol", ctypes.c_float), ("fallback_iters", ctypes.c_int32),
                 ("panel_steps", ctypes.c_int32), ("scale", ctypes.c_void_p),
-                ("lower", ctypes.c_void_p)]
+                ("lower", ctypes.c_void_p), ("lower_log10", ctypes.c_void_p),
+                ("lower_factor", ctypes.c_float)]
 
 
 class SubInfo(ctypes.Structure):
@@ -97,6 +98,15 @@ def lib():
         "nolsm_energy": (i32, [P(Pattern), i32, vp, vp, vp, vp, vp, vp]),
         "nolsm_check": (i32, [vp, vp]),
         "nolsm_plan_set_timing": (i32, [vp, i32]),
+        "nolsm_setup_batched": (i32, [vp, vp]),
+        "nolsm_features": (i32, [vp, dbl, vp, vp]),
+        "nolsm_mlp_param_count": (i64, [i32]),
+        "nolsm_mlp_scratch_floats": (i64, [i64, i32]),
+        "nolsm_mlp_forward": (i32, [vp, i32, vp, i64, vp, vp, vp]),
+        "nolsm_mlp_backward": (i32, [vp, i32, vp, vp, vp, i64, vp, vp, vp]),
+        "nolsm_mlp_mse": (i32, [vp, vp, i64, i32, vp, vp, vp, vp]),
+        "nolsm_mlp_adam": (i32, [vp, vp, vp, vp, i64, ctypes.c_float, ctypes.c_float,
+                                 ctypes.c_float, ctypes.c_float, i32, vp]),
         "nolsm_plan_get_timings": (i32, [vp, P(Timings), i32]),
         "nolsm_last_error": (ctypes.c_char_p, []),
     }
@@ -111,7 +121,12 @@ def lib():
 EXPORTED = ("nolsm_plan_create", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
             "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
             "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_check",
-            "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings")
+            "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings",
+            "nolsm_setup_batched", "nolsm_features", "nolsm_mlp_param_count",
+            "nolsm_mlp_scratch_floats", "nolsm_mlp_forward", "nolsm_mlp_backward",
+            "nolsm_mlp_mse", "nolsm_mlp_adam")
+NFEAT = 16
+MLP_HIDDEN = 64
 
 
 def _ok(code):
@@ -159,8 +174,11 @@ class DevicePattern:
 
 
 def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=None,
-             lower=None):
-    """nolsm_schedule from [(prec, iters, tol, extra), ...]; scale/lower: device tensors."""
+             lower=None, lower_log10=None, lower_factor=1.0):
+    """nolsm_schedule from [(prec, iters, tol, extra), ...].
+
+    scale, lower: device FP64 tensors [K]; lower_log10: device FP32 tensor [K].
+    """
     s = Schedule()
     s.nphase = len(phases)
     for i, (prec, iters, tol, extra) in enumerate(phases):
@@ -171,7 +189,9 @@ def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=N
     s.panel_steps = panel_steps
     s.scale = None if scale is None else scale.data_ptr()
     s.lower = None if lower is None else lower.data_ptr()
-    s._keep = (scale, lower)
+    s.lower_log10 = None if lower_log10 is None else lower_log10.data_ptr()
+    s.lower_factor = lower_factor
+    s._keep = (scale, lower, lower_log10)
     return s
 
 
@@ -229,6 +249,43 @@ def nolsm_energy(dev_pattern: DevicePattern, D_val, H_val, S_val, col_traces, ou
 def nolsm_check(plan, stream=None) -> int:
     code = lib().nolsm_check(plan, _stream(stream))
     return int(code)
+
+
+def nolsm_setup_batched(plan, stream=None):
+    _ok(lib().nolsm_setup_batched(plan, _stream(stream)))
+
+
+def nolsm_features(plan, mu, feat, stream=None):
+    _ok(lib().nolsm_features(plan, float(mu), _ptr(feat), _stream(stream)))
+
+
+def nolsm_mlp_param_count(nout) -> int:
+    return int(lib().nolsm_mlp_param_count(int(nout)))
+
+
+def nolsm_mlp_scratch_floats(B, nout) -> int:
+    return int(lib().nolsm_mlp_scratch_floats(int(B), int(nout)))
+
+
+def nolsm_mlp_forward(params, nout, x, y, act=None, stream=None):
+    _ok(lib().nolsm_mlp_forward(_ptr(params), int(nout), _ptr(x), int(x.shape[0]), _ptr(y),
+                                _ptr(act), _stream(stream)))
+
+
+def nolsm_mlp_backward(params, nout, x, act, dy, grad, scratch, stream=None):
+    _ok(lib().nolsm_mlp_backward(_ptr(params), int(nout), _ptr(x), _ptr(act), _ptr(dy),
+                                 int(x.shape[0]), _ptr(grad), _ptr(scratch), _stream(stream)))
+
+
+def nolsm_mlp_mse(y, t, dy, loss, scratch, stream=None):
+    _ok(lib().nolsm_mlp_mse(_ptr(y), _ptr(t), int(y.shape[0]), int(y.shape[1]), _ptr(dy),
+                            _ptr(loss), _ptr(scratch), _stream(stream)))
+
+
+def nolsm_mlp_adam(params, grad, m, v, lr, beta1, beta2, eps, step, stream=None):
+    _ok(lib().nolsm_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), int(params.numel()),
+                             float(lr), float(beta1), float(beta2), float(eps), int(step),
+                             _stream(stream)))
 
 
 def nolsm_plan_set_timing(plan, enable=True):

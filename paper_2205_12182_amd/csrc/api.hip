@@ -15,8 +15,8 @@ void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mo
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
                    const double *S_val, char *ws, hipStream_t stream);
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws, hipStream_t s);
-void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const Tile *tiles,
-                 int ntiles, char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
+void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
+                 char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
                  double flop, hipStream_t s);
 void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
                             char *ws, int panel_steps, hipStream_t s);
@@ -29,6 +29,8 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
                   hipStream_t s);
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
+void launch_features(const SubDesc *desc, const SubState *st, int K, const char *ws, double mu,
+                     float *feat, hipStream_t s);
 }  // namespace nolsm
 
 using namespace nolsm;
@@ -40,11 +42,13 @@ struct nolsm_plan {
   int32_t max_npad = 0;
   std::vector<SubDesc> desc;
   std::vector<int32_t> mem_mol, mem_loc;
-  std::vector<Tile> tiles;
+  std::vector<Tile> tiles;      // 128 x 128 tiles first (n_small of them), then 256 x 256
+  int32_t n_small = 0;
   size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
   size_t bytes = 0;
   char *ws = nullptr;
   bool bound = false;
+  bool setup_done = false;      // M_k and L^-1 are current (set-up ran after the last gather)
   double gemm_flop = 0.0;       // executed MFMA flops of one sign GEMM launch (all tiles)
   EventLog log;
 };
@@ -128,13 +132,24 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
     p->maxmem = std::max(p->maxmem, d.nmem);
     p->max_npad = std::max(p->max_npad, d.npad);
   }
-  // tiles of the symmetric sign-iteration products: upper triangle, ST x ST
-  for (int i = 0; i < K; ++i) {
-    const int nt = (p->desc[i].npad + ST - 1) / ST;
-    for (int ti = 0; ti < nt; ++ti)
-      for (int tj = ti; tj < nt; ++tj) p->tiles.push_back(Tile{i, ti, tj, 0});
+  // tiles of the symmetric sign-iteration products: upper triangle; small
+  // submatrices use 128 x 128 tiles, the rest 256 x 256.  Executed flops skip the
+  // 32 x 32 blocks that lie entirely in the padding.
+  for (int big = 0; big < 2; ++big) {
+    const int T = big ? 256 : 128;
+    for (int i = 0; i < K; ++i) {
+      const int np = p->desc[i].npad;
+      if ((np >= BIG_TILE_MIN_NPAD) != (big == 1)) continue;
+      const int nt = (np + T - 1) / T;
+      for (int ti = 0; ti < nt; ++ti)
+        for (int tj = ti; tj < nt; ++tj) {
+          p->tiles.push_back(Tile{i, ti, tj, 0});
+          const double rows = std::min(T, np - ti * T), cols = std::min(T, np - tj * T);
+          p->gemm_flop += 2.0 * rows * cols * (double)np;
+        }
+    }
+    if (!big) p->n_small = (int32_t)p->tiles.size();
   }
-  for (const Tile &t : p->tiles) p->gemm_flop += 2.0 * ST * ST * (double)p->desc[t.sub].npad;
   // workspace layout
   off = 0;
   p->off_desc = off;
@@ -237,6 +252,7 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, co
   const int ev = p->log.begin(T_GATHER, s);
   launch_gather(desc, p->K, p->maxmem, mem_mol, mem_loc, pat, H_val, S_val, p->ws, s);
   p->log.end(ev, s);
+  p->setup_done = false;
   return hip_check("nolsm_build_submatrices");
 }
 
@@ -271,12 +287,20 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   }
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
-  int ev = p->log.begin(T_SETUP, s);
-  launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
-  p->log.end(ev, s);
+  int ev;
+  if (!p->setup_done) {
+    ev = p->log.begin(T_SETUP, s);
+    launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
+    p->log.end(ev, s);
+    p->setup_done = true;
+  }
   ev = p->log.begin(T_SIGN, s);
-  launch_sign(desc, st, p->K, p->max_npad, tiles, (int)p->tiles.size(), p->ws, mu, sch, &p->log,
-              p->gemm_flop, s);
+  TileSet ts;
+  ts.t[0] = tiles;
+  ts.n[0] = p->n_small;
+  ts.t[1] = tiles + p->n_small;
+  ts.n[1] = (int)p->tiles.size() - p->n_small;
+  launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, &p->log, p->gemm_flop, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
   p->log.end(ev, s);
@@ -285,6 +309,32 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   p->log.end(ev, s);
   if (stats) launch_stats(desc, st, p->K, stats, s);
   return hip_check("nolsm_sign_batched");
+}
+
+nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
+  if (!p) return fail(NOLSM_EINVAL, "nolsm_setup_batched: null plan");
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_setup_batched: plan not bound");
+  if (p->K == 0) return NOLSM_OK;
+  PLAN_PTRS
+  const int ev = p->log.begin(T_SETUP, s);
+  launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
+  p->log.end(ev, s);
+  p->setup_done = true;
+  return hip_check("nolsm_setup_batched");
+}
+
+nolsm_status nolsm_features(nolsm_plan *p, double mu, float *feat, hipStream_t s) {
+  if (!p || !feat) return fail(NOLSM_EINVAL, "nolsm_features: null argument");
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_features: plan not bound");
+  if (!std::isfinite(mu)) return fail(NOLSM_EINVAL, "nolsm_features: mu not finite");
+  if (p->K == 0) return NOLSM_OK;
+  if (!p->setup_done) {
+    const nolsm_status r = nolsm_setup_batched(p, s);
+    if (r != NOLSM_OK) return r;
+  }
+  PLAN_PTRS
+  launch_features(desc, st, p->K, p->ws, mu, feat, s);
+  return hip_check("nolsm_features");
 }
 
 nolsm_status nolsm_scatter_density(nolsm_plan *p, const nolsm_pattern *pat, double *D_val,

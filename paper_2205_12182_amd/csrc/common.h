@@ -58,6 +58,14 @@ struct SubState {
 
 struct Tile { int32_t sub, ti, tj, pad; };
 
+// Upper-triangle tile lists of the sign-iteration products: t[0] in 128 x 128
+// tiles, t[1] in 256 x 256 tiles (each submatrix appears in exactly one list).
+struct TileSet {
+  const Tile *t[2];
+  int n[2];
+};
+constexpr int BIG_TILE_MIN_NPAD = 768;   // submatrices at least this large use 256 x 256 tiles
+
 // Host-side record of HIP event pairs around launch groups (measurement only).
 enum TimeCat { T_GATHER = 0, T_SETUP, T_SIGN, T_GEMM, T_PANEL, T_SCATTER, T_NCAT };
 

@@ -1,0 +1,87 @@
+// Per-submatrix descriptors of A_k = M_k - mu I for the learned schedule.
+//
+// One workgroup per submatrix; wave w handles columns c = w, w + 4, ... (A is
+// symmetric, so column statistics are row statistics), lanes stride down a
+// column.  Per column: the diagonal d = A_cc and the off-diagonal absolute sum
+// R_c; per submatrix: Gershgorin bound b = max_c (|d| + R_c) and edges
+// min (d - R), max (d + R), Tr A, ||A||_F^2 and diagonal moments.  The fixed
+// thread-to-column assignment and combine order make the result reproducible.
+#include <cfloat>
+
+#include "common.h"
+
+namespace nolsm {
+
+struct ColAcc {
+  double bmax, lo, hi, sd, sd2, sabsd, mind, sR, maxR, neg, f2;
+};
+
+__device__ __forceinline__ void acc_init(ColAcc &a) {
+  a.bmax = 0.0; a.lo = DBL_MAX; a.hi = -DBL_MAX; a.sd = 0.0; a.sd2 = 0.0; a.sabsd = 0.0;
+  a.mind = DBL_MAX; a.sR = 0.0; a.maxR = 0.0; a.neg = 0.0; a.f2 = 0.0;
+}
+
+__device__ __forceinline__ void acc_merge(ColAcc &a, const ColAcc &b) {
+  a.bmax = fmax(a.bmax, b.bmax); a.lo = fmin(a.lo, b.lo); a.hi = fmax(a.hi, b.hi);
+  a.sd += b.sd; a.sd2 += b.sd2; a.sabsd += b.sabsd; a.mind = fmin(a.mind, b.mind);
+  a.sR += b.sR; a.maxR = fmax(a.maxR, b.maxR); a.neg += b.neg; a.f2 += b.f2;
+}
+
+__global__ __launch_bounds__(256) void features_kernel(const SubDesc *__restrict__ desc,
+                                                       const SubState *__restrict__ st,
+                                                       const char *ws, double mu,
+                                                       float *__restrict__ feat) {
+  const SubDesc d = desc[blockIdx.x];
+  float *f = feat + (int64_t)blockIdx.x * NOLSM_NFEAT;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  __shared__ ColAcc part[4];
+  ColAcc a;
+  acc_init(a);
+  for (int c = w; c < d.n; c += 4) {
+    double R = 0.0, f2 = 0.0, diag = 0.0;
+    for (int r = lane; r < d.n; r += 64) {
+      double v = M[(int64_t)c * d.npad + r];
+      if (r == c) { v -= mu; diag = v; } else R += fabs(v);
+      f2 += v * v;
+    }
+    R = wave_sum(R);
+    f2 = wave_sum(f2);
+    diag = wave_sum(diag);                     // only one lane holds it
+    a.bmax = fmax(a.bmax, fabs(diag) + R);
+    a.lo = fmin(a.lo, diag - R);
+    a.hi = fmax(a.hi, diag + R);
+    a.sd += diag; a.sd2 += diag * diag; a.sabsd += fabs(diag);
+    a.mind = fmin(a.mind, fabs(diag));
+    a.sR += R; a.maxR = fmax(a.maxR, R);
+    a.neg += diag < 0.0 ? 1.0 : 0.0;
+    a.f2 += f2;
+  }
+  if (lane == 0) part[w] = a;
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  ColAcc t = part[0];
+  acc_merge(t, part[1]);
+  acc_merge(t, part[2]);
+  acc_merge(t, part[3]);
+  const bool bad = st[blockIdx.x].status != 0 || d.n == 0;
+  const double n = d.n > 0 ? (double)d.n : 1.0;
+  const double b = t.bmax > 0.0 ? t.bmax : 1.0;
+  const double rms = sqrt(t.f2 / n);
+  const double mean = t.sd / n;
+  const double var = fmax(t.sd2 / n - mean * mean, 0.0);
+  float v[NOLSM_NFEAT] = {
+      (float)log(n), (float)(d.nmem / 100.0), (float)(d.m / 32.0), (float)log(b),
+      (float)(t.lo / b), (float)(t.hi / b), (float)(mean / b), (float)(rms / b),
+      (float)(sqrt(var) / b), (float)(t.mind / b), (float)(t.sR / n / b), (float)(t.maxR / b),
+      (float)(t.neg / n), (float)(t.sabsd / n / b), (float)(rms > 0.0 ? t.mind / rms : 0.0),
+      1.0f};
+  for (int i = 0; i < NOLSM_NFEAT; ++i) f[i] = bad ? 0.0f : v[i];
+}
+
+void launch_features(const SubDesc *desc, const SubState *st, int K, const char *ws, double mu,
+                     float *feat, hipStream_t s) {
+  features_kernel<<<K, 256, 0, s>>>(desc, st, ws, mu, feat);
+}
+
+}  // namespace nolsm

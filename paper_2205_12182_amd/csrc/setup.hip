@@ -291,11 +291,23 @@ __global__ __launch_bounds__(256) void trmm_right_kernel(const SubDesc *__restri
   });
 }
 
+// keep_spd = 0: clear every status (a new set-up); 1: clear only NOLSM_ENOCONV
+__global__ void reset_status_kernel(SubState *__restrict__ st, int K, int keep_spd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  if (!keep_spd || st[i].status == NOLSM_ENOCONV) st[i].status = 0;
+}
+
+void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s) {
+  reset_status_kernel<<<(K + 255) / 256, 256, 0, s>>>(st, K, keep_spd);
+}
+
 // ------------------------------------------------------------------ host launcher
 
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
                   hipStream_t s) {
   const int nbmax = max_npad / NB;
+  launch_reset_status(st, K, 0, s);
   for (int jb = 0; jb < nbmax; ++jb) {
     chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
     const int rem = nbmax - jb - 1;

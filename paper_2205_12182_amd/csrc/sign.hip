@@ -18,197 +18,9 @@
 // order inside an LDS stage is permuted identically for A and B, which leaves the
 // contraction unchanged and lets each lane read its whole stage slice as one
 // 32-byte LDS access.
-#include "common.h"
+#include "ns_gemm.h"
 
 namespace nolsm {
-
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef __bf16 b8 __attribute__((ext_vector_type(8)));
-typedef float f16x __attribute__((ext_vector_type(16)));
-
-enum { EPI_SQUARE = 0, EPI_UPDATE = 1 };
-
-constexpr int LROW16 = 5;          // LDS row: 80 bytes = 5 x uint4 (64 data + 16 pad)
-constexpr int STAGE_U4 = ST * LROW16;
-
-template <typename TI> struct KStage;
-template <> struct KStage<_Float16> { static constexpr int KS = 32; };
-template <> struct KStage<__bf16> { static constexpr int KS = 32; };
-template <> struct KStage<float> { static constexpr int KS = 16; };
-
-template <typename TI>
-__device__ __forceinline__ void mfma_stage(const uint4 a[2][2], const uint4 b[2][2],
-                                           f16x acc[2][2]);
-
-template <>
-__device__ __forceinline__ void mfma_stage<_Float16>(const uint4 a[2][2], const uint4 b[2][2],
-                                                     f16x acc[2][2]) {
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
-        h8 av = __builtin_bit_cast(h8, a[bm][s]);
-        h8 bv = __builtin_bit_cast(h8, b[bn][s]);
-        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, acc[bm][bn], 0, 0, 0);
-      }
-}
-
-template <>
-__device__ __forceinline__ void mfma_stage<__bf16>(const uint4 a[2][2], const uint4 b[2][2],
-                                                   f16x acc[2][2]) {
-#pragma unroll
-  for (int s = 0; s < 2; ++s)
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
-        b8 av = __builtin_bit_cast(b8, a[bm][s]);
-        b8 bv = __builtin_bit_cast(b8, b[bn][s]);
-        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, acc[bm][bn], 0, 0, 0);
-      }
-}
-
-template <>
-__device__ __forceinline__ void mfma_stage<float>(const uint4 a[2][2], const uint4 b[2][2],
-                                                  f16x acc[2][2]) {
-#pragma unroll
-  for (int s = 0; s < 8; ++s)
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn) {
-        const uint4 &av = a[bm][s >> 2];
-        const uint4 &bv = b[bn][s >> 2];
-        const unsigned ai = (s & 3) == 0 ? av.x : (s & 3) == 1 ? av.y : (s & 3) == 2 ? av.z : av.w;
-        const unsigned bi = (s & 3) == 0 ? bv.x : (s & 3) == 1 ? bv.y : (s & 3) == 2 ? bv.z : bv.w;
-        acc[bm][bn] = __builtin_amdgcn_mfma_f32_32x32x2f32(__builtin_bit_cast(float, ai),
-                                                          __builtin_bit_cast(float, bi),
-                                                          acc[bm][bn], 0, 0, 0);
-      }
-}
-
-template <typename TI>
-__device__ __forceinline__ TI *buf_ptr(char *ws, const SubDesc &d, int q) {
-  return reinterpret_cast<TI *>(ws + d.off_lo + (int64_t)q * 4 * d.npad * d.npad);
-}
-
-// 256 threads, tile ST x ST = 128 x 128, wave w owns rows (w >> 1) * 64, cols (w & 1) * 64.
-template <typename TI, int EPI>
-__global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ tiles,
-                                                      const SubDesc *__restrict__ desc,
-                                                      SubState *__restrict__ st, char *ws,
-                                                      int prec) {
-  constexpr int KS = KStage<TI>::KS;
-  const Tile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
-  SubState &S = st[t.sub];
-  if (!S.active || S.prec != prec) return;
-  const SubDesc d = desc[t.sub];
-  const int ld = d.npad, n = d.n;
-  const int cur = S.cur;
-  const TI *A = buf_ptr<TI>(ws, d, cur);
-  const TI *B = (EPI == EPI_SQUARE) ? A : buf_ptr<TI>(ws, d, (cur + 1) % 3);
-  TI *Out = buf_ptr<TI>(ws, d, (cur + (EPI == EPI_SQUARE ? 1 : 2)) % 3);
-  const int i0 = t.ti * ST, j0 = t.tj * ST;
-
-  __shared__ uint4 sA[2][STAGE_U4];
-  __shared__ uint4 sB[2][STAGE_U4];
-  __shared__ float red[4];
-
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  const int lrow = tid >> 1, lpart = tid & 1;           // loader: row, 32-byte half
-  const bool arow_ok = (i0 + lrow) < ld, brow_ok = (j0 + lrow) < ld;
-  const uint4 *gA = reinterpret_cast<const uint4 *>(A + (int64_t)(i0 + lrow) * ld) + lpart * 2;
-  const uint4 *gB = reinterpret_cast<const uint4 *>(B + (int64_t)(j0 + lrow) * ld) + lpart * 2;
-  const int kstep_u4 = KS * (int)sizeof(TI) / 16;       // uint4 per row per stage (= 4)
-  const uint4 zero = {0u, 0u, 0u, 0u};
-
-  f16x acc[2][2];
-#pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[bm][bn][q] = 0.0f;
-
-  const int nk = ld / KS;
-  uint4 ra0, ra1, rb0, rb1;
-  ra0 = arow_ok ? gA[0] : zero;
-  ra1 = arow_ok ? gA[1] : zero;
-  rb0 = brow_ok ? gB[0] : zero;
-  rb1 = brow_ok ? gB[1] : zero;
-  sA[0][lrow * LROW16 + lpart * 2] = ra0;
-  sA[0][lrow * LROW16 + lpart * 2 + 1] = ra1;
-  sB[0][lrow * LROW16 + lpart * 2] = rb0;
-  sB[0][lrow * LROW16 + lpart * 2 + 1] = rb1;
-  __syncthreads();
-
-  const int h = lane >> 5, l32 = lane & 31;
-  for (int kt = 0; kt < nk; ++kt) {
-    const int buf = kt & 1;
-    if (kt + 1 < nk) {
-      const int o = (kt + 1) * kstep_u4;
-      ra0 = arow_ok ? gA[o] : zero;
-      ra1 = arow_ok ? gA[o + 1] : zero;
-      rb0 = brow_ok ? gB[o] : zero;
-      rb1 = brow_ok ? gB[o + 1] : zero;
-    }
-    uint4 af[2][2], bf[2][2];
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm) {
-      const int r = wm + bm * 32 + l32;
-      af[bm][0] = sA[buf][r * LROW16 + h * 2];
-      af[bm][1] = sA[buf][r * LROW16 + h * 2 + 1];
-    }
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn) {
-      const int r = wn + bn * 32 + l32;
-      bf[bn][0] = sB[buf][r * LROW16 + h * 2];
-      bf[bn][1] = sB[buf][r * LROW16 + h * 2 + 1];
-    }
-    mfma_stage<TI>(af, bf, acc);
-    if (kt + 1 < nk) {
-      sA[buf ^ 1][lrow * LROW16 + lpart * 2] = ra0;
-      sA[buf ^ 1][lrow * LROW16 + lpart * 2 + 1] = ra1;
-      sB[buf ^ 1][lrow * LROW16 + lpart * 2] = rb0;
-      sB[buf ^ 1][lrow * LROW16 + lpart * 2 + 1] = rb1;
-    }
-    __syncthreads();
-  }
-
-  // epilogue: element (r, c) of block (bm, bn), register q:
-  //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32
-  const float c1 = S.c1, c3 = S.c3;
-  float rs = 0.0f;
-#pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int gr = i0 + wm + 32 * bm + 8 * (q >> 2) + 4 * h + (q & 3);
-        const int gc = j0 + wn + 32 * bn + l32;
-        if (gr > gc || gc >= ld) continue;
-        float v = acc[bm][bn][q];
-        if (EPI == EPI_SQUARE) {
-          if (gc < n) {
-            const float e = v - (gr == gc ? 1.0f : 0.0f);
-            rs += (gr == gc ? 1.0f : 2.0f) * e * e;
-          }
-        } else {
-          v = c3 * v + c1 * to_f32<TI>(A[(int64_t)gc * ld + gr]);
-        }
-        const TI o = from_f32<TI>(v);
-        Out[(int64_t)gc * ld + gr] = o;
-        Out[(int64_t)gr * ld + gc] = o;
-      }
-  if (EPI == EPI_SQUARE) {
-    const float tot = block_sum256(rs, red);
-    if (tid == 0) atomicAdd(&S.racc, resid_fixed(tot));
-  }
-}
 
 // ------------------------------------------------------------------ per-submatrix control
 
@@ -358,7 +170,9 @@ __global__ __launch_bounds__(256) void gersh_kernel(const SubDesc *__restrict__ 
 // Pick b_k and l_k, reset the iteration state.  only_fb: restart fallback submatrices.
 __global__ void scale_init_kernel(const SubDesc *__restrict__ desc, SubState *__restrict__ st,
                                   int K, const double *__restrict__ user_scale,
-                                  const double *__restrict__ user_lower, int prec, int only_fb) {
+                                  const double *__restrict__ user_lower,
+                                  const float *__restrict__ lower_log10, float lower_factor,
+                                  int prec, int only_fb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -366,7 +180,12 @@ __global__ void scale_init_kernel(const SubDesc *__restrict__ desc, SubState *__
   double g = __longlong_as_double((long long)s.scale_bits);
   if (!(g > 0.0)) g = 1.0;
   s.scale = (user_scale && !only_fb) ? user_scale[i] : g;
-  s.lower = (user_lower && !only_fb) ? user_lower[i] : 1.0;
+  double l = 1.0;
+  if (!only_fb) {
+    if (user_lower) l = user_lower[i];
+    else if (lower_log10) l = (double)lower_factor * pow(10.0, (double)lower_log10[i]);
+  }
+  s.lower = l < 1.0e-7 ? 1.0e-7 : (l > 1.0 ? 1.0 : l);
   s.prec = prec;
   s.cur = 0;
   s.racc = 0ull;
@@ -439,20 +258,29 @@ __global__ void clear_scale_kernel(SubState *__restrict__ st, int K) {
 
 static inline int nblk(int K) { return (K + 255) / 256; }
 
-template <typename TI>
-static void launch_ns_gemm(int epi, const Tile *tiles, int ntiles, const SubDesc *desc,
-                           SubState *st, char *ws, int prec, hipStream_t s) {
-  if (epi == EPI_SQUARE)
-    ns_gemm_kernel<TI, EPI_SQUARE><<<ntiles, 256, 0, s>>>(tiles, desc, st, ws, prec);
-  else
-    ns_gemm_kernel<TI, EPI_UPDATE><<<ntiles, 256, 0, s>>>(tiles, desc, st, ws, prec);
+void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s);
+
+template <typename TI, int EPI>
+static void launch_ns_gemm_t(const TileSet &ts, const SubDesc *desc, SubState *st, char *ws,
+                             int prec, hipStream_t s) {
+  if (ts.n[0] > 0)
+    ns_gemm_kernel<TI, EPI, 2><<<ts.n[0], 256, 0, s>>>(ts.t[0], desc, st, ws, prec);
+  if (ts.n[1] > 0)
+    ns_gemm_kernel<TI, EPI, 4><<<ts.n[1], 256, 0, s>>>(ts.t[1], desc, st, ws, prec);
 }
 
-static void ns_gemm(int epi, int prec, const Tile *tiles, int ntiles, const SubDesc *desc,
-                    SubState *st, char *ws, hipStream_t s) {
-  if (prec == P_FP32) launch_ns_gemm<float>(epi, tiles, ntiles, desc, st, ws, prec, s);
-  else if (prec == P_FP16) launch_ns_gemm<_Float16>(epi, tiles, ntiles, desc, st, ws, prec, s);
-  else launch_ns_gemm<__bf16>(epi, tiles, ntiles, desc, st, ws, prec, s);
+template <typename TI>
+static void launch_ns_gemm(int epi, const TileSet &ts, const SubDesc *desc, SubState *st,
+                           char *ws, int prec, hipStream_t s) {
+  if (epi == EPI_SQUARE) launch_ns_gemm_t<TI, EPI_SQUARE>(ts, desc, st, ws, prec, s);
+  else launch_ns_gemm_t<TI, EPI_UPDATE>(ts, desc, st, ws, prec, s);
+}
+
+static void ns_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc, SubState *st,
+                    char *ws, hipStream_t s) {
+  if (prec == P_FP32) launch_ns_gemm<float>(epi, ts, desc, st, ws, prec, s);
+  else if (prec == P_FP16) launch_ns_gemm<_Float16>(epi, ts, desc, st, ws, prec, s);
+  else launch_ns_gemm<__bf16>(epi, ts, desc, st, ws, prec, s);
 }
 
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s) {
@@ -460,10 +288,10 @@ void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s) {
 }
 
 // One phase of the iteration (host loop of launches; no host synchronisation).
-static void timed_gemm(int epi, int prec, const Tile *tiles, int ntiles, const SubDesc *desc,
+static void timed_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc,
                        SubState *st, char *ws, EventLog *log, double flop, hipStream_t s) {
   const int e = log ? log->begin(T_GEMM, s) : -1;
-  ns_gemm(epi, prec, tiles, ntiles, desc, st, ws, s);
+  ns_gemm(epi, prec, ts, desc, st, ws, s);
   if (log && log->on) {
     log->end(e, s);
     ++log->n_gemm;
@@ -471,7 +299,7 @@ static void timed_gemm(int epi, int prec, const Tile *tiles, int ntiles, const S
   }
 }
 
-void launch_phase(const SubDesc *desc, SubState *st, int K, const Tile *tiles, int ntiles,
+void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
                   char *ws, const nolsm_phase &ph, int use_lower, int fallback, EventLog *log,
                   double flop, hipStream_t s) {
   PhaseArgs p;
@@ -483,22 +311,23 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const Tile *tiles, i
   const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
   for (int t = 0; t <= last; ++t) {
     p.t = t;
-    timed_gemm(EPI_SQUARE, ph.prec, tiles, ntiles, desc, st, ws, log, flop, s);
+    timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, s);
     ns_check_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, p);
-    timed_gemm(EPI_UPDATE, ph.prec, tiles, ntiles, desc, st, ws, log, flop, s);
+    timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, s);
     ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback);
   }
   phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
 }
 
 // flop: executed MFMA flops of one GEMM launch over every tile of the plan.
-void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const Tile *tiles,
-                 int ntiles, char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
+void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
+                 char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
                  double flop, hipStream_t s) {
+  launch_reset_status(st, K, 1, s);
   clear_scale_kernel<<<nblk(K), 256, 0, s>>>(st, K);
   gersh_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, mu);
-  scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower,
-                                            sch.phase[0].prec, 0);
+  scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower, sch.lower_log10,
+                                            sch.lower_factor, sch.phase[0].prec, 0);
   cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 0);
   for (int q = 0; q < sch.nphase; ++q) {
     const nolsm_phase &ph = sch.phase[q];
@@ -507,11 +336,13 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
       convert_commit_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
     }
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, 0);
-    launch_phase(desc, st, K, tiles, ntiles, ws, ph, sch.lower != nullptr, 0, log, flop, s);
+    const int scaled = (sch.lower != nullptr || sch.lower_log10 != nullptr) ? 1 : 0;
+    launch_phase(desc, st, K, ts, ws, ph, scaled, 0, log, flop, s);
   }
   if (sch.fallback_iters > 0) {
     fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol);
-    scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, P_FP32, 1);
+    scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, nullptr, 0.0f,
+                                              P_FP32, 1);
     cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 1);
     nolsm_phase fb;
     fb.prec = P_FP32;
@@ -519,7 +350,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     fb.tol = 1.0e-3f;
     fb.extra = 2;
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, P_FP32, 1);
-    launch_phase(desc, st, K, tiles, ntiles, ws, fb, 0, 1, nullptr, 0.0, s);
+    launch_phase(desc, st, K, ts, ws, fb, 0, 1, nullptr, 0.0, s);
     fb_finish_kernel<<<nblk(K), 256, 0, s>>>(st, K);
   }
 }

@@ -54,6 +54,7 @@ class Runner:
         self.col_traces = torch.zeros(2 * inst.nmol, dtype=torch.float64, device=device)
         self.out2 = torch.zeros(2, dtype=torch.float64, device=device)
         self.bound = None
+        self._feat = None
         if len(self.plans) == 1:
             self._bind(0)
 
@@ -69,17 +70,35 @@ class Runner:
             L.nolsm_plan_bind(self.plans[i], self.workspace)
             self.bound = i
 
-    def run_batch(self, i, mu, sched):
+    def run_batch(self, i, mu, sched, predictor=None, lower_factor=0.5):
+        """Gather, sign iteration and write-back for batch i.
+
+        predictor: a learn.ScheduleMLP; its prediction of log10 l_k from the batch's
+        nolsm_features drives the scaled iteration (lower_factor is the safety
+        factor applied to l_k).
+        """
         self._bind(i)
         p = self.plans[i]
         L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
+        if predictor is not None:
+            K = len(self.batches[i])
+            if self._feat is None or self._feat.shape[0] < K:
+                self._feat = torch.empty(K, L.NFEAT, device=self.device)
+            feat = self._feat[:K]
+            L.nolsm_features(p, mu, feat)
+            y = predictor.predict(feat)
+            s2 = L.Schedule.from_buffer_copy(sched)
+            s2.lower_log10 = y.data_ptr()
+            s2.lower_factor = lower_factor
+            s2._keep = (getattr(sched, "_keep", None), y)
+            sched = s2
         L.nolsm_sign_batched(p, mu, sched, self.stats[i])
         L.nolsm_scatter_density(p, self.dpat, self.D, self.H, self.S, self.stats[i])
 
-    def run(self, mu=None, sched=None, energy=True):
+    def run(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5):
         mu = self.inst.mu if mu is None else mu
         for i in range(len(self.plans)):
-            self.run_batch(i, mu, sched)
+            self.run_batch(i, mu, sched, predictor, lower_factor)
         if energy:
             L.nolsm_energy(self.dpat, self.D, self.H, self.S, self.col_traces, self.out2)
 

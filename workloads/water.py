@@ -40,8 +40,10 @@ Construction (the instance recipe):
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -215,13 +217,17 @@ def _fill_values(inst_dims, blk_off, rowblk, colblk, valoff, sites, fn_site, ons
     rc2 = r_cut * r_cut if math.isfinite(r_cut) else np.inf
     two_s2 = 2.0 * SIGMA * SIGMA
     shapes = np.stack([inst_dims[rowblk], inst_dims[colblk]], axis=1)
+    jobs = []
     for dI, dJ in np.unique(shapes, axis=0):
         sel = np.nonzero((shapes[:, 0] == dI) & (shapes[:, 1] == dJ))[0]
+        step = max(1, (1 << 21) // int(dI * dJ))
+        jobs += [(int(dI), int(dJ), sel[a:a + step]) for a in range(0, sel.size, step)]
+
+    def work(job):
+        dI, dJ, t = job
         fr = np.arange(dI)
         fc = np.arange(dJ)
-        step = max(1, (1 << 23) // int(dI * dJ))
-        for a in range(0, sel.size, step):
-            t = sel[a:a + step]
+        if True:
             Ib, Jb = rowblk[t], colblk[t]
             sI = fn_site[Ib][:, :dI]                      # [nt, dI] site of each row fn
             sJ = fn_site[Jb][:, :dJ]
@@ -244,6 +250,15 @@ def _fill_values(inst_dims, blk_off, rowblk, colblk, valoff, sites, fn_site, ons
             dst = (valoff[t][:, None] + np.arange(sz)[None, :]).ravel()
             S_val[dst] = np.transpose(s0, (0, 2, 1)).reshape(-1)
             H_val[dst] = np.transpose(h, (0, 2, 1)).reshape(-1)
+
+    # chunks write disjoint slices; NumPy releases the GIL inside the array work
+    workers = min(16, os.cpu_count() or 1)
+    if workers > 1 and len(jobs) > 1:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            list(ex.map(work, jobs))
+    else:
+        for j in jobs:
+            work(j)
 
 
 def block_matvec(inst_like, val: np.ndarray, x: np.ndarray) -> np.ndarray:
