@@ -181,6 +181,8 @@ def main():
         cpu = cpu_baseline(inst, O, args.cpu_sample, flops / K)
         log(f"cpu baseline: {json.dumps(cpu)}")
 
+    # executed MFMA flops of the active tiles (device counter) over the time of every
+    # GEMM launch in the timed region (HIP events around each launch)
     achieved = exec_flop_step / (gemm_ms * 1e-3) / 1e12
     n_gemm = tm["n_gemm"] / args.steps
     out = {
@@ -219,7 +221,8 @@ def main():
                      "kernel": "ns_gemm_kernel (symmetric upper-tile FP16 product)",
                      "launches_per_step": n_gemm,
                      "avg_launch_ms": round(gemm_ms / max(n_gemm, 1), 4),
-                     "executed_flop_per_launch": exec_flop_step / max(n_gemm, 1)},
+                     "executed_flop_per_step": exec_flop_step,
+                     "note": "achieved = executed MFMA flops of active tiles / summed launch time"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -242,9 +242,12 @@ typedef struct {
   double ms_panel;       /* panel refinement and density columns                     */
   double ms_scatter;     /* nolsm_scatter_density                                    */
   int64_t n_gemm;        /* GEMM launches timed                                      */
-  double gemm_flop;      /* executed MFMA flops of those launches (all tiles of the plan) */
+  double gemm_flop;      /* executed MFMA flops of the tiles that were active (device count) */
 } nolsm_timings;
 
+/* gemm_flop comes from a counter in the first 256 bytes of the workspace, shared by
+ * every plan bound to that workspace: it accumulates over all of them and is
+ * cleared by a call with reset != 0 (it starts undefined). */
 nolsm_status nolsm_plan_set_timing(nolsm_plan *plan, int enable);
 nolsm_status nolsm_plan_get_timings(nolsm_plan *plan, nolsm_timings *out /*host*/, int reset);
 

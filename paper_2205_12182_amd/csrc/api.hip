@@ -42,9 +42,10 @@ struct nolsm_plan {
   int32_t max_npad = 0;
   std::vector<SubDesc> desc;
   std::vector<int32_t> mem_mol, mem_loc;
-  std::vector<Tile> tiles;      // 128 x 128 tiles first (n_small of them), then 256 x 256
-  int32_t n_small = 0;
+  std::vector<Tile> tiles;      // the three tile lists of TileSet, back to back
+  int32_t list_end[3] = {0, 0, 0};
   size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
+  size_t off_counter = 0;       // unsigned long long: executed sign-GEMM work (FLOP_UNIT)
   size_t bytes = 0;
   char *ws = nullptr;
   bool bound = false;
@@ -135,23 +136,27 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
   // tiles of the symmetric sign-iteration products: upper triangle; small
   // submatrices use 128 x 128 tiles, the rest 256 x 256.  Executed flops skip the
   // 32 x 32 blocks that lie entirely in the padding.
-  for (int big = 0; big < 2; ++big) {
-    const int T = big ? 256 : 128;
+  // list 0: small submatrices, 128 tiles; list 1: large, 256 tiles; list 2: large, 128 tiles
+  for (int list = 0; list < 3; ++list) {
+    const int T = list == 1 ? 256 : 128;
     for (int i = 0; i < K; ++i) {
       const int np = p->desc[i].npad;
-      if ((np >= BIG_TILE_MIN_NPAD) != (big == 1)) continue;
+      if ((np >= BIG_TILE_MIN_NPAD) != (list != 0)) continue;
       const int nt = (np + T - 1) / T;
       for (int ti = 0; ti < nt; ++ti)
         for (int tj = ti; tj < nt; ++tj) {
           p->tiles.push_back(Tile{i, ti, tj, 0});
           const double rows = std::min(T, np - ti * T), cols = std::min(T, np - tj * T);
-          p->gemm_flop += 2.0 * rows * cols * (double)np;
+          if (list < 2) p->gemm_flop += 2.0 * rows * cols * (double)np;
         }
     }
-    if (!big) p->n_small = (int32_t)p->tiles.size();
+    p->list_end[list] = (int32_t)p->tiles.size();
   }
-  // workspace layout
+  // workspace layout: a fixed header shared by every plan bound to the workspace
+  // (the executed-flop counter), then this plan's tables and per-submatrix arenas
   off = 0;
+  p->off_counter = off;
+  off = align256(off + sizeof(unsigned long long));
   p->off_desc = off;
   off = align256(off + sizeof(SubDesc) * (size_t)K);
   p->off_mem_mol = off;
@@ -296,10 +301,12 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   }
   ev = p->log.begin(T_SIGN, s);
   TileSet ts;
-  ts.t[0] = tiles;
-  ts.n[0] = p->n_small;
-  ts.t[1] = tiles + p->n_small;
-  ts.n[1] = (int)p->tiles.size() - p->n_small;
+  for (int l = 0; l < 3; ++l) {
+    const int b = l ? p->list_end[l - 1] : 0;
+    ts.t[l] = tiles + b;
+    ts.n[l] = p->list_end[l] - b;
+  }
+  ts.flop_units = reinterpret_cast<unsigned long long *>(p->ws + p->off_counter);
   launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, &p->log, p->gemm_flop, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
@@ -370,6 +377,13 @@ nolsm_status nolsm_plan_set_timing(nolsm_plan *p, int enable) {
 nolsm_status nolsm_plan_get_timings(nolsm_plan *p, nolsm_timings *out, int reset) {
   if (!p || !out) return fail(NOLSM_EINVAL, "nolsm_plan_get_timings: null argument");
   p->log.collect();
+  unsigned long long units = 0;
+  if (p->bound && p->K > 0) {
+    hipError_t e = hipMemcpy(&units, p->ws + p->off_counter, sizeof units, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && reset) e = hipMemset(p->ws + p->off_counter, 0, sizeof units);
+    if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_plan_get_timings: %s", hipGetErrorString(e));
+  }
+  p->log.gemm_flop = (double)units * FLOP_UNIT;
   out->ms_gather = p->log.ms[T_GATHER];
   out->ms_setup = p->log.ms[T_SETUP];
   out->ms_sign = p->log.ms[T_SIGN];

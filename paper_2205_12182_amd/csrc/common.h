@@ -58,12 +58,18 @@ struct SubState {
 
 struct Tile { int32_t sub, ti, tj, pad; };
 
-// Upper-triangle tile lists of the sign-iteration products: t[0] in 128 x 128
-// tiles, t[1] in 256 x 256 tiles (each submatrix appears in exactly one list).
+// Upper-triangle tile lists of the sign-iteration products: t[0] holds the small
+// submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 256 tiles (FP16 and
+// BF16), t[2] the large ones in 128 x 128 tiles (FP32, whose 256 x 256 tile does
+// not fit the register file).
 struct TileSet {
-  const Tile *t[2];
-  int n[2];
+  const Tile *t[3];
+  int n[3];
+  unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
 };
+// 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad
+// are multiples of these, so the count is exact)
+constexpr double FLOP_UNIT = 131072.0;
 constexpr int BIG_TILE_MIN_NPAD = 768;   // submatrices at least this large use 256 x 256 tiles
 
 // Host-side record of HIP event pairs around launch groups (measurement only).

@@ -66,6 +66,17 @@ template <> struct Mfma<float> {
   }
 };
 
+// LDS for the epilogue's column-major staging tile: TILE columns of TILE + 8
+// elements, in one round or (if that exceeds EPI_LDS_BYTES) two rounds of half
+// the columns.
+constexpr int EPI_LDS_BYTES = 135168;
+template <typename TI, int TILE>
+__host__ __device__ constexpr int smem_epi_u4() {
+  return ((int)sizeof(TI) * TILE * (TILE + 8) > EPI_LDS_BYTES ? (int)sizeof(TI) * TILE * (TILE + 8) / 2
+                                                               : (int)sizeof(TI) * TILE * (TILE + 8)) /
+         16;
+}
+
 template <typename TI>
 __device__ __forceinline__ TI *buf_ptr(char *ws, const SubDesc &d, int q) {
   return reinterpret_cast<TI *>(ws + d.off_lo + (int64_t)q * 4 * d.npad * d.npad);
@@ -173,46 +184,104 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
     __syncthreads();
   }
 
-  // epilogue: element (r, c) of block (bm, bn), register q:
-  //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32
-  // Only r <= c is stored, to both (r, c) and (c, r): the result is exactly symmetric.
-  float rs = 0.0f;
+  // Epilogue.  Element (r, c) of block (bm, bn), register q:
+  //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32.
+  // SQUARE turns X^2 into Z = c1 I + c3 X^2 (the residual is taken from X^2), so
+  // UPDATE is the plain product X' = X Z.  Only elements with r <= c (global) are
+  // kept, and each is stored to (r, c) and (c, r), so the result is exactly
+  // symmetric.  The (c, r) stores go straight from registers (the 32 lanes of a
+  // register hold 32 consecutive rows of column r of the output); the (r, c)
+  // stores are staged in LDS, column major, and leave as 16-byte chunks.
+  constexpr int CH = 16 / (int)sizeof(TI);                 // elements per 16-byte chunk
+  constexpr int LSTR = TILE + 8;                            // LDS column stride (elements)
+  constexpr int ROUNDS = ((int)sizeof(TI) * TILE * LSTR > EPI_LDS_BYTES) ? 2 : 1;
+  constexpr int RCOLS = TILE / ROUNDS;
+  TI *sT = reinterpret_cast<TI *>(sA);
+  const bool diag_tile = (i0 == j0);
+  // keep the row stride in a vector register so that the per-row store offsets
+  // are formed with vector arithmetic instead of occupying scalar registers
+  int ldv = ld;
+  asm volatile("" : "+v"(ldv));
+  float rs = 0.0f;     // diagonal tiles: weighted sum; other tiles: plain sum (weight 2 later)
 #pragma unroll
-  for (int bm = 0; bm < BMB; ++bm)
+  for (int rd = 0; rd < ROUNDS; ++rd) {
+    if (ROUNDS == 1 || wn / RCOLS == rd) {
 #pragma unroll
-    for (int bn = 0; bn < BMB; ++bn) {
-      if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
+      for (int bm = 0; bm < BMB; ++bm)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int gr = i0 + wm + 32 * bm + 8 * (q >> 2) + 4 * h + (q & 3);
-        const int gc = j0 + wn + 32 * bn + l32;
-        if (gr > gc) continue;
-        float v = acc[bm][bn][q];
-        if (EPI == EPI_SQUARE) {
-          if (gc < n) {
-            const float e = v - (gr == gc ? 1.0f : 0.0f);
-            rs += (gr == gc ? 1.0f : 2.0f) * e * e;
+        for (int bn = 0; bn < BMB; ++bn) {
+          if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
+          const int c = wn + 32 * bn + l32, gc = j0 + c;
+          TI *mir = Out + (int64_t)(i0 + wm + 32 * bm + 4 * h) * ldv + gc;
+#pragma unroll
+          for (int g = 0; g < 4; ++g) {
+            const int r0 = wm + 32 * bm + 8 * g + 4 * h;
+            TI o[4];
+            if (!diag_tile) {          // every element has r < c (global)
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                float v = acc[bm][bn][4 * g + e];
+                if (EPI == EPI_SQUARE) {
+                  rs += v * v;
+                  v = c3 * v;
+                }
+                o[e] = from_f32<TI>(v);
+                mir[(int64_t)(8 * g + e) * ldv] = o[e];
+              }
+            } else {
+#pragma unroll
+              for (int e = 0; e < 4; ++e) {
+                const int gr = i0 + r0 + e;
+                float v = acc[bm][bn][4 * g + e];
+                if (EPI == EPI_SQUARE) {
+                  const bool diag = gr == gc && gc < n;
+                  if (gr <= gc && gc < n) {
+                    const float df = v - (diag ? 1.0f : 0.0f);
+                    rs += (diag ? 1.0f : 2.0f) * df * df;
+                  }
+                  v = c3 * v + (diag ? c1 : 0.0f);
+                }
+                o[e] = from_f32<TI>(v);
+                if (gr < gc) mir[(int64_t)(8 * g + e) * ldv] = o[e];
+              }
+            }
+            TI *dst = sT + (c - rd * RCOLS) * LSTR + r0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) dst[e] = o[e];
           }
-        } else {
-          v = c3 * v + c1 * to_f32<TI>(A[(int64_t)gc * ld + gr]);
         }
-        const TI o = from_f32<TI>(v);
-        Out[(int64_t)gc * ld + gr] = o;
-        Out[(int64_t)gr * ld + gc] = o;
+    }
+    __syncthreads();
+    constexpr int CPC = TILE / CH;                           // chunks per column
+    for (int idx = tid; idx < RCOLS * CPC; idx += 256) {
+      const int cl = idx / CPC, row = (idx % CPC) * CH;
+      const int gc = j0 + rd * RCOLS + cl, gr0 = i0 + row;
+      if (PARTIAL && (gc >= ld || gr0 >= ld)) continue;
+      const TI *src = sT + cl * LSTR + row;
+      TI *dst = Out + (int64_t)gc * ld + gr0;
+      if (gr0 + CH - 1 <= gc) {
+        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+      } else if (gr0 <= gc) {
+        for (int e = 0; e < CH && gr0 + e <= gc; ++e) dst[e] = src[e];
       }
     }
+    if (ROUNDS > 1) __syncthreads();
+  }
   if (EPI == EPI_SQUARE) {
-    const float tot = block_sum256(rs, red);
+    // off-diagonal tiles count each element twice (it stands for (r, c) and (c, r));
+    // their padding rows and columns are zero and contribute nothing
+    const float tot = block_sum256(diag_tile ? rs : 2.0f * rs, red);
     if (tid == 0) atomicAdd(racc, resid_fixed(tot));
   }
 }
 
-// SQUARE: Y = X X (+ residual);  UPDATE: X' = c1 X + c3 X Y.
+// SQUARE: Z = c1 I + c3 X X (+ residual of X X);  UPDATE: X' = X Z.
 template <typename TI, int EPI, int BMB>
 __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ tiles,
                                                       const SubDesc *__restrict__ desc,
                                                       SubState *__restrict__ st, char *ws,
-                                                      int prec) {
+                                                      int prec,
+                                                      unsigned long long *__restrict__ flop_units) {
   constexpr int TILE = 64 * BMB;
   const Tile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
   SubState &S = st[t.sub];
@@ -224,9 +293,17 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
   const TI *B = (EPI == EPI_SQUARE) ? A : buf_ptr<TI>(ws, d, (cur + 1) % 3);
   TI *Out = buf_ptr<TI>(ws, d, (cur + (EPI == EPI_SQUARE ? 1 : 2)) % 3);
   const int i0 = t.ti * TILE, j0 = t.tj * TILE;
-  __shared__ uint4 sA[2 * TILE * LROW16];
-  __shared__ uint4 sB[2 * TILE * LROW16];
+  if (threadIdx.x == 0) {
+    const int rows = (ld - i0 < TILE ? ld - i0 : TILE), cols = (ld - j0 < TILE ? ld - j0 : TILE);
+    atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
+  }
+  // one LDS union: the main loop's two double-buffered operand rings, then the
+  // epilogue's staging tile
+  constexpr int MAIN_U4 = 4 * TILE * LROW16;
+  constexpr int EPI_U4 = smem_epi_u4<TI, TILE>();
+  __shared__ uint4 smem[MAIN_U4 > EPI_U4 ? MAIN_U4 : EPI_U4];
   __shared__ float red[4];
+  uint4 *sA = smem, *sB = smem + 2 * TILE * LROW16;
   if (i0 + TILE <= ld && j0 + TILE <= ld)
     ns_gemm_body<TI, EPI, BMB, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, sA, sB, red,
                                       &S.racc);

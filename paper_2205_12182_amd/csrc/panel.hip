@@ -34,50 +34,76 @@ __global__ __launch_bounds__(256) void panel_v_kernel(const SubDesc *__restrict_
   }
 }
 
-// O[:, c] = alpha * X P[:, c] + beta * Q[:, c] for 64 rows per workgroup.
-// X is symmetric, so X(i, k) is read as column i: contiguous in k for the LDS tile.
+// O[:, c] = alpha * X P[:, c] + beta * Q[:, c], PANEL_ROWS rows per workgroup.
+// Bound by reading X once (n^2 elements per product).  X is symmetric, so rows of
+// X are read as columns: 16-byte loads contiguous in k.  The X tile is staged in
+// LDS as FP32 [k][row] and each thread accumulates a 4 x 4 block (4 rows, 4 of
+// the m <= 32 columns), i.e. two 16-byte LDS reads per 16 FMAs.
+constexpr int PANEL_ROWS = 128;
+constexpr int PANEL_K = 64;
+
+template <typename TI>
+__device__ __forceinline__ void panel_load_x(const TI *__restrict__ X, int ld, int i0, int k0,
+                                             float (*sX)[PANEL_ROWS + 4]) {
+  constexpr int EPU = 16 / (int)sizeof(TI);                  // elements per 16-byte load
+  constexpr int CPR = PANEL_K / EPU;                         // loads per row
+  constexpr int PER_T = PANEL_ROWS * CPR / 256;
+#pragma unroll
+  for (int q = 0; q < PER_T; ++q) {
+    const int idx = threadIdx.x + 256 * q, row = idx / CPR, kc = idx % CPR;
+    uint4 v = {0u, 0u, 0u, 0u};
+    if (i0 + row < ld)
+      v = *reinterpret_cast<const uint4 *>(X + (int64_t)(i0 + row) * ld + k0 + kc * EPU);
+    const TI *e = reinterpret_cast<const TI *>(&v);
+#pragma unroll
+    for (int j = 0; j < EPU; ++j) sX[kc * EPU + j][row] = to_f32<TI>(e[j]);
+  }
+}
+
 template <typename TI>
 __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict__ P,
                                const float *__restrict__ Q, float *__restrict__ O, int ld, int m,
-                               float alpha, float beta) {
-  __shared__ float sX[64][65];      // sX[i][k]
-  __shared__ float sP[64][33];      // sP[k][c], m <= 32
+                               float alpha, float beta, float (*sX)[PANEL_ROWS + 4],
+                               float (*sP)[MAXM]) {
   const int tid = threadIdx.x;
-  const int i0 = blockIdx.x * 64;
-  const int il = tid & 63, cg = tid >> 6;       // row, column group (c = cg + 4 q)
-  float acc[8];
+  const int i0 = blockIdx.x * PANEL_ROWS;
+  const int ti = tid & 31, tc = tid >> 5;         // rows 4 ti .. 4 ti + 3, columns 4 tc .. + 3
+  float acc[4][4];
 #pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0f;
-  for (int k0 = 0; k0 < ld; k0 += 64) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int kk = e & 63, ii = e >> 6;
-      sX[ii][kk] = (i0 + ii < ld) ? to_f32<TI>(X[(int64_t)(i0 + ii) * ld + k0 + kk]) : 0.0f;
-    }
-    for (int e = tid; e < 64 * m; e += 256) {
-      const int kk = e & 63, c = e >> 6;
-      sP[kk][c] = P[(int64_t)c * ld + k0 + kk];
+  for (int r = 0; r < 4; ++r)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
+  for (int k0 = 0; k0 < ld; k0 += PANEL_K) {
+    panel_load_x<TI>(X, ld, i0, k0, sX);
+    for (int e = tid; e < PANEL_K * MAXM; e += 256) {
+      const int kk = e % PANEL_K, c = e / PANEL_K;
+      sP[kk][c] = c < m ? P[(int64_t)c * ld + k0 + kk] : 0.0f;
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 64; ++kk) {
-      const float x = sX[il][kk];
+#pragma unroll 8
+    for (int kk = 0; kk < PANEL_K; ++kk) {
+      const float4 x = *reinterpret_cast<const float4 *>(&sX[kk][4 * ti]);
+      const float4 p = *reinterpret_cast<const float4 *>(&sP[kk][4 * tc]);
+      const float xs[4] = {x.x, x.y, x.z, x.w}, ps[4] = {p.x, p.y, p.z, p.w};
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = cg + 4 * q;
-        if (c < m) acc[q] += x * sP[kk][c];
-      }
+      for (int r = 0; r < 4; ++r)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[r][c] += xs[r] * ps[c];
     }
     __syncthreads();
   }
-  const int i = i0 + il;
-  if (i >= ld) return;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int c = cg + 4 * q;
-    if (c >= m) continue;
-    float v = alpha * acc[q];
-    if (beta != 0.0f) v += beta * Q[(int64_t)c * ld + i];
-    O[(int64_t)c * ld + i] = v;
+  for (int c = 0; c < 4; ++c) {
+    const int col = 4 * tc + c;
+    if (col >= m) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * ti + r;
+      if (i >= ld) continue;
+      float v = alpha * acc[r][c];
+      if (beta != 0.0f) v += beta * Q[(int64_t)col * ld + i];
+      O[(int64_t)col * ld + i] = v;
+    }
   }
 }
 
@@ -87,19 +113,22 @@ __global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restric
                                                         float beta) {
   const SubDesc d = desc[blockIdx.y];
   const SubState &s = st[blockIdx.y];
-  if (s.status != 0 || blockIdx.x * 64 >= (unsigned)d.npad) return;
+  if (s.status != 0 || blockIdx.x * PANEL_ROWS >= (unsigned)d.npad) return;
+  __shared__ float sX[PANEL_K][PANEL_ROWS + 4];
+  __shared__ float sP[PANEL_K][MAXM];
   const float *P = panel_ptr(ws, d, qp);
   const float *Q = panel_ptr(ws, d, qq);
   float *O = panel_ptr(ws, d, qo);
   const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
   if (s.prec == P_FP32)
-    panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, d.m, alpha, beta);
+    panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, d.m, alpha, beta,
+                          sX, sP);
   else if (s.prec == P_FP16)
     panel_mul_body<_Float16>(reinterpret_cast<const _Float16 *>(xb), P, Q, O, d.npad, d.m, alpha,
-                             beta);
+                             beta, sX, sP);
   else
     panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, d.m, alpha,
-                           beta);
+                           beta, sX, sP);
 }
 
 // Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c])
@@ -280,7 +309,7 @@ struct PanelCtx {
   }
   void release(int q) { used &= ~(1u << q); }
   int apply(int steps, int qin) {
-    const dim3 grid(max_npad / 64, K);
+    const dim3 grid((max_npad + PANEL_ROWS - 1) / PANEL_ROWS, K);
     if (steps == 0) {
       const int qo = alloc();
       panel_mul_kernel<<<grid, 256, 0, s>>>(desc, st, ws, qin, qin, qo, 1.0f, 0.0f);

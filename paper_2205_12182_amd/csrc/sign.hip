@@ -8,16 +8,18 @@
 // per-submatrix state word decides which submatrices still iterate.
 //
 // Per iteration:
-//   ns_gemm<SQUARE>   Y = X X                and sum (Y - I)^2 for the residual
-//   ns_check          residual, stop rule, coefficients (c1, c3)
-//   ns_gemm<UPDATE>   X' = c1 X + c3 X Y     (Newton-Schulz: c1 = 3/2, c3 = -1/2)
-//   ns_advance        X <- X', advance the spectral lower bound
+//   ns_gemm<SQUARE>   Z = c1 I + c3 X X      and sum (X X - I)^2 for the residual
+//   ns_check          residual, stop rule
+//   ns_gemm<UPDATE>   X' = X Z               (Newton-Schulz: c1 = 3/2, c3 = -1/2)
+//   ns_advance        X <- X', advance the spectral lower bound, next (c1, c3)
 //
 // Operands: both factors are read as column panels (A(m, k) = X(k, m) by
 // symmetry), so every lane's MFMA fragment is a run of consecutive k.  The k
 // order inside an LDS stage is permuted identically for A and B, which leaves the
 // contraction unchanged and lets each lane read its whole stage slice as one
 // 32-byte LDS access.
+#include <type_traits>
+
 #include "ns_gemm.h"
 
 namespace nolsm {
@@ -69,7 +71,6 @@ __global__ void ns_check_kernel(const SubDesc *__restrict__ desc, SubState *__re
     go = p.t < p.iters;
   }
   if (!go) s.active = 0;
-  else set_coeffs(s, p.use_lower);
 }
 
 __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, int use_lower,
@@ -86,11 +87,13 @@ __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, in
     double ln = 0.5 * a * l * (3.0 - a * a * l * l);
     s.lower = ln > 1.0 ? 1.0 : ln;
   }
+  set_coeffs(s, use_lower);       // for the next iteration's Z = c1 I + c3 X^2
 }
 
 // Start a phase: every healthy submatrix iterates; convert the current iterate
 // if the phase changes precision (handled by convert_kernel on the host side).
-__global__ void phase_start_kernel(SubState *__restrict__ st, int K, int prec, int only_fb) {
+__global__ void phase_start_kernel(SubState *__restrict__ st, int K, int use_lower,
+                                   int only_fb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -100,7 +103,7 @@ __global__ void phase_start_kernel(SubState *__restrict__ st, int K, int prec, i
   s.extra_left = -1;
   s.converged = 0;
   s.racc = 0ull;
-  (void)prec;
+  set_coeffs(s, use_lower);
 }
 
 __global__ void phase_end_kernel(SubState *__restrict__ st, int K) {
@@ -264,9 +267,16 @@ template <typename TI, int EPI>
 static void launch_ns_gemm_t(const TileSet &ts, const SubDesc *desc, SubState *st, char *ws,
                              int prec, hipStream_t s) {
   if (ts.n[0] > 0)
-    ns_gemm_kernel<TI, EPI, 2><<<ts.n[0], 256, 0, s>>>(ts.t[0], desc, st, ws, prec);
-  if (ts.n[1] > 0)
-    ns_gemm_kernel<TI, EPI, 4><<<ts.n[1], 256, 0, s>>>(ts.t[1], desc, st, ws, prec);
+    ns_gemm_kernel<TI, EPI, 2><<<ts.n[0], 256, 0, s>>>(ts.t[0], desc, st, ws, prec,
+                                                       ts.flop_units);
+  if (std::is_same<TI, float>::value) {
+    if (ts.n[2] > 0)
+      ns_gemm_kernel<TI, EPI, 2><<<ts.n[2], 256, 0, s>>>(ts.t[2], desc, st, ws, prec,
+                                                         ts.flop_units);
+  } else if (ts.n[1] > 0) {
+    ns_gemm_kernel<TI, EPI, (std::is_same<TI, float>::value ? 2 : 4)>
+        <<<ts.n[1], 256, 0, s>>>(ts.t[1], desc, st, ws, prec, ts.flop_units);
+  }
 }
 
 template <typename TI>
@@ -290,12 +300,12 @@ void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s) {
 // One phase of the iteration (host loop of launches; no host synchronisation).
 static void timed_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc,
                        SubState *st, char *ws, EventLog *log, double flop, hipStream_t s) {
+  (void)flop;
   const int e = log ? log->begin(T_GEMM, s) : -1;
   ns_gemm(epi, prec, ts, desc, st, ws, s);
   if (log && log->on) {
     log->end(e, s);
     ++log->n_gemm;
-    log->gemm_flop += flop;
   }
 }
 
@@ -335,8 +345,8 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
       convert_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, ph.prec);
       convert_commit_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
     }
-    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, 0);
     const int scaled = (sch.lower != nullptr || sch.lower_log10 != nullptr) ? 1 : 0;
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0);
     launch_phase(desc, st, K, ts, ws, ph, scaled, 0, log, flop, s);
   }
   if (sch.fallback_iters > 0) {
@@ -349,7 +359,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     fb.iters = sch.fallback_iters;
     fb.tol = 1.0e-3f;
     fb.extra = 2;
-    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, P_FP32, 1);
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, 0, 1);
     launch_phase(desc, st, K, ts, ws, fb, 0, 1, nullptr, 0.0, s);
     fb_finish_kernel<<<nblk(K), 256, 0, s>>>(st, K);
   }

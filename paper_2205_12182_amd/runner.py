@@ -13,7 +13,7 @@ from . import _lib as L
 
 
 def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallback_iters=60,
-                           tol=0.1, cap=40, scale=None, lower=None):
+                           tol=0.1, cap=30, scale=None, lower=None):
     """Low-precision bulk, then one FP32 Newton-Schulz step on the own-column panel.
 
     By default the bulk runs until ||X^2 - I||_F <= tol (every eigenvalue within
