@@ -6,12 +6,17 @@
 // the workgroup tile is (64 BMB)^2: 128 x 128 (BMB = 2) or 256 x 256 (BMB = 4).
 //
 // Both factors are read as column panels (A(m, k) = X(k, m) by symmetry): in
-// every LDS stage, row r of a panel is 64 contiguous bytes (32 FP16 or 16 FP32 k
-// values), staged through registers into a double-buffered LDS ring with 80-byte
-// rows (16 bytes of padding keep the fragment reads free of bank conflicts).
-// Lane half h of an MFMA fragment takes the 32 bytes at offset 32 h of its row;
-// the k order inside a stage is therefore permuted identically for A and B,
-// which leaves the contraction unchanged.
+// every stage, row r of a panel is 64 contiguous bytes (32 FP16 or 16 FP32 k
+// values, four 16-byte chunks).  Stages travel from memory straight into LDS
+// (buffer loads with the LDS destination) through a ring of four slots, three
+// stages ahead of the MFMAs; each slot is its own LDS array so that the
+// compiler's wait-count tracking sees which slot a fragment read depends on,
+// and the waits before each barrier are partial (only the stage about to be
+// consumed).  Within a row the chunks are stored XOR-permuted by
+// ((r >> 1) ^ (r >> 3)) & 3, which makes the 16-byte fragment reads free of
+// bank conflicts without padding.  Lane half h of an MFMA fragment takes chunks
+// 2 h and 2 h + 1 of its row; the k order inside a stage is therefore permuted
+// identically for A and B, which leaves the contraction unchanged.
 //
 // Tiles on the ragged edge (n padded to 64, tiles of 128/256) skip the 32 x 32
 // blocks that lie entirely in the padding.
@@ -26,7 +31,7 @@ typedef float f16x __attribute__((ext_vector_type(16)));
 
 enum { EPI_SQUARE = 0, EPI_UPDATE = 1 };
 
-constexpr int LROW16 = 5;          // LDS row: 80 bytes = 5 x uint4 (64 data + 16 pad)
+constexpr int NSLOT = 4;           // LDS ring slots (stages in flight: NSLOT - 1)
 // Word 3 of a raw (stride 0) buffer resource on CDNA: 32-bit data format, no
 // swizzle; offsets at or beyond num_records return zero.
 constexpr int BUFFER_RSRC_WORD3 = 0x00020000;
@@ -66,31 +71,34 @@ template <> struct Mfma<float> {
   }
 };
 
-// LDS for the epilogue's column-major staging tile: TILE columns of TILE + 8
-// elements, in one round or (if that exceeds EPI_LDS_BYTES) two rounds of half
-// the columns.
-constexpr int EPI_LDS_BYTES = 135168;
-template <typename TI, int TILE>
-__host__ __device__ constexpr int smem_epi_u4() {
-  return ((int)sizeof(TI) * TILE * (TILE + 8) > EPI_LDS_BYTES ? (int)sizeof(TI) * TILE * (TILE + 8) / 2
-                                                               : (int)sizeof(TI) * TILE * (TILE + 8)) /
-         16;
-}
+// One ring slot: the stage's A rows, then its B rows, 4 uint4 per row.
+template <int BMB> __host__ __device__ constexpr int slot_u4() { return 2 * 64 * BMB * 4; }
 
 template <typename TI>
 __device__ __forceinline__ TI *buf_ptr(char *ws, const SubDesc &d, int q) {
   return reinterpret_cast<TI *>(ws + d.off_lo + (int64_t)q * 4 * d.npad * d.npad);
 }
 
+__device__ __forceinline__ int chunk_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+
+// s_waitcnt immediate: wait until at most `vm` vector-memory operations are
+// outstanding and every LDS operation has completed (expcnt left alone).
+__host__ __device__ constexpr int wait_vm_lgkm0(int vm) {
+  return (vm & 0xF) | ((vm >> 4) << 14) | (0x7 << 4);
+}
+
+#define NS_LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
+
 template <typename TI, int EPI, int BMB, bool PARTIAL>
 __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI *__restrict__ B,
                                              TI *__restrict__ Out, int ld, int n, int i0, int j0,
-                                             float c1, float c3, uint4 *sA, uint4 *sB,
-                                             float *red, unsigned long long *racc) {
+                                             float c1, float c3, uint4 *s0, uint4 *s1, uint4 *s2,
+                                             uint4 *s3, float *red, unsigned long long *racc) {
   constexpr int TILE = 64 * BMB;
-  constexpr int SU4 = TILE * LROW16;             // uint4 per operand per LDS stage
-  constexpr int U4T = TILE * 4 / 256;            // uint4 loaded per thread per operand
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  constexpr int LPS = TILE / 64;                 // loads per wave per operand per stage
+  constexpr int BOFF = TILE * 4;                 // B rows start here within a slot (uint4)
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = (w >> 1) * 32 * BMB, wn = (w & 1) * 32 * BMB;
   const int h = lane >> 5, l32 = lane & 31;
   const int nk = ld / KStage<TI>::KS;
@@ -105,33 +113,38 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   }
 
   // Panel loads go through buffer resources whose size is the npad x npad matrix:
-  // rows past npad (ragged edge tiles) are out of range and read as zero.
+  // rows past npad (ragged edge tiles) are out of range and read as zero.  Stages
+  // past the last one are issued (every wave issues the same number of loads, so
+  // the partial waits count right) against zero-size resources: nothing is read
+  // and their slots are never consumed.
   const int nrec = ld * ld * (int)sizeof(TI);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(A), (short)0, nrec, BUFFER_RSRC_WORD3);
   const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(B), (short)0, nrec, BUFFER_RSRC_WORD3);
-  unsigned voA[U4T], voB[U4T];
-  int lofs[U4T];
+  const __amdgpu_buffer_rsrc_t rA0 = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<TI *>(A), (short)0, 0, BUFFER_RSRC_WORD3);
+  const __amdgpu_buffer_rsrc_t rB0 = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<TI *>(B), (short)0, 0, BUFFER_RSRC_WORD3);
+
+  // A wave's load q fills rows 16 (4 q + w) .. + 15 of a panel: lane L writes the
+  // 16 bytes at LDS offset 16 L of that 1 KiB block, i.e. row 16 (4 q + w) + L / 4,
+  // slot L % 4, and so fetches chunk (L % 4) ^ chunk_swz(row) of the row.
+  unsigned voA[LPS], voB[LPS];
 #pragma unroll
-  for (int q = 0; q < U4T; ++q) {
-    const int row = (tid >> 2) + 64 * q, ch = tid & 3;
+  for (int q = 0; q < LPS; ++q) {
+    const int row = 16 * (4 * q + w) + (lane >> 2);
+    const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
     voA[q] = (unsigned)((i0 + row) * ld) * (unsigned)sizeof(TI) + 16u * ch;
     voB[q] = (unsigned)((j0 + row) * ld) * (unsigned)sizeof(TI) + 16u * ch;
-    lofs[q] = row * LROW16 + ch;
   }
-  uint4 ra[U4T], rb[U4T];
-#pragma unroll
-  for (int q = 0; q < U4T; ++q) {
-    ra[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rA, voA[q], 0, 0));
-    rb[q] = __builtin_bit_cast(uint4, __builtin_amdgcn_raw_buffer_load_b128(rB, voB[q], 0, 0));
-  }
-#pragma unroll
-  for (int q = 0; q < U4T; ++q) {
-    sA[lofs[q]] = ra[q];
-    sB[lofs[q]] = rb[q];
-  }
-  __syncthreads();
+  // Fragment reads: lane (h, l32) takes chunks 2 h and 2 h + 1 of rows
+  // wm + 32 b + l32 (A) and wn + 32 b + l32 (B); the chunk permutation of those
+  // rows depends on l32 only.
+  const int z = chunk_swz(l32);
+  const int fa0 = (wm + l32) * 4 + ((2 * h) ^ z), fa1 = (wm + l32) * 4 + ((2 * h + 1) ^ z);
+  const int fb0 = BOFF + (wn + l32) * 4 + ((2 * h) ^ z),
+            fb1 = BOFF + (wn + l32) * 4 + ((2 * h + 1) ^ z);
 
   f16x acc[BMB][BMB];
 #pragma unroll
@@ -141,31 +154,44 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[bm][bn][q] = 0.0f;
 
-  for (int kt = 0; kt < nk; ++kt) {
-    const int cur = (kt & 1) * SU4, nxt = SU4 - cur;
-    if (kt + 1 < nk) {
-      const unsigned o = 64u * (unsigned)(kt + 1);
+  struct Frag { uint4 a[BMB][2], b[BMB][2]; };
+  auto issue = [&](uint4 *slot, int kt) {
+    const bool live = kt < nk;
+    const __amdgpu_buffer_rsrc_t ra = live ? rA : rA0, rb = live ? rB : rB0;
+    const int so = live ? 64 * kt : 0;
 #pragma unroll
-      for (int q = 0; q < U4T; ++q) {
-        ra[q] = __builtin_bit_cast(uint4,
-                                   __builtin_amdgcn_raw_buffer_load_b128(rA, voA[q] + o, 0, 0));
-        rb[q] = __builtin_bit_cast(uint4,
-                                   __builtin_amdgcn_raw_buffer_load_b128(rB, voB[q] + o, 0, 0));
-      }
+    for (int q = 0; q < LPS; ++q) {
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, NS_LDS_PTR(slot + (4 * q + w) * 64), 16,
+                                               voA[q], so, 0, 0);
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, NS_LDS_PTR(slot + BOFF + (4 * q + w) * 64),
+                                               16, voB[q], so, 0, 0);
     }
-    uint4 af[BMB][2], bf[BMB][2];
+  };
+  auto read = [&](const uint4 *slot, Frag &f) {
 #pragma unroll
-    for (int bm = 0; bm < BMB; ++bm) {
-      const int r = (wm + bm * 32 + l32) * LROW16 + h * 2 + cur;
-      af[bm][0] = sA[r];
-      af[bm][1] = sA[r + 1];
+    for (int b = 0; b < BMB; ++b) {
+      f.a[b][0] = slot[fa0 + 128 * b];
+      f.a[b][1] = slot[fa1 + 128 * b];
+      f.b[b][0] = slot[fb0 + 128 * b];
+      f.b[b][1] = slot[fb1 + 128 * b];
     }
-#pragma unroll
-    for (int bn = 0; bn < BMB; ++bn) {
-      const int r = (wn + bn * 32 + l32) * LROW16 + h * 2 + cur;
-      bf[bn][0] = sB[r];
-      bf[bn][1] = sB[r + 1];
-    }
+  };
+  // Stage kt is in registers (f).  Wait for stage kt + 1 to land (stages kt + 2
+  // and kt + 3 may stay in flight) and for this wave's reads of stage kt; after
+  // the barrier every wave is done with slot kt % NSLOT, which takes stage
+  // kt + NSLOT.  Stage kt + 1 is read into g while the MFMAs consume f.
+  // Instruction order inside a step (scheduling groups): one MFMA, two fragment
+  // reads and one LDS-destination load, repeated until the reads and loads are
+  // issued, then the remaining MFMAs; nothing moves across step boundaries.
+  constexpr int NDS = 4 * BMB, NVM = 2 * LPS, NMF = BMB * BMB * Mfma<TI>::STEPS;
+  static_assert(NDS / 2 >= NVM && NMF >= NDS / 2, "step interleave");
+  auto step = [&](const uint4 *next, uint4 *refill, int kt, Frag &f, Frag &g) {
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NSLOT - 2) * 2 * LPS));
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_sched_barrier(0);
+    issue(refill, kt + NSLOT);
+    read(next, g);
 #pragma unroll
     for (int s = 0; s < Mfma<TI>::STEPS; ++s)
 #pragma unroll
@@ -173,16 +199,41 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
 #pragma unroll
         for (int bn = 0; bn < BMB; ++bn)
           if (!PARTIAL || (bm < nvr && bn < nvc))
-            acc[bm][bn] = Mfma<TI>::op(af[bm], bf[bn], s, acc[bm][bn]);
-    if (kt + 1 < nk) {
+            acc[bm][bn] = Mfma<TI>::op(f.a[bm], f.b[bn], s, acc[bm][bn]);
+    if (!PARTIAL) {
 #pragma unroll
-      for (int q = 0; q < U4T; ++q) {
-        sA[nxt + lofs[q]] = ra[q];
-        sB[nxt + lofs[q]] = rb[q];
+      for (int j = 0; j < NDS / 2; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);    // LDS read
+        if (j < NVM) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // memory load
       }
+      __builtin_amdgcn_sched_group_barrier(0x008, NMF - NDS / 2, 0);
     }
-    __syncthreads();
+    __builtin_amdgcn_sched_barrier(0);
+  };
+
+  Frag f, g;
+  issue(s0, 0);
+  issue(s1, 1);
+  issue(s2, 2);
+  issue(s3, 3);
+  __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NSLOT - 1) * 2 * LPS));
+  __builtin_amdgcn_s_barrier();
+  read(s0, f);
+  int kt = 0;
+  for (; kt + NSLOT <= nk; kt += NSLOT) {
+    step(s1, s0, kt, f, g);
+    step(s2, s1, kt + 1, g, f);
+    step(s3, s2, kt + 2, f, g);
+    step(s0, s3, kt + 3, g, f);
   }
+  const int rem = nk - kt;
+  if (rem > 0) step(s1, s0, kt, f, g);
+  if (rem > 1) step(s2, s1, kt + 1, g, f);
+  if (rem > 2) step(s3, s2, kt + 2, f, g);
+  // drain the trailing (empty) loads before the slots are reused for staging
+  __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
+  __builtin_amdgcn_s_barrier();
 
   // Epilogue.  Element (r, c) of block (bm, bn), register q:
   //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32.
@@ -191,12 +242,16 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   // kept, and each is stored to (r, c) and (c, r), so the result is exactly
   // symmetric.  The (c, r) stores go straight from registers (the 32 lanes of a
   // register hold 32 consecutive rows of column r of the output); the (r, c)
-  // stores are staged in LDS, column major, and leave as 16-byte chunks.
+  // stores are staged in LDS, column major, and leave as 16-byte chunks.  The
+  // staging tile is split by columns into four quarters, one per ring slot;
+  // within a column the 16-byte chunk k sits at k ^ (column & 15).
   constexpr int CH = 16 / (int)sizeof(TI);                 // elements per 16-byte chunk
-  constexpr int LSTR = TILE + 8;                            // LDS column stride (elements)
-  constexpr int ROUNDS = ((int)sizeof(TI) * TILE * LSTR > EPI_LDS_BYTES) ? 2 : 1;
-  constexpr int RCOLS = TILE / ROUNDS;
-  TI *sT = reinterpret_cast<TI *>(sA);
+  constexpr int QC = TILE / 4;                              // columns per quarter
+  static_assert(QC * TILE * (int)sizeof(TI) <= slot_u4<BMB>() * 16, "staging quarter");
+  static_assert(TILE / CH >= 16, "chunk permutation needs 16 chunks per column");
+  auto quarter = [&](int qi) -> TI * {
+    return reinterpret_cast<TI *>(qi == 0 ? s0 : qi == 1 ? s1 : qi == 2 ? s2 : s3);
+  };
   const bool diag_tile = (i0 == j0);
   // keep the row stride in a vector register so that the per-row store offsets
   // are formed with vector arithmetic instead of occupying scalar registers
@@ -204,68 +259,67 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   asm volatile("" : "+v"(ldv));
   float rs = 0.0f;     // diagonal tiles: weighted sum; other tiles: plain sum (weight 2 later)
 #pragma unroll
-  for (int rd = 0; rd < ROUNDS; ++rd) {
-    if (ROUNDS == 1 || wn / RCOLS == rd) {
+  for (int bm = 0; bm < BMB; ++bm)
 #pragma unroll
-      for (int bm = 0; bm < BMB; ++bm)
+    for (int bn = 0; bn < BMB; ++bn) {
+      if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
+      const int c = wn + 32 * bn + l32, gc = j0 + c;
+      TI *sq = quarter(c / QC) + (c % QC) * TILE;
+      const int cz = c & 15;
+      TI *mir = Out + (int64_t)(i0 + wm + 32 * bm + 4 * h) * ldv + gc;
 #pragma unroll
-        for (int bn = 0; bn < BMB; ++bn) {
-          if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
-          const int c = wn + 32 * bn + l32, gc = j0 + c;
-          TI *mir = Out + (int64_t)(i0 + wm + 32 * bm + 4 * h) * ldv + gc;
+      for (int g = 0; g < 4; ++g) {
+        const int r0 = wm + 32 * bm + 8 * g + 4 * h;
+        TI o[4];
+        if (!diag_tile) {          // every element has r < c (global)
 #pragma unroll
-          for (int g = 0; g < 4; ++g) {
-            const int r0 = wm + 32 * bm + 8 * g + 4 * h;
-            TI o[4];
-            if (!diag_tile) {          // every element has r < c (global)
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                float v = acc[bm][bn][4 * g + e];
-                if (EPI == EPI_SQUARE) {
-                  rs += v * v;
-                  v = c3 * v;
-                }
-                o[e] = from_f32<TI>(v);
-                mir[(int64_t)(8 * g + e) * ldv] = o[e];
-              }
-            } else {
-#pragma unroll
-              for (int e = 0; e < 4; ++e) {
-                const int gr = i0 + r0 + e;
-                float v = acc[bm][bn][4 * g + e];
-                if (EPI == EPI_SQUARE) {
-                  const bool diag = gr == gc && gc < n;
-                  if (gr <= gc && gc < n) {
-                    const float df = v - (diag ? 1.0f : 0.0f);
-                    rs += (diag ? 1.0f : 2.0f) * df * df;
-                  }
-                  v = c3 * v + (diag ? c1 : 0.0f);
-                }
-                o[e] = from_f32<TI>(v);
-                if (gr < gc) mir[(int64_t)(8 * g + e) * ldv] = o[e];
-              }
+          for (int e = 0; e < 4; ++e) {
+            float v = acc[bm][bn][4 * g + e];
+            if (EPI == EPI_SQUARE) {
+              rs += v * v;
+              v = c3 * v;
             }
-            TI *dst = sT + (c - rd * RCOLS) * LSTR + r0;
+            o[e] = from_f32<TI>(v);
+            mir[(int64_t)(8 * g + e) * ldv] = o[e];
+          }
+        } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) dst[e] = o[e];
+          for (int e = 0; e < 4; ++e) {
+            const int gr = i0 + r0 + e;
+            float v = acc[bm][bn][4 * g + e];
+            if (EPI == EPI_SQUARE) {
+              const bool diag = gr == gc && gc < n;
+              if (gr <= gc && gc < n) {
+                const float df = v - (diag ? 1.0f : 0.0f);
+                rs += (diag ? 1.0f : 2.0f) * df * df;
+              }
+              v = c3 * v + (diag ? c1 : 0.0f);
+            }
+            o[e] = from_f32<TI>(v);
+            if (gr < gc) mir[(int64_t)(8 * g + e) * ldv] = o[e];
           }
         }
-    }
-    __syncthreads();
-    constexpr int CPC = TILE / CH;                           // chunks per column
-    for (int idx = tid; idx < RCOLS * CPC; idx += 256) {
-      const int cl = idx / CPC, row = (idx % CPC) * CH;
-      const int gc = j0 + rd * RCOLS + cl, gr0 = i0 + row;
-      if (PARTIAL && (gc >= ld || gr0 >= ld)) continue;
-      const TI *src = sT + cl * LSTR + row;
-      TI *dst = Out + (int64_t)gc * ld + gr0;
-      if (gr0 + CH - 1 <= gc) {
-        *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
-      } else if (gr0 <= gc) {
-        for (int e = 0; e < CH && gr0 + e <= gc; ++e) dst[e] = src[e];
+        typedef TI v4 __attribute__((ext_vector_type(4)));
+        v4 ov;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) ov[e] = o[e];
+        *reinterpret_cast<v4 *>(sq + (((r0 / CH) ^ cz) * CH) + (r0 % CH)) = ov;
       }
     }
-    if (ROUNDS > 1) __syncthreads();
+  __syncthreads();
+  constexpr int CPC = TILE / CH;                             // chunks per column
+  for (int idx = tid; idx < TILE * CPC; idx += 256) {
+    const int c = idx / CPC, k = idx % CPC, row = k * CH;
+    const int gc = j0 + c, gr0 = i0 + row;
+    if (PARTIAL && (gc >= ld || gr0 >= ld)) continue;
+    if (gr0 > gc) continue;
+    const TI *src = quarter(c / QC) + (c % QC) * TILE + ((k ^ (c & 15)) * CH);
+    TI *dst = Out + (int64_t)gc * ld + gr0;
+    if (gr0 + CH - 1 <= gc) {
+      *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
+    } else {
+      for (int e = 0; e < CH && gr0 + e <= gc; ++e) dst[e] = src[e];
+    }
   }
   if (EPI == EPI_SQUARE) {
     // off-diagonal tiles count each element twice (it stands for (r, c) and (c, r));
@@ -297,18 +351,16 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
     const int rows = (ld - i0 < TILE ? ld - i0 : TILE), cols = (ld - j0 < TILE ? ld - j0 : TILE);
     atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
   }
-  // one LDS union: the main loop's two double-buffered operand rings, then the
-  // epilogue's staging tile
-  constexpr int MAIN_U4 = 4 * TILE * LROW16;
-  constexpr int EPI_U4 = smem_epi_u4<TI, TILE>();
-  __shared__ uint4 smem[MAIN_U4 > EPI_U4 ? MAIN_U4 : EPI_U4];
+  // the ring slots (separate arrays, see above); the epilogue reuses them as the
+  // four column quarters of its staging tile
+  __shared__ uint4 s0[slot_u4<BMB>()], s1[slot_u4<BMB>()], s2[slot_u4<BMB>()],
+      s3[slot_u4<BMB>()];
   __shared__ float red[4];
-  uint4 *sA = smem, *sB = smem + 2 * TILE * LROW16;
   if (i0 + TILE <= ld && j0 + TILE <= ld)
-    ns_gemm_body<TI, EPI, BMB, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, sA, sB, red,
-                                      &S.racc);
+    ns_gemm_body<TI, EPI, BMB, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3,
+                                      red, &S.racc);
   else
-    ns_gemm_body<TI, EPI, BMB, true>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, sA, sB, red,
+    ns_gemm_body<TI, EPI, BMB, true>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3, red,
                                      &S.racc);
 }
 
