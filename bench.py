@@ -60,16 +60,33 @@ def timed_steps(runner, sched, steps, L, torch):
     return wall, tot
 
 
-def sampled_parity(inst, runner, O, ks):
-    """Oracle one submatrix at a time; compare the written columns and traces."""
+def oracle_sample(inst, runner, O, sample, flops_per_sub):
+    """The oracle on `sample` evenly spaced molecules (one submatrix each), timed on
+    the host cores; the same results give the GPU path's error on that sample."""
+    try:
+        from threadpoolctl import threadpool_info
+        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
+    except Exception:
+        cores = os.cpu_count()
+    ks = np.linspace(0, inst.nmol - 1, sample).astype(int)
+    t0 = time.perf_counter()
+    refs = [O.submatrix_result(inst, int(k)) for k in ks]
+    dt = time.perf_counter() - t0
+    subs_per_s = len(ks) / dt
+    cpu = {"value": round(subs_per_s * flops_per_sub / 1e12, 6), "unit": "TFLOP/s",
+           "cores": int(cores), "kind": "oracle",
+           "submatrices_per_s": round(subs_per_s, 4),
+           "sample": f"{len(ks)} evenly spaced submatrices of the same workload "
+                     f"({dt:.1f} s); TFLOP/s = the paper-convention sign-iteration FLOPs "
+                     f"the GPU schedule counts for those submatrices / oracle time"}
+    # error of the GPU result on the same submatrices: block column k of D read back
+    # into T_k layout, and the per-column Tr(DH) contributions
     D = runner.D.cpu().numpy()
     st = runner.stats_host()
     pos = {int(k): i for i, k in enumerate(runner.mols)}
     dmax, demax = 0.0, 0.0
-    for k in ks:
-        ref = O.submatrix_result(inst, int(k))
+    for k, ref in zip(ks, refs):
         got = np.zeros_like(ref["D_cols"])
-        # read block column k of the GPU's D back into T_k layout
         for a, I in enumerate(ref["members"]):
             t = int(inst.colptr[k]) + a
             dI = int(inst.blk_dim[I])
@@ -79,28 +96,20 @@ def sampled_parity(inst, runner, O, ks):
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
         de = abs(float(st["tr_dh"][pos[int(k)]]) - ref["tr_dh"]) / int(inst.atoms[k])
         demax = max(demax, de)
-    return dmax, demax
+    err = {"max_abs_dD": dmax, "max_dE_per_atom": demax, "sampled_submatrices": int(len(ks))}
+    return cpu, err
 
 
-def cpu_baseline(inst, O, sample, flops_per_sub):
-    """Time the oracle on `sample` molecules (one submatrix each)."""
-    try:
-        from threadpoolctl import threadpool_info
-        cores = max([d.get("num_threads", 1) for d in threadpool_info()] or [os.cpu_count()])
-    except Exception:
-        cores = os.cpu_count()
-    ks = np.linspace(0, inst.nmol - 1, sample).astype(int)
-    t0 = time.perf_counter()
-    for k in ks:
-        O.submatrix_result(inst, int(k))
-    dt = time.perf_counter() - t0
-    subs_per_s = len(ks) / dt
-    return {"value": round(subs_per_s * flops_per_sub / 1e12, 6), "unit": "TFLOP/s",
-            "cores": int(cores), "kind": "oracle",
-            "submatrices_per_s": round(subs_per_s, 4),
-            "sample": f"{len(ks)} evenly spaced submatrices of the same workload "
-                      f"({dt:.1f} s); TFLOP/s = the paper-convention sign-iteration FLOPs "
-                      f"the GPU schedule counts for those submatrices / oracle time"}
+def copy_calibration(torch, mib):
+    """A plain elementwise copy of known size (read mib MiB, write mib MiB), run three
+    times so that hardware byte counters can be scaled against it."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"copy calibration: 3 x elementwise copy of {mib} MiB")
 
 
 def main():
@@ -113,8 +122,12 @@ def main():
     ap.add_argument("--iters", type=int, default=0, help="fixed FP16 iterations (0: to tolerance)")
     ap.add_argument("--prec", default="fp16")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of plain FP32 (0: skip)")
-    ap.add_argument("--cpu-sample", type=int, default=12)
-    ap.add_argument("--parity-sample", type=int, default=4)
+    ap.add_argument("--cpu-sample", type=int, default=40,
+                    help="submatrices the oracle solves on the host (0: skip)")
+    ap.add_argument("--graph-steps", type=int, default=2,
+                    help="timed replays of the step captured as a HIP graph (0: skip)")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="after the run, three elementwise copies of MIB MiB (counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the method's submatrices are independent, so the "
@@ -154,11 +167,27 @@ def main():
     sign_ms = tm["ms_sign"] / args.steps
     exec_flop_step = tm["gemm_flop"] / args.steps
 
-    from oracle import nolsm_oracle as O
-    ks = np.linspace(0, inst.nmol - 1, args.parity_sample).astype(int)
-    dmax, demax = sampled_parity(inst, runner, O, ks)
-    log(f"sampled parity ({len(ks)} submatrices): max|dD| {dmax:.2e}  max|dE|/atom {demax:.2e}")
+    graph = None
+    if args.graph_steps > 0:
+        g = runner.capture(sched=mixed)
+        g.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.graph_steps):
+            g.replay()
+        torch.cuda.synchronize()
+        graph = {"ms_per_step": round((time.perf_counter() - t0) / args.graph_steps * 1e3, 2),
+                 "steps": args.graph_steps,
+                 "energy_matches_eager": runner.energy_host()[0] == e_mixed}
+        log(f"graph replay: {json.dumps(graph)}")
+        del g
 
+    cpu, err = None, None
+    if args.cpu_sample > 0:
+        from oracle import nolsm_oracle as O
+        cpu, err = oracle_sample(inst, runner, O, args.cpu_sample, flops / K)
+        log(f"cpu baseline: {json.dumps(cpu)}")
+        log(f"error vs oracle: {json.dumps(err)}")
     plain = None
     if args.plain_steps > 0:
         pl = plain_fp32_schedule()
@@ -176,10 +205,8 @@ def main():
                  "energy_per_atom_diff_vs_mixed": abs(e_plain - e_mixed) / inst.natoms}
         log(f"plain fp32: {json.dumps(plain)}")
 
-    cpu = None
-    if args.cpu_sample > 0:
-        cpu = cpu_baseline(inst, O, args.cpu_sample, flops / K)
-        log(f"cpu baseline: {json.dumps(cpu)}")
+    if args.calibrate_copy > 0:
+        copy_calibration(torch, args.calibrate_copy)
 
     # executed MFMA flops of the active tiles (device counter) over the time of every
     # GEMM launch in the timed region (HIP events around each launch)
@@ -212,8 +239,8 @@ def main():
         "sign_phase_tflops": round(flops / (sign_ms * 1e-3) / 1e12, 3),
         "phase_ms": {k[3:]: round(v / args.steps, 2) for k, v in tm.items() if k.startswith("ms_")},
         "energy": e_mixed, "electrons": n_mixed,
-        "error_vs_oracle": {"max_abs_dD": dmax, "max_dE_per_atom": demax,
-                            "sampled_submatrices": int(len(ks))},
+        "error_vs_oracle": err,
+        "graph_replay": graph,
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": round(plain["ms_per_step"] / (wall * 1e3), 3) if plain else None,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_PEAK,

@@ -10,10 +10,13 @@
  * Conventions shared by every entry point
  *  - Pointers are DEVICE pointers unless the argument says "(host)".
  *  - The caller owns every buffer.  The library never allocates device memory:
- *    per-batch state lives in a caller-provided workspace whose size comes from
- *    nolsm_plan_workspace_bytes().  A plan itself is a small host object.
+ *    per-batch data live in a caller-provided workspace (nolsm_plan_workspace_bytes,
+ *    the large per-submatrix arenas, which plans may share) and a per-plan table
+ *    buffer (nolsm_plan_table_bytes: descriptors, member and tile lists, state).
+ *    A plan itself is a small host object.
  *  - Work is enqueued asynchronously on `stream`; nothing synchronises the host
- *    except nolsm_check().  Return codes report argument and launch errors only;
+ *    except nolsm_check() and the first nolsm_plan_bind() of a plan to a table
+ *    buffer.  Return codes report argument and launch errors only;
  *    data-dependent failures (a submatrix of S that is not positive definite, a
  *    sign iteration that did not converge) are recorded per submatrix in
  *    nolsm_stats and folded into a code by nolsm_check() after a stream sync.
@@ -145,11 +148,25 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
                                int32_t K, nolsm_plan **plan /*host out*/);
 void nolsm_plan_destroy(nolsm_plan *plan);
 
-/* Device workspace bytes the plan needs (256-byte aligned base required). */
+/* Device workspace bytes the plan needs: a 256-byte header shared by every plan
+ * bound to the same workspace, then the per-submatrix arenas (256-byte aligned
+ * base required). */
 size_t nolsm_plan_workspace_bytes(const nolsm_plan *plan);
 
-/* Attach a device workspace and upload the plan's tables into it (async on stream). */
-nolsm_status nolsm_plan_bind(nolsm_plan *plan, void *workspace, size_t bytes, hipStream_t stream);
+/* Device table-buffer bytes of the plan (descriptors, member lists, GEMM tile
+ * lists, per-submatrix state); one buffer per plan, 256-byte aligned. */
+size_t nolsm_plan_table_bytes(const nolsm_plan *plan);
+
+/* Attach the plan to its table buffer and to a workspace.  The first bind to a
+ * given table buffer uploads the tables and clears the state on `stream` and
+ * then synchronises the stream (the host copies must outlive the upload); later
+ * binds with the same table buffer do no device work at all, so several plans can
+ * take turns on one workspace inside stream capture (a HIP graph of a whole
+ * multi-batch step).  Calls on plans sharing a workspace must not overlap.
+ * Errors: NOLSM_EINVAL for null pointers, NOLSM_EWORKSPACE for buffers that are
+ * too small or misaligned, NOLSM_EHIP for a failed upload. */
+nolsm_status nolsm_plan_bind(nolsm_plan *plan, void *tables, size_t table_bytes, void *workspace,
+                             size_t bytes, hipStream_t stream);
 
 /* Layout of submatrix i (0 <= i < K) inside the bound workspace. */
 nolsm_status nolsm_plan_query(const nolsm_plan *plan, int32_t i, nolsm_sub_info *info /*host*/);

@@ -90,7 +90,8 @@ def lib():
         "nolsm_plan_create": (i32, [P(Pattern), vp, i32, P(vp)]),
         "nolsm_plan_destroy": (None, [vp]),
         "nolsm_plan_workspace_bytes": (sz, [vp]),
-        "nolsm_plan_bind": (i32, [vp, vp, sz, vp]),
+        "nolsm_plan_table_bytes": (sz, [vp]),
+        "nolsm_plan_bind": (i32, [vp, vp, sz, vp, sz, vp]),
         "nolsm_plan_query": (i32, [vp, i32, P(SubInfo)]),
         "nolsm_build_submatrices": (i32, [vp, P(Pattern), vp, vp, vp]),
         "nolsm_sign_batched": (i32, [vp, dbl, P(Schedule), vp, vp]),
@@ -119,7 +120,7 @@ def lib():
 
 
 EXPORTED = ("nolsm_plan_create", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
-            "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
+            "nolsm_plan_table_bytes", "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
             "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_check",
             "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings",
             "nolsm_setup_batched", "nolsm_features", "nolsm_mlp_param_count",
@@ -213,8 +214,13 @@ def nolsm_plan_workspace_bytes(plan) -> int:
     return int(lib().nolsm_plan_workspace_bytes(plan))
 
 
-def nolsm_plan_bind(plan, workspace, stream=None):
-    _ok(lib().nolsm_plan_bind(plan, _ptr(workspace), workspace.numel() * workspace.element_size(),
+def nolsm_plan_table_bytes(plan) -> int:
+    return int(lib().nolsm_plan_table_bytes(plan))
+
+
+def nolsm_plan_bind(plan, tables, workspace, stream=None):
+    _ok(lib().nolsm_plan_bind(plan, _ptr(tables), tables.numel() * tables.element_size(),
+                              _ptr(workspace), workspace.numel() * workspace.element_size(),
                               _stream(stream)))
 
 

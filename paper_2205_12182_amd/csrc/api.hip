@@ -14,7 +14,8 @@ namespace nolsm {
 void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
                    const double *S_val, char *ws, hipStream_t stream);
-void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws, hipStream_t s);
+void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
+                  char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                  char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
                  double flop, hipStream_t s);
@@ -42,11 +43,15 @@ struct nolsm_plan {
   int32_t max_npad = 0;
   std::vector<SubDesc> desc;
   std::vector<int32_t> mem_mol, mem_loc;
-  std::vector<Tile> tiles;      // the three tile lists of TileSet, back to back
-  int32_t list_end[3] = {0, 0, 0};
+  std::vector<Tile> tiles;      // the four tile lists of TileSet, back to back
+  int32_t list_end[4] = {0, 0, 0, 0};
+  // tables (bytes from the plan's table buffer)
   size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
+  size_t tab_bytes = 0;
+  // workspace (bytes from the workspace base)
   size_t off_counter = 0;       // unsigned long long: executed sign-GEMM work (FLOP_UNIT)
   size_t bytes = 0;
+  char *tab = nullptr;          // table buffer the tables were last uploaded to
   char *ws = nullptr;
   bool bound = false;
   bool setup_done = false;      // M_k and L^-1 are current (set-up ran after the last gather)
@@ -136,15 +141,16 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
   // tiles of the symmetric sign-iteration products: upper triangle; small
   // submatrices use 128 x 128 tiles, the rest 256 x 256.  Executed flops skip the
   // 32 x 32 blocks that lie entirely in the padding.
-  // list 0: small submatrices, 128 tiles; list 1: large, 256 tiles; list 2: large, 128 tiles
-  for (int list = 0; list < 3; ++list) {
+  // list 0: small submatrices, 128 tiles; list 1: large, 256 tiles; list 2: large, 128 tiles;
+  // list 3: every submatrix, every 128 tile (not only the upper triangle)
+  for (int list = 0; list < 4; ++list) {
     const int T = list == 1 ? 256 : 128;
     for (int i = 0; i < K; ++i) {
       const int np = p->desc[i].npad;
-      if ((np >= BIG_TILE_MIN_NPAD) != (list != 0)) continue;
+      if (list < 3 && (np >= BIG_TILE_MIN_NPAD) != (list != 0)) continue;
       const int nt = (np + T - 1) / T;
       for (int ti = 0; ti < nt; ++ti)
-        for (int tj = ti; tj < nt; ++tj) {
+        for (int tj = list == 3 ? 0 : ti; tj < nt; ++tj) {
           p->tiles.push_back(Tile{i, ti, tj, 0});
           const double rows = std::min(T, np - ti * T), cols = std::min(T, np - tj * T);
           if (list < 2) p->gemm_flop += 2.0 * rows * cols * (double)np;
@@ -152,11 +158,8 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
     }
     p->list_end[list] = (int32_t)p->tiles.size();
   }
-  // workspace layout: a fixed header shared by every plan bound to the workspace
-  // (the executed-flop counter), then this plan's tables and per-submatrix arenas
+  // table buffer: descriptors, member lists, tile lists, per-submatrix state
   off = 0;
-  p->off_counter = off;
-  off = align256(off + sizeof(unsigned long long));
   p->off_desc = off;
   off = align256(off + sizeof(SubDesc) * (size_t)K);
   p->off_mem_mol = off;
@@ -167,6 +170,12 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
   off = align256(off + sizeof(Tile) * p->tiles.size());
   p->off_state = off;
   off = align256(off + sizeof(SubState) * (size_t)K);
+  p->tab_bytes = std::max<size_t>(off, 256);
+  // workspace: a fixed header shared by every plan bound to the workspace (the
+  // executed-flop counter), then the per-submatrix arenas
+  off = 0;
+  p->off_counter = off;
+  off = align256(off + sizeof(unsigned long long));
   for (int i = 0; i < K; ++i) {
     SubDesc &d = p->desc[i];
     const size_t np = (size_t)d.npad;
@@ -192,32 +201,45 @@ void nolsm_plan_destroy(nolsm_plan *p) { delete p; }
 
 size_t nolsm_plan_workspace_bytes(const nolsm_plan *p) { return p ? p->bytes : 0; }
 
-nolsm_status nolsm_plan_bind(nolsm_plan *p, void *workspace, size_t bytes, hipStream_t s) {
-  if (!p || !workspace) return fail(NOLSM_EINVAL, "nolsm_plan_bind: null argument");
+size_t nolsm_plan_table_bytes(const nolsm_plan *p) { return p ? p->tab_bytes : 0; }
+
+nolsm_status nolsm_plan_bind(nolsm_plan *p, void *tables, size_t table_bytes, void *workspace,
+                             size_t bytes, hipStream_t s) {
+  if (!p || !tables || !workspace) return fail(NOLSM_EINVAL, "nolsm_plan_bind: null argument");
+  if (table_bytes < p->tab_bytes)
+    return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: table buffer %zu bytes < %zu needed",
+                table_bytes, p->tab_bytes);
   if (bytes < p->bytes)
     return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: workspace %zu bytes < %zu needed", bytes,
                 p->bytes);
-  if (reinterpret_cast<uintptr_t>(workspace) & 255)
-    return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: workspace must be 256-byte aligned");
-  p->ws = static_cast<char *>(workspace);
-  hipError_t e = hipSuccess;
-  if (p->K > 0) {
-    e = hipMemcpyAsync(p->ws + p->off_desc, p->desc.data(), sizeof(SubDesc) * p->K,
-                       hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(p->ws + p->off_mem_mol, p->mem_mol.data(),
-                         sizeof(int32_t) * p->mem_mol.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(p->ws + p->off_mem_loc, p->mem_loc.data(),
-                         sizeof(int32_t) * p->mem_loc.size(), hipMemcpyHostToDevice, s);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(p->ws + p->off_tiles, p->tiles.data(), sizeof(Tile) * p->tiles.size(),
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) || (reinterpret_cast<uintptr_t>(tables) & 255))
+    return fail(NOLSM_EWORKSPACE, "nolsm_plan_bind: buffers must be 256-byte aligned");
+  char *tab = static_cast<char *>(tables);
+  if (tab != p->tab) {
+    // first bind to this table buffer: upload the tables and clear the state
+    p->tab = nullptr;
+    hipError_t e = hipSuccess;
+    if (p->K > 0) {
+      e = hipMemcpyAsync(tab + p->off_desc, p->desc.data(), sizeof(SubDesc) * p->K,
                          hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(p->ws + p->off_state, 0, sizeof(SubState) * p->K, s);
-    // the host copies must stay alive until the copies complete
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(tab + p->off_mem_mol, p->mem_mol.data(),
+                           sizeof(int32_t) * p->mem_mol.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(tab + p->off_mem_loc, p->mem_loc.data(),
+                           sizeof(int32_t) * p->mem_loc.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(tab + p->off_tiles, p->tiles.data(), sizeof(Tile) * p->tiles.size(),
+                           hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipMemsetAsync(tab + p->off_state, 0, sizeof(SubState) * p->K, s);
+      // the host copies must stay alive until the copies complete
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+    }
+    if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_plan_bind: %s", hipGetErrorString(e));
+    p->tab = tab;
   }
-  if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_plan_bind: %s", hipGetErrorString(e));
+  p->setup_done = false;        // the workspace may have served another plan since
+  p->ws = static_cast<char *>(workspace);
   p->bound = true;
   return NOLSM_OK;
 }
@@ -240,12 +262,23 @@ nolsm_status nolsm_plan_query(const nolsm_plan *p, int32_t i, nolsm_sub_info *in
 }
 
 #define PLAN_PTRS                                                                          \
-  const SubDesc *desc = reinterpret_cast<const SubDesc *>(p->ws + p->off_desc);            \
-  const int32_t *mem_mol = reinterpret_cast<const int32_t *>(p->ws + p->off_mem_mol);      \
-  const int32_t *mem_loc = reinterpret_cast<const int32_t *>(p->ws + p->off_mem_loc);      \
-  const Tile *tiles = reinterpret_cast<const Tile *>(p->ws + p->off_tiles);                \
-  SubState *st = reinterpret_cast<SubState *>(p->ws + p->off_state);                       \
+  const SubDesc *desc = reinterpret_cast<const SubDesc *>(p->tab + p->off_desc);           \
+  const int32_t *mem_mol = reinterpret_cast<const int32_t *>(p->tab + p->off_mem_mol);     \
+  const int32_t *mem_loc = reinterpret_cast<const int32_t *>(p->tab + p->off_mem_loc);     \
+  const Tile *tiles = reinterpret_cast<const Tile *>(p->tab + p->off_tiles);               \
+  SubState *st = reinterpret_cast<SubState *>(p->tab + p->off_state);                      \
   (void)desc; (void)mem_mol; (void)mem_loc; (void)tiles; (void)st;
+
+static TileSet tile_set(const nolsm_plan *p, const Tile *tiles) {
+  TileSet ts;
+  for (int l = 0; l < 4; ++l) {
+    const int b = l ? p->list_end[l - 1] : 0;
+    ts.t[l] = tiles + b;
+    ts.n[l] = p->list_end[l] - b;
+  }
+  ts.flop_units = reinterpret_cast<unsigned long long *>(p->ws + p->off_counter);
+  return ts;
+}
 
 nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, const double *H_val,
                                      const double *S_val, hipStream_t s) {
@@ -293,20 +326,14 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   int ev;
+  const TileSet ts = tile_set(p, tiles);
   if (!p->setup_done) {
     ev = p->log.begin(T_SETUP, s);
-    launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
+    launch_setup(desc, st, p->K, p->max_npad, ts, p->ws, s);
     p->log.end(ev, s);
     p->setup_done = true;
   }
   ev = p->log.begin(T_SIGN, s);
-  TileSet ts;
-  for (int l = 0; l < 3; ++l) {
-    const int b = l ? p->list_end[l - 1] : 0;
-    ts.t[l] = tiles + b;
-    ts.n[l] = p->list_end[l] - b;
-  }
-  ts.flop_units = reinterpret_cast<unsigned long long *>(p->ws + p->off_counter);
   launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, &p->log, p->gemm_flop, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
@@ -324,7 +351,7 @@ nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   const int ev = p->log.begin(T_SETUP, s);
-  launch_setup(desc, st, p->K, p->max_npad, p->ws, s);
+  launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->ws, s);
   p->log.end(ev, s);
   p->setup_done = true;
   return hip_check("nolsm_setup_batched");
@@ -406,7 +433,7 @@ nolsm_status nolsm_check(nolsm_plan *p, hipStream_t s) {
   if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_check: %s", hipGetErrorString(e));
   std::vector<SubState> host(p->K);
   if (p->K > 0) {
-    e = hipMemcpy(host.data(), p->ws + p->off_state, sizeof(SubState) * p->K, hipMemcpyDeviceToHost);
+    e = hipMemcpy(host.data(), p->tab + p->off_state, sizeof(SubState) * p->K, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return fail(NOLSM_EHIP, "nolsm_check: %s", hipGetErrorString(e));
   }
   int nspd = 0, nconv = 0, first = -1;

@@ -58,13 +58,14 @@ struct SubState {
 
 struct Tile { int32_t sub, ti, tj, pad; };
 
-// Upper-triangle tile lists of the sign-iteration products: t[0] holds the small
+// Tile lists: upper-triangle tiles of the symmetric products, t[0] the small
 // submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 256 tiles (FP16 and
 // BF16), t[2] the large ones in 128 x 128 tiles (FP32, whose 256 x 256 tile does
-// not fit the register file).
+// not fit the register file); t[3] every 128 x 128 tile of every submatrix (the
+// non-symmetric set-up product).
 struct TileSet {
-  const Tile *t[3];
-  int n[3];
+  const Tile *t[4];
+  int n[4];
   unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
 };
 // 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad

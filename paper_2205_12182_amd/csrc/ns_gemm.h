@@ -29,7 +29,10 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
 
-enum { EPI_SQUARE = 0, EPI_UPDATE = 1 };
+// SQUARE: Z = c1 I + c3 X X (+ residual); UPDATE: X' = X Z; PLAIN_SYM: the plain
+// product of a symmetric result (upper tiles, mirrored); PLAIN_FULL: the plain
+// product, every tile, nothing mirrored.
+enum { EPI_SQUARE = 0, EPI_UPDATE = 1, EPI_PLAIN_SYM = 2, EPI_PLAIN_FULL = 3 };
 
 constexpr int NSLOT = 4;           // LDS ring slots (stages in flight: NSLOT - 1)
 // Word 3 of a raw (stride 0) buffer resource on CDNA: 32-bit data format, no
@@ -89,9 +92,13 @@ __host__ __device__ constexpr int wait_vm_lgkm0(int vm) {
 
 #define NS_LDS_PTR(p) ((__attribute__((address_space(3))) void *)(p))
 
+// C(m, c) = sum_{k < kend} A[m ld + k] B[c ld + k] for the tile at (i0, j0), i.e.
+// C = A^T B for column-major A, B with leading dimension ld (kend: a multiple of
+// the stage depth, at most ld).
 template <typename TI, int EPI, int BMB, bool PARTIAL>
 __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI *__restrict__ B,
-                                             TI *__restrict__ Out, int ld, int n, int i0, int j0,
+                                             TI *__restrict__ Out, int ld, int kend, int n, int i0,
+                                             int j0,
                                              float c1, float c3, uint4 *s0, uint4 *s1, uint4 *s2,
                                              uint4 *s3, float *red, unsigned long long *racc) {
   constexpr int TILE = 64 * BMB;
@@ -101,7 +108,7 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wm = (w >> 1) * 32 * BMB, wn = (w & 1) * 32 * BMB;
   const int h = lane >> 5, l32 = lane & 31;
-  const int nk = ld / KStage<TI>::KS;
+  const int nk = kend / KStage<TI>::KS;
 
   // blocks of this wave that hold rows/columns < ld
   int nvr = BMB, nvc = BMB;
@@ -252,7 +259,8 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   auto quarter = [&](int qi) -> TI * {
     return reinterpret_cast<TI *>(qi == 0 ? s0 : qi == 1 ? s1 : qi == 2 ? s2 : s3);
   };
-  const bool diag_tile = (i0 == j0);
+  constexpr bool MIRROR = EPI != EPI_PLAIN_FULL;
+  const bool diag_tile = MIRROR && (i0 == j0);
   // keep the row stride in a vector register so that the per-row store offsets
   // are formed with vector arithmetic instead of occupying scalar registers
   int ldv = ld;
@@ -280,7 +288,7 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
               v = c3 * v;
             }
             o[e] = from_f32<TI>(v);
-            mir[(int64_t)(8 * g + e) * ldv] = o[e];
+            if (MIRROR) mir[(int64_t)(8 * g + e) * ldv] = o[e];
           }
         } else {
 #pragma unroll
@@ -312,10 +320,10 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
     const int c = idx / CPC, k = idx % CPC, row = k * CH;
     const int gc = j0 + c, gr0 = i0 + row;
     if (PARTIAL && (gc >= ld || gr0 >= ld)) continue;
-    if (gr0 > gc) continue;
+    if (MIRROR && gr0 > gc) continue;
     const TI *src = quarter(c / QC) + (c % QC) * TILE + ((k ^ (c & 15)) * CH);
     TI *dst = Out + (int64_t)gc * ld + gr0;
-    if (gr0 + CH - 1 <= gc) {
+    if (!MIRROR || gr0 + CH - 1 <= gc) {
       *reinterpret_cast<uint4 *>(dst) = *reinterpret_cast<const uint4 *>(src);
     } else {
       for (int e = 0; e < CH && gr0 + e <= gc; ++e) dst[e] = src[e];
@@ -357,11 +365,44 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
       s3[slot_u4<BMB>()];
   __shared__ float red[4];
   if (i0 + TILE <= ld && j0 + TILE <= ld)
-    ns_gemm_body<TI, EPI, BMB, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3,
+    ns_gemm_body<TI, EPI, BMB, false>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3,
                                       red, &S.racc);
   else
-    ns_gemm_body<TI, EPI, BMB, true>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3, red,
+    ns_gemm_body<TI, EPI, BMB, true>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3, red,
                                      &S.racc);
+}
+
+// Set-up products in FP32 (128 x 128 tiles), on the three FP32 buffers of the
+// iteration arena: buffer 0 = L^-T, buffer 1 = H (then M), buffer 2 = U.
+//   PLAIN_FULL: U = H L^-T, every tile; L^-T(k, c) = 0 for k > c, so the
+//               contraction stops at the tile's last column.
+//   PLAIN_SYM:  M = L^-1 U (symmetric), upper tiles mirrored; L^-1(r, k) = 0 for
+//               k > r, so the contraction stops at the tile's last row.
+template <int EPI>
+__global__ __launch_bounds__(256) void setup_gemm_kernel(const Tile *__restrict__ tiles,
+                                                         const SubDesc *__restrict__ desc,
+                                                         const SubState *__restrict__ st,
+                                                         char *ws) {
+  constexpr int TILE = 128;
+  const Tile t = tiles[xcd_remap(blockIdx.x, gridDim.x)];
+  if (st[t.sub].status != 0) return;
+  const SubDesc d = desc[t.sub];
+  const int ld = d.npad;
+  float *Lt = buf_ptr<float>(ws, d, 0), *H = buf_ptr<float>(ws, d, 1), *U = buf_ptr<float>(ws, d, 2);
+  const int i0 = t.ti * TILE, j0 = t.tj * TILE;
+  const float *A = EPI == EPI_PLAIN_FULL ? H : Lt;
+  const float *B = EPI == EPI_PLAIN_FULL ? Lt : U;
+  float *Out = EPI == EPI_PLAIN_FULL ? U : H;
+  const int kl = (EPI == EPI_PLAIN_FULL ? j0 : i0) + TILE;
+  const int kend = kl < ld ? kl : ld;
+  __shared__ uint4 s0[slot_u4<2>()], s1[slot_u4<2>()], s2[slot_u4<2>()], s3[slot_u4<2>()];
+  __shared__ float red[4];
+  if (i0 + TILE <= ld && j0 + TILE <= ld)
+    ns_gemm_body<float, EPI, 2, false>(A, B, Out, ld, kend, d.n, i0, j0, 0.0f, 0.0f, s0, s1, s2,
+                                       s3, red, nullptr);
+  else
+    ns_gemm_body<float, EPI, 2, true>(A, B, Out, ld, kend, d.n, i0, j0, 0.0f, 0.0f, s0, s1, s2, s3,
+                                      red, nullptr);
 }
 
 }  // namespace nolsm

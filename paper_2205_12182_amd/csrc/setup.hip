@@ -1,4 +1,4 @@
-// FP64 set-up of the sign argument for Eq. 8.
+// Set-up of the sign argument for Eq. 8 (FP64 factorisation, FP32 products).
 //
 // T_k(S)^-1 T_k(H0) - mu I has the same spectrum as the symmetric matrix
 //   M_k - mu I,  M_k = L^-1 T_k(H0) L^-T,  T_k(S) = L L^T,
@@ -11,9 +11,15 @@
 //   chol_panel   A[j+64:, j] <- A[j+64:, j] L_jj^-T                  (FP64 MFMA)
 //   chol_update  A[j+64:, j+64:] -= P P^T, lower tiles                 (FP64 MFMA)
 //   trtri_*      L^-1 in place, block columns right to left            (FP64 MFMA)
-//   trmm_left    T = L^-1 H                                             (FP64 MFMA)
-//   trmm_right   M = T L^-T, lower tiles mirrored (M exactly symmetric) (FP64 MFMA)
+//   prep_products  L^-T and H rounded to FP32
+//   setup_gemm     U = H L^-T, then M = L^-1 U, upper tiles mirrored so that M is
+//                  exactly symmetric                                    (FP32 MFMA)
+//   widen_m        M to FP64 for the scaling and the first iterate
+// M only feeds the low-precision sign iteration and its scaling; the density
+// columns use the FP64 L^-1, so FP32 rounding in M (relative ~1e-7) stays far
+// below the FP16 rounding of the iteration.
 #include "common.h"
+#include "ns_gemm.h"
 
 namespace nolsm {
 
@@ -252,44 +258,42 @@ __global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restri
 
 // ------------------------------------------------------------------ M = L^-1 H L^-T
 
-// T = Linv H into the low-precision arena (used as FP64 scratch before the iteration)
-__global__ __launch_bounds__(256) void trmm_left_kernel(const SubDesc *__restrict__ desc,
-                                                        char *ws) {
+// FP32 operands of the set-up products in the iteration arena: buffer 0 = L^-T
+// (the transpose of L^-1, through an LDS tile), buffer 1 = H.
+__global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__restrict__ desc,
+                                                            char *ws) {
   SUB_PTRS
   const int nt = ld / 64;
-  const int ti = blockIdx.x / nt, tj = blockIdx.x % nt;   // blockIdx.x < ntmax^2
-  if (blockIdx.x >= nt * nt) return;
-  double *Tb = reinterpret_cast<double *>(ws + d.off_lo);
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
-  d4 acc[2][2];
-  acc_zero(acc);
-  gemm64_f64<false>(Sb + ti * 64, ld, Hb + (int64_t)tj * 64 * ld, ld, 0, (ti + 1) * 64, acc, sA,
-                    sB);
-  acc_foreach(acc,
-              [&](int r, int c, double v) { Tb[(int64_t)(tj * 64 + c) * ld + ti * 64 + r] = v; });
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+  float *Lt = reinterpret_cast<float *>(ws + d.off_lo);
+  float *H32 = Lt + (int64_t)ld * ld;
+  __shared__ float tile[64][65];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    const int64_t o = (int64_t)(bj * 64 + c) * ld + bi * 64 + r;
+    tile[c][r] = (float)Sb[o];
+    H32[o] = (float)Hb[o];
+  }
+  __syncthreads();
+  // L^-T(bj*64 + c, bi*64 + r) = L^-1(bi*64 + r, bj*64 + c)
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e & 63, r = e >> 6;
+    Lt[(int64_t)(bi * 64 + r) * ld + bj * 64 + c] = tile[c][r];
+  }
 }
 
-// M = T Linv^T, lower tiles, written to both triangles of the H buffer
-__global__ __launch_bounds__(256) void trmm_right_kernel(const SubDesc *__restrict__ desc,
-                                                         char *ws) {
+// M (FP32, buffer 1) widened to FP64 into the H buffer.
+__global__ __launch_bounds__(256) void widen_m_kernel(const SubDesc *__restrict__ desc,
+                                                      const SubState *__restrict__ st, char *ws) {
   SUB_PTRS
-  const int nt = ld / 64;
-  int ti, tj;
-  tri_index(blockIdx.x, ti, tj);
-  if (ti >= nt) return;
-  const double *Tb = reinterpret_cast<const double *>(ws + d.off_lo);
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
-  d4 acc[2][2];
-  acc_zero(acc);
-  // M(r, c) = sum_k T(ti*64 + r, k) Linv(tj*64 + c, k);  B(k, n) = Linv[k*ld + tj*64 + n]
-  gemm64_f64<true>(Tb + ti * 64, ld, Sb + tj * 64, ld, 0, (tj + 1) * 64, acc, sA, sB);
-  acc_foreach(acc, [&](int r, int c, double v) {
-    const int gi = ti * 64 + r, gj = tj * 64 + c;
-    if (gi < gj) return;            // diagonal tiles: the lower half writes both triangles
-    Hb[(int64_t)gj * ld + gi] = v;
-    Hb[(int64_t)gi * ld + gj] = v;
-  });
+  if (st[blockIdx.y].status != 0) return;
+  const float *M32 = reinterpret_cast<const float *>(ws + d.off_lo) + (int64_t)ld * ld;
+  const int64_t tot = (int64_t)ld * ld;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
+    Hb[e] = (double)M32[e];
 }
+
 
 // keep_spd = 0: clear every status (a new set-up); 1: clear only NOLSM_ENOCONV
 __global__ void reset_status_kernel(SubState *__restrict__ st, int K, int keep_spd) {
@@ -304,8 +308,8 @@ void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s) {
 
 // ------------------------------------------------------------------ host launcher
 
-void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
-                  hipStream_t s) {
+void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
+                  char *ws, hipStream_t s) {
   const int nbmax = max_npad / NB;
   launch_reset_status(st, K, 0, s);
   for (int jb = 0; jb < nbmax; ++jb) {
@@ -323,8 +327,15 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, char *
     trtri_update_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
   }
   zero_upper_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, ws);
-  trmm_left_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
-  trmm_right_kernel<<<dim3(nbmax * (nbmax + 1) / 2, K), 256, 0, s>>>(desc, ws);
+  // M = L^-1 H L^-T as two FP32 products: U = H L^-T, then M = L^-1 U
+  prep_products_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
+  if (ts.n[3] > 0)
+    setup_gemm_kernel<EPI_PLAIN_FULL><<<ts.n[3], 256, 0, s>>>(ts.t[3], desc, st, ws);
+  if (ts.n[0] > 0)
+    setup_gemm_kernel<EPI_PLAIN_SYM><<<ts.n[0], 256, 0, s>>>(ts.t[0], desc, st, ws);
+  if (ts.n[2] > 0)
+    setup_gemm_kernel<EPI_PLAIN_SYM><<<ts.n[2], 256, 0, s>>>(ts.t[2], desc, st, ws);
+  widen_m_kernel<<<dim3(256, K), 256, 0, s>>>(desc, st, ws);
 }
 
 }  // namespace nolsm

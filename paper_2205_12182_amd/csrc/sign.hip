@@ -31,16 +31,30 @@ struct PhaseArgs {
   float tol;
 };
 
+// Spectrum-interval scaling of Newton-Schulz (Eq. 6 with a scaled argument): with
+// every |eigenvalue| of X in [l, u], the step x <- p(a x), p(y) = y (3 - y^2) / 2,
+// a^2 = 3 / (u^2 + u l + l^2), maps both ends of the interval to the same value
+// p(a l) and keeps every eigenvalue up to sqrt(u^2 + u l + l^2) >= u positive
+// (p(y) < 0 for y > sqrt 3).  The upper end is u = 1 + SCALE_MARGIN rather than 1:
+// the low-precision iterates carry rounding errors that move eigenvalues near 1 by
+// a few 1e-3 in FP16, and with u = 1 and a small l the margin sqrt(1 + l + l^2) - 1
+// ~ l / 2 is smaller than that, which would send such eigenvalues to the wrong
+// sign.  Once a <= 1 the plain step (a = 1) is used; its fixed points are exactly
+// +-1.
+constexpr double SCALE_MARGIN = 0.05;
+
+__device__ __forceinline__ double ns_alpha(double l) {
+  const double u = 1.0 + SCALE_MARGIN;
+  const double a = sqrt(3.0 / (u * u + u * l + l * l));
+  return a > 1.0 ? a : 1.0;
+}
+
+__device__ __forceinline__ double ns_p(double y) { return 0.5 * y * (3.0 - y * y); }
+
 __device__ __forceinline__ void set_coeffs(SubState &s, int use_lower) {
-  if (use_lower && s.lower < 1.0) {
-    const double l = s.lower;
-    const double a = sqrt(3.0 / (1.0 + l + l * l));
-    s.c1 = (float)(1.5 * a);
-    s.c3 = (float)(-0.5 * a * a * a);
-  } else {
-    s.c1 = 1.5f;
-    s.c3 = -0.5f;
-  }
+  const double a = (use_lower && s.lower < 1.0) ? ns_alpha(s.lower) : 1.0;
+  s.c1 = (float)(1.5 * a);
+  s.c3 = (float)(-0.5 * a * a * a);
 }
 
 __global__ void ns_check_kernel(const SubDesc *__restrict__ desc, SubState *__restrict__ st,
@@ -82,9 +96,10 @@ __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, in
   s.cur = (s.cur + 2) % 3;
   if (fallback) ++s.iters_fb; else ++s.iters_lo;
   if (use_lower && s.lower < 1.0) {
-    const double l = s.lower;
-    const double a = sqrt(3.0 / (1.0 + l + l * l));
-    double ln = 0.5 * a * l * (3.0 - a * a * l * l);
+    // new lower bound: the smaller image of the two interval ends
+    const double l = s.lower, a = ns_alpha(l);
+    const double pl = ns_p(a * l), pu = ns_p(a * (1.0 + SCALE_MARGIN));
+    const double ln = pl < pu ? pl : pu;
     s.lower = ln > 1.0 ? 1.0 : ln;
   }
   set_coeffs(s, use_lower);       // for the next iteration's Z = c1 I + c3 X^2

@@ -168,6 +168,80 @@ class ScheduleMLP:
         return cls(nout=nout, params=p, device=device)
 
 
+def pick_molecules(nmol: int, count: int, seed: int, salt: int = 0x5EED) -> np.ndarray:
+    """A seeded, sorted sample of `count` molecules (all of them if count >= nmol)."""
+    if count >= nmol:
+        return np.arange(nmol, dtype=np.int32)
+    rng = np.random.default_rng([salt, seed])
+    return np.sort(rng.choice(nmol, count, replace=False)).astype(np.int32)
+
+
+def collect(inst, mols, tol: float = 1e-3, extra: int = 2):
+    """Descriptors and labels for the submatrices of `mols` (one batch on the GPU).
+
+    The label is log10 of the smallest starting eigenvalue that the plain FP32
+    Newton-Schulz iteration (Gershgorin scale, run to ||X^2 - I||_F <= tol plus
+    `extra` steps) would bring to tolerance in the number of steps it took.
+    Returns (features [K, NFEAT] float64, labels [K], plain iterations [K], ok [K]).
+    """
+    from .runner import Runner, plain_fp32_schedule
+    r = Runner(inst, mols=mols)
+    L.nolsm_build_submatrices(r.plans[0], r.dpat, r.H, r.S)
+    feat = features(r, 0, inst.mu).cpu().numpy().astype(np.float64)
+    r.run(sched=plain_fp32_schedule(tol=tol, extra=extra), energy=False)
+    st = r.stats_host()
+    ok = (st["status"] == 0) & (st["fell_back"] == 0)
+    lab = labels_from_plain_run(st["iters_lo"], extra, tol)
+    del r
+    return feat, lab, st["iters_lo"].astype(np.int32), ok
+
+
+def compare_schedules(inst, mols, model: "ScheduleMLP", lower_factor: float = 0.5):
+    """Plain FP32, default mixed and learned mixed on one batch of `mols`.
+
+    Returns a dict per schedule: mean low-precision and fallback iterations, sign
+    and GEMM time (HIP events), paper-convention sign-phase TFLOP/s, fallbacks, and
+    for the mixed forms the largest density difference, the energy difference per
+    atom of the sampled molecules together, and the largest single-molecule energy
+    difference per atom, all against the plain FP32 result of the same submatrices.
+    """
+    from .runner import Runner, default_mixed_schedule, plain_fp32_schedule
+    r = Runner(inst, mols=mols)
+    p = r.plans[0]
+    atoms = np.asarray(inst.atoms)[mols].astype(np.float64)
+    out, ref = {}, None
+    for name, sched, pred in (("plain_fp32", plain_fp32_schedule(), None),
+                              ("mixed_default", default_mixed_schedule(), None),
+                              ("mixed_learned", default_mixed_schedule(), model)):
+        r.run(sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)  # warm-up
+        L.nolsm_plan_get_timings(p, reset=True)
+        L.nolsm_plan_set_timing(p, True)
+        r.run(sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)
+        torch.cuda.synchronize()
+        tm = L.nolsm_plan_get_timings(p, reset=True).as_dict()
+        L.nolsm_plan_set_timing(p, False)
+        st = r.stats_host()
+        n3 = st["n"].astype(np.float64) ** 3
+        flops = float((4.0 * n3 * (st["iters_lo"] + st["iters_fb"])).sum())
+        rec = {"iters_lo_mean": float(st["iters_lo"].mean()),
+               "iters_fb_mean": float(st["iters_fb"].mean()),
+               "fallbacks": int(st["fell_back"].sum()),
+               "failed": int((st["status"] != 0).sum()),
+               "ms_sign": tm["ms_sign"], "ms_gemm": tm["ms_gemm"],
+               "sign_tflops": flops / (tm["ms_sign"] * 1e-3) / 1e12 if tm["ms_sign"] > 0 else None}
+        if ref is None:
+            ref = (r.D.clone(), st["tr_dh"].copy())
+        else:
+            rec["max_abs_dD_vs_plain"] = float((r.D - ref[0]).abs().max().item())
+            # energy of these molecules' columns per atom (the whole-system measure
+            # restricted to the sample), and the largest single-molecule error
+            rec["dE_per_atom_vs_plain"] = float(abs(np.sum(st["tr_dh"] - ref[1])) / atoms.sum())
+            rec["max_sub_dE_per_atom_vs_plain"] = float(np.max(np.abs(st["tr_dh"] - ref[1]) / atoms))
+        out[name] = rec
+    del r
+    return out
+
+
 def features(runner, batch_index: int, mu: float) -> torch.Tensor:
     """nolsm_features for one batch of a Runner (runs the FP64 set-up if needed)."""
     K = len(runner.batches[batch_index])

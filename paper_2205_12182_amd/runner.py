@@ -49,6 +49,8 @@ class Runner:
         self.plans = [L.nolsm_plan_create(self.hpat, b) for b in self.batches]
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
         self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        self.tables = [torch.empty(L.nolsm_plan_table_bytes(p), dtype=torch.uint8, device=device)
+                       for p in self.plans]
         self.stats = [torch.zeros(len(b) * L.STATS_DTYPE.itemsize, dtype=torch.uint8,
                                   device=device) for b in self.batches]
         self.col_traces = torch.zeros(2 * inst.nmol, dtype=torch.float64, device=device)
@@ -67,7 +69,7 @@ class Runner:
 
     def _bind(self, i):
         if self.bound != i:
-            L.nolsm_plan_bind(self.plans[i], self.workspace)
+            L.nolsm_plan_bind(self.plans[i], self.tables[i], self.workspace)
             self.bound = i
 
     def run_batch(self, i, mu, sched, predictor=None, lower_factor=0.5):
@@ -101,6 +103,27 @@ class Runner:
             self.run_batch(i, mu, sched, predictor, lower_factor)
         if energy:
             L.nolsm_energy(self.dpat, self.D, self.H, self.S, self.col_traces, self.out2)
+
+    def capture(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5):
+        """Record one whole step (every batch in turn, then the energy) as a HIP graph.
+
+        Every plan is bound once before the capture (the table uploads are not
+        capturable); inside the capture the batches take turns on the shared
+        workspace with host-only binds.  graph.replay() repeats the step on the
+        current contents of H, S with the captured mu and schedule.
+        """
+        for i in range(len(self.plans)):
+            self._bind(i)
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):            # warm-up outside the capture
+            self.run(mu, sched, energy, predictor, lower_factor)
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            self.run(mu, sched, energy, predictor, lower_factor)
+        return graph
 
     def check(self):
         """Status of every batch (after the last run): first failing code or OK."""

@@ -51,6 +51,27 @@ def test_plan_layout_c1():
         L.nolsm_plan_destroy(plan)
 
 
+def test_bind_checks_buffers_before_any_device_work():
+    """Null, short or misaligned buffers are refused before anything is enqueued
+    (the fake addresses below are never dereferenced)."""
+    inst = get_config("c1")
+    hp = L.HostPattern(inst)
+    plan = L.nolsm_plan_create(hp, np.arange(inst.nmol, dtype=np.int32))
+    try:
+        tb, wb = L.nolsm_plan_table_bytes(plan), L.nolsm_plan_workspace_bytes(plan)
+        assert tb > 0 and wb > tb
+        fake_t, fake_w = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 30)
+        bind = L.lib().nolsm_plan_bind
+        assert bind(plan, None, tb, fake_w, wb, None) == L.EINVAL
+        assert bind(plan, fake_t, tb - 1, fake_w, wb, None) == L.EWORKSPACE
+        assert "table buffer" in L.nolsm_last_error()
+        assert bind(plan, fake_t, tb, fake_w, wb - 1, None) == L.EWORKSPACE
+        assert bind(plan, ctypes.c_void_p((1 << 20) + 64), tb, fake_w, wb, None) == L.EWORKSPACE
+        assert "aligned" in L.nolsm_last_error()
+    finally:
+        L.nolsm_plan_destroy(plan)
+
+
 def test_plan_rejects_bad_molecule():
     inst = get_config("c1")
     hp = L.HostPattern(inst)

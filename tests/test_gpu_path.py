@@ -69,8 +69,10 @@ def test_gather_bit_exact(gpu_ok):
         assert info.own_lo == int(O.own_columns(inst, info.mol, offs)[0])
 
 
-def test_fp64_setup_identities(gpu_ok):
-    """L^-1 S L^-T = I and M = L^-1 H L^-T (exactly symmetric) in FP64."""
+def test_setup_identities(gpu_ok):
+    """L^-1 S L^-T = I in FP64; M = L^-1 H L^-T exactly symmetric and within the
+    FP32 rounding bound of its two products (operands rounded to FP32, FP32
+    accumulation over at most n terms each)."""
     inst = get_config("t_23")
     print_case("setup t_23")
     r = Runner(inst)
@@ -86,7 +88,9 @@ def test_fp64_setup_identities(gpu_ok):
         assert np.array_equal(Li, np.tril(Li))
         assert np.abs(Li @ Sk @ Li.T - np.eye(n)).max() < 1e-11
         assert np.array_equal(M, M.T)
-        assert np.abs(M[:n, :n] - Li @ Hk @ Li.T).max() < 1e-11
+        u = 2.0 ** -24
+        bound = (2 * n + 4) * u * (np.abs(Li) @ np.abs(Hk) @ np.abs(Li).T)
+        assert np.all(np.abs(M[:n, :n] - Li @ Hk @ Li.T) <= bound)
         assert not M[n:, :].any()
 
 
