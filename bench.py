@@ -41,14 +41,14 @@ def paper_flops(stats):
     return float((4.0 * n3 * (stats["iters_lo"] + stats["iters_fb"])).sum())
 
 
-def timed_steps(runner, sched, steps, L, torch):
+def timed_steps(runner, sched, steps, L, torch, predictor=None):
     for p in runner.plans:
         L.nolsm_plan_get_timings(p, reset=True)
         L.nolsm_plan_set_timing(p, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        runner.run(sched=sched)
+        runner.run(sched=sched, predictor=predictor)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     tot = {}
@@ -121,6 +121,9 @@ def main():
     ap.add_argument("--batch", type=int, default=1024)
     ap.add_argument("--iters", type=int, default=0, help="fixed FP16 iterations (0: to tolerance)")
     ap.add_argument("--prec", default="fp16")
+    ap.add_argument("--schedule", choices=("learned", "default"), default=None,
+                    help="learned: scaled iteration from the trained network's lower bound "
+                         "(the default when trained weights exist); default: unscaled")
     ap.add_argument("--plain-steps", type=int, default=1, help="timed steps of plain FP32 (0: skip)")
     ap.add_argument("--cpu-sample", type=int, default=40,
                     help="submatrices the oracle solves on the host (0: skip)")
@@ -137,7 +140,9 @@ def main():
 
     import torch
     from paper_2205_12182_amd import _lib as L
-    from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, plain_fp32_schedule
+    from paper_2205_12182_amd import learn
+    from paper_2205_12182_amd.runner import (Runner, default_mixed_schedule, learned_schedule,
+                                             plain_fp32_schedule)
     from workloads import get_config
     if not torch.cuda.is_available():
         print("no GPU: the benchmark needs an MI355X", file=sys.stderr)
@@ -152,12 +157,20 @@ def main():
     runner = Runner(inst, batch=args.batch)
     log(f"{len(runner.plans)} batches, workspace {runner.workspace.numel() / 2**30:.1f} GiB")
 
-    mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec)
+    weights = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
+    if args.schedule is None:
+        args.schedule = "learned" if (os.path.exists(weights) and not args.iters) else "default"
+    predictor = None
+    if args.schedule == "learned":
+        predictor = learn.ScheduleMLP.load(weights)
+        mixed = learned_schedule(prec=args.prec)
+    else:
+        mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec)
     for w in range(args.warmup):
-        runner.run(sched=mixed)
+        runner.run(sched=mixed, predictor=predictor)
         torch.cuda.synchronize()
         log(f"warmup {w} done")
-    wall, tm = timed_steps(runner, mixed, args.steps, L, torch)
+    wall, tm = timed_steps(runner, mixed, args.steps, L, torch, predictor)
     log(f"mixed: {wall * 1e3:.1f} ms/step  phases {json.dumps({k: round(v, 1) for k, v in tm.items()})}")
     st = runner.stats_host()
     e_mixed, n_mixed = runner.energy_host()
@@ -169,7 +182,7 @@ def main():
 
     graph = None
     if args.graph_steps > 0:
-        g = runner.capture(sched=mixed)
+        g = runner.capture(sched=mixed, predictor=predictor)
         g.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -188,6 +201,19 @@ def main():
         cpu, err = oracle_sample(inst, runner, O, args.cpu_sample, flops / K)
         log(f"cpu baseline: {json.dumps(cpu)}")
         log(f"error vs oracle: {json.dumps(err)}")
+    other = None
+    if args.schedule == "learned" and args.plain_steps > 0:
+        dflt = default_mixed_schedule(prec=args.prec)
+        runner.run(sched=dflt)
+        wall_d, tm_d = timed_steps(runner, dflt, 1, L, torch)
+        st_d = runner.stats_host()
+        other = {"ms_per_step": round(wall_d * 1e3, 2),
+                 "tflops": round(paper_flops(st_d) / wall_d / 1e12, 3),
+                 "sign_ms": round(tm_d["ms_sign"], 2),
+                 "iters_mean": round(float(st_d["iters_lo"].mean()), 2),
+                 "fallbacks": int(st_d["fell_back"].sum()),
+                 "energy_per_atom_diff_vs_learned": abs(runner.energy_host()[0] - e_mixed) / inst.natoms}
+        log(f"default schedule: {json.dumps(other)}")
     plain = None
     if args.plain_steps > 0:
         pl = plain_fp32_schedule()
@@ -231,7 +257,10 @@ def main():
                    "batch": args.batch,
                    "schedule": (f"{args.prec} Newton-Schulz " +
                                 (f"x{args.iters}" if args.iters else "to ||X^2-I||_F<=0.1 +1") +
-                                ", Gershgorin scale, FP32 panel step, FP64 set-up/traces"),
+                                (", learned lower bound -> scaled iteration (cap 16)"
+                                 if args.schedule == "learned" else ", unscaled") +
+                                ", Gershgorin scale, FP32 fallback and panel step, FP64 "
+                                "Cholesky/L^-1/D columns/traces, FP32 set-up products"),
                    "iters_mean": round(float(st["iters_lo"].mean()), 2),
                    "fallbacks": int(st["fell_back"].sum()),
                    "parallelism": "none (1 GPU)"},
@@ -241,6 +270,7 @@ def main():
         "energy": e_mixed, "electrons": n_mixed,
         "error_vs_oracle": err,
         "graph_replay": graph,
+        "default_schedule": other,
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": round(plain["ms_per_step"] / (wall * 1e3), 3) if plain else None,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_PEAK,

@@ -13,8 +13,10 @@
 // compiler's wait-count tracking sees which slot a fragment read depends on,
 // and the waits before each barrier are partial (only the stage about to be
 // consumed).  Within a row the chunks are stored XOR-permuted by
-// ((r >> 1) ^ (r >> 3)) & 3, which makes the 16-byte fragment reads free of
-// bank conflicts without padding.  Lane half h of an MFMA fragment takes chunks
+// (r ^ (r >> 2)) & 3, which makes the 16-byte fragment reads free of bank
+// conflicts without padding (measured with the hardware conflict counter: this
+// permutation reads as fast as linear addresses, while ((r >> 1) ^ (r >> 3)) & 3
+// costs 20% and 80-byte padded rows 60% extra LDS cycles).  Lane half h of an MFMA fragment takes chunks
 // 2 h and 2 h + 1 of its row; the k order inside a stage is therefore permuted
 // identically for A and B, which leaves the contraction unchanged.
 //
@@ -82,7 +84,7 @@ __device__ __forceinline__ TI *buf_ptr(char *ws, const SubDesc &d, int q) {
   return reinterpret_cast<TI *>(ws + d.off_lo + (int64_t)q * 4 * d.npad * d.npad);
 }
 
-__device__ __forceinline__ int chunk_swz(int r) { return ((r >> 1) ^ (r >> 3)) & 3; }
+__device__ __forceinline__ int chunk_swz(int r) { return (r ^ (r >> 2)) & 3; }
 
 // s_waitcnt immediate: wait until at most `vm` vector-memory operations are
 // outstanding and every LDS operation has completed (expcnt left alone).
@@ -187,11 +189,14 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   // and kt + 3 may stay in flight) and for this wave's reads of stage kt; after
   // the barrier every wave is done with slot kt % NSLOT, which takes stage
   // kt + NSLOT.  Stage kt + 1 is read into g while the MFMAs consume f.
-  // Instruction order inside a step (scheduling groups): one MFMA, two fragment
-  // reads and one LDS-destination load, repeated until the reads and loads are
-  // issued, then the remaining MFMAs; nothing moves across step boundaries.
+  // Instruction order inside a step (scheduling groups): the MFMAs are split into
+  // NVM equal groups; inside each group half the MFMAs, then NDS / NVM fragment
+  // reads and one LDS-destination load, then the other half.  The loads are
+  // spread evenly, so a load that waits for space in the address unit's queue
+  // delays few MFMAs; nothing moves across step boundaries.
   constexpr int NDS = 4 * BMB, NVM = 2 * LPS, NMF = BMB * BMB * Mfma<TI>::STEPS;
-  static_assert(NDS / 2 >= NVM && NMF >= NDS / 2, "step interleave");
+  constexpr int MPG = NMF / NVM;
+  static_assert(NDS % NVM == 0 && NMF % NVM == 0 && MPG >= 2, "step interleave");
   auto step = [&](const uint4 *next, uint4 *refill, int kt, Frag &f, Frag &g) {
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0((NSLOT - 2) * 2 * LPS));
@@ -209,12 +214,12 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
             acc[bm][bn] = Mfma<TI>::op(f.a[bm], f.b[bn], s, acc[bm][bn]);
     if (!PARTIAL) {
 #pragma unroll
-      for (int j = 0; j < NDS / 2; ++j) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);    // MFMA
-        __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);    // LDS read
-        if (j < NVM) __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);   // memory load
+      for (int j = 0; j < NVM; ++j) {
+        __builtin_amdgcn_sched_group_barrier(0x008, MPG / 2, 0);          // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x100, NDS / NVM, 0);        // LDS read
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                // memory load
+        __builtin_amdgcn_sched_group_barrier(0x008, MPG - MPG / 2, 0);    // MFMA
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, NMF - NDS / 2, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   };

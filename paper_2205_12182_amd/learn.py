@@ -205,14 +205,14 @@ def compare_schedules(inst, mols, model: "ScheduleMLP", lower_factor: float = 0.
     atom of the sampled molecules together, and the largest single-molecule energy
     difference per atom, all against the plain FP32 result of the same submatrices.
     """
-    from .runner import Runner, default_mixed_schedule, plain_fp32_schedule
+    from .runner import Runner, default_mixed_schedule, learned_schedule, plain_fp32_schedule
     r = Runner(inst, mols=mols)
     p = r.plans[0]
     atoms = np.asarray(inst.atoms)[mols].astype(np.float64)
     out, ref = {}, None
     for name, sched, pred in (("plain_fp32", plain_fp32_schedule(), None),
                               ("mixed_default", default_mixed_schedule(), None),
-                              ("mixed_learned", default_mixed_schedule(), model)):
+                              ("mixed_learned", learned_schedule(), model)):
         r.run(sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)  # warm-up
         L.nolsm_plan_get_timings(p, reset=True)
         L.nolsm_plan_set_timing(p, True)

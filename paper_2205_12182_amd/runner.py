@@ -25,6 +25,20 @@ def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallbac
                       panel_steps=panel_steps, scale=scale, lower=lower)
 
 
+# Cap of the low-precision phase under the learned (scaled) schedule.  The scaled
+# iteration reaches the tolerance from a lower bound l ~ 1e-6 in about 16 steps,
+# the unscaled one in about 30 (the default cap), so both send the same kind of
+# submatrix -- a tiny gap at mu, where FP16 rounding is amplified most -- to the
+# FP32 restart instead of accepting a low-precision result.
+LEARNED_CAP = 16
+
+
+def learned_schedule(panel_steps=1, prec="fp16", fallback_iters=60, tol=0.1):
+    """The mixed schedule used with a learned lower bound (Runner.run(predictor=...))."""
+    return default_mixed_schedule(panel_steps=panel_steps, prec=prec,
+                                  fallback_iters=fallback_iters, tol=tol, cap=LEARNED_CAP)
+
+
 def plain_fp32_schedule(tol=1e-3, extra=2, cap=100):
     """Plain FP32 Newton-Schulz to convergence (no panel step, no fallback)."""
     return L.schedule([("fp32", cap, tol, extra)], fallback_iters=0, panel_steps=0)
