@@ -183,22 +183,24 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
   acc_foreach(acc, [&](int r, int c, double v) { Sb[(int64_t)(j + c) * ld + i0 + r] = v; });
 }
 
+// A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s] on the 64 x 64 tiles (ti, tj) with
+// tj in [cb0, cb1) and ti >= tj (lower tiles only).  blockIdx.x enumerates the
+// rectangle ti in [cb0, nb_max), tj in [cb0, cb1) column by column; tiles above
+// the diagonal or beyond this submatrix exit at once.
 __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restrict__ desc,
-                                                          char *ws, int jb) {
+                                                          char *ws, int k0, int k1, int cb0,
+                                                          int cb1, int rows) {
   SUB_PTRS
-  const int j = jb * NB, m0 = j + NB;
-  if (m0 >= ld) return;
-  const int T = (ld - m0) / 64;
-  int ti, tj;
-  tri_index(blockIdx.x, ti, tj);
-  if (ti >= T) return;
-  const int r0 = m0 + ti * 64, c0 = m0 + tj * 64;
+  const int ti = cb0 + (int)blockIdx.x % rows, tj = cb0 + (int)blockIdx.x / rows;
+  const int nb = ld / 64;
+  if (ti < tj || ti >= nb || tj >= nb || k0 >= ld) return;
+  const int r0 = ti * 64, c0 = tj * 64;
   __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
-  // C(r, c) -= sum_s P(r0 + r, s) P(c0 + c, s);  B(k=s, n=c) = S[(j+s)*ld + c0 + c]
-  gemm64_f64<true>(Sb + (int64_t)j * ld + r0, ld, Sb + (int64_t)j * ld + c0, ld, 0, NB, acc, sA,
-                   sB);
+  // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
+  gemm64_f64<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0, k1 - k0,
+                   acc, sA, sB);
   acc_foreach(acc, [&](int r, int c, double v) {
     double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
     *p = *p - v;
@@ -312,12 +314,28 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
                   char *ws, hipStream_t s) {
   const int nbmax = max_npad / NB;
   launch_reset_status(st, K, 0, s);
-  for (int jb = 0; jb < nbmax; ++jb) {
-    chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
-    const int rem = nbmax - jb - 1;
-    if (rem > 0) {
-      chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
-      chol_update_kernel<<<dim3(rem * (rem + 1) / 2, K), 256, 0, s>>>(desc, ws, jb);
+  // Right-looking blocked Cholesky with two levels: inside an outer block of OB
+  // columns the 64-wide steps update only the outer block's own columns; the
+  // trailing matrix receives the outer block's OB columns in one update (k = OB),
+  // which reads and writes it OB / 64 times less often.
+  constexpr int OBB = 4;                        // outer block = 4 x 64 columns
+  for (int J = 0; J < nbmax; J += OBB) {
+    const int Jend = J + OBB < nbmax ? J + OBB : nbmax;
+    for (int jb = J; jb < Jend; ++jb) {
+      chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
+      const int rem = nbmax - jb - 1;
+      if (rem > 0) {
+        chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
+        const int cb0 = jb + 1, cb1 = Jend, rows = nbmax - cb0;
+        if (cb1 > cb0)
+          chol_update_kernel<<<dim3(rows * (cb1 - cb0), K), 256, 0, s>>>(
+              desc, ws, jb * NB, (jb + 1) * NB, cb0, cb1, rows);
+      }
+    }
+    if (Jend < nbmax) {
+      const int rows = nbmax - Jend;
+      chol_update_kernel<<<dim3(rows * rows, K), 256, 0, s>>>(desc, ws, J * NB, Jend * NB, Jend,
+                                                              nbmax, rows);
     }
   }
   trtri_diag_kernel<<<dim3(nbmax, K), 256, 0, s>>>(desc, ws);
