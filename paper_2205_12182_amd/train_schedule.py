@@ -9,6 +9,9 @@ shift of S (the per-seed Lanczos estimate of lambda_min is too slow to repeat fo
 120 geometries; the shift keeps lambda_min(S) >= 0.1 for lambda_min(S0) >= -1.3,
 and a submatrix whose S_k is not positive definite is reported and left out).
 
+Further training geometries (--water-seeds): 2,048-molecule water boxes built like the
+4,096-molecule benchmark box, with a per-seed diagonal shift in [0.75, 1.5].
+
 Training data: for `per-seed` seeded molecules of each training geometry, the
 descriptors (nolsm_features) and the plain FP32 iteration count turned into a
 lower-bound label (learn.collect).  The network is trained on the GPU with the
@@ -36,6 +39,28 @@ import numpy as np
 
 SHIFT = 1.4
 WORKLOAD = "c3"
+# Additional training geometries: water boxes built like the 4,096-molecule benchmark
+# box (13+5+5 functions, r_c = 8 A) but with 2,048 molecules and a per-seed diagonal
+# shift drawn from [WATER_SHIFT_LO, WATER_SHIFT_HI], so that the network also sees
+# the pure-water environment and a range of overlap conditioning.
+WATER_NMOL = 2048
+WATER_SHIFT_LO, WATER_SHIFT_HI = 0.75, 1.5
+
+
+def water_shift(seed: int) -> float:
+    u = np.random.default_rng([0x5A1F, seed]).random()
+    return round(WATER_SHIFT_LO + (WATER_SHIFT_HI - WATER_SHIFT_LO) * u, 3)
+
+
+def build(kind: str, seed: int):
+    from workloads import get_config
+    from workloads.water import water_box
+    if kind == "water":
+        return water_box(WATER_NMOL, (13, 5, 5), 8.0, seed=seed, shift=water_shift(seed),
+                         name=f"water{WATER_NMOL}")
+    if kind == "c2":
+        return get_config("c2")
+    return get_config(WORKLOAD, seed=seed, shift=SHIFT)
 
 
 def _range(s: str):
@@ -45,17 +70,16 @@ def _range(s: str):
 
 # ----------------------------------------------------------------- worker tasks
 
-def _collect_task(seed, per_seed, tol, extra):
-    from workloads import get_config
+def _collect_task(seed, per_seed, tol, extra, kind="slab"):
     from . import learn
     t0 = time.perf_counter()
-    inst = get_config(WORKLOAD, seed=seed, shift=SHIFT)
+    inst = build(kind, seed)
     t1 = time.perf_counter()
     mols = learn.pick_molecules(inst.nmol, per_seed, seed)
     feat, lab, iters, ok = learn.collect(inst, mols, tol=tol, extra=extra)
     dims = inst.submatrix_dims()[mols]
-    return {"seed": seed, "mols": mols, "n": dims, "feat": feat, "label": lab, "iters": iters,
-            "ok": ok, "t_build": t1 - t0, "t_gpu": time.perf_counter() - t1}
+    return {"seed": seed, "kind": kind, "mols": mols, "n": dims, "feat": feat, "label": lab,
+            "iters": iters, "ok": ok, "t_build": t1 - t0, "t_gpu": time.perf_counter() - t1}
 
 
 def _train_task(x, t, steps, lr, seed):
@@ -69,14 +93,14 @@ def _train_task(x, t, steps, lr, seed):
     return {"params": m.params.cpu().numpy(), "loss": hist, "t_train": dt, "pred": pred}
 
 
-def _eval_task(seed, per_seed, params, lower_factor):
-    from workloads import get_config
+def _eval_task(seed, per_seed, params, lower_factor, kind="slab"):
     from . import learn
-    inst = get_config(WORKLOAD, seed=seed, shift=SHIFT)
+    inst = build(kind, seed)
     mols = learn.pick_molecules(inst.nmol, per_seed, seed, salt=0xE7A1)
     model = learn.ScheduleMLP(nout=1, params=params)
     res = learn.compare_schedules(inst, mols, model, lower_factor=lower_factor)
     res["seed"] = seed
+    res["kind"] = kind
     res["n_mean"] = float(inst.submatrix_dims()[mols].mean())
     return res
 
@@ -87,6 +111,10 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--train", default="0:100", help="training seeds a:b")
     ap.add_argument("--eval", default="100:120", help="evaluation seeds a:b")
+    ap.add_argument("--water-seeds", default="1:41",
+                    help="additional training water boxes a:b (empty: none)")
+    ap.add_argument("--c2-check", type=int, default=64,
+                    help="also evaluate on this many molecules of the 4,096-molecule box (0: skip)")
     ap.add_argument("--per-seed", type=int, default=32)
     ap.add_argument("--eval-per-seed", type=int, default=64)
     ap.add_argument("--workers", type=int, default=6)
@@ -115,15 +143,18 @@ def main(argv=None):
         else:
             futs = [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra)
                     for s in _range(args.train)]
+            if args.water_seeds:
+                futs += [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra, "water")
+                         for s in _range(args.water_seeds)]
         data = []
         for f in cf.as_completed(futs):
             r = f.result()
             data.append(r)
-            say(f"collected seed {r['seed']}: {int(r['ok'].sum())}/{len(r['ok'])} usable, "
+            say(f"collected {r['kind']} seed {r['seed']}: {int(r['ok'].sum())}/{len(r['ok'])} usable, "
                 f"plain iters {r['iters'].min()}-{r['iters'].max()}, build {r['t_build']:.1f} s, "
                 f"gpu {r['t_gpu']:.1f} s  ({len(data)}/{len(futs)})")
         if not args.eval_only:
-            data.sort(key=lambda r: r["seed"])
+            data.sort(key=lambda r: (r["kind"], r["seed"]))
             x = np.concatenate([r["feat"][r["ok"]] for r in data])
             t = np.concatenate([r["label"][r["ok"]] for r in data])
             say(f"training on {len(x)} submatrices, label log10 l in [{t.min():.2f}, {t.max():.2f}]")
@@ -133,6 +164,8 @@ def main(argv=None):
                 f"{tr['loss'][-1]:.4f}, train rms {np.sqrt(np.mean(resid ** 2)):.3f} (log10)")
         efuts = [pool.submit(_eval_task, s, args.eval_per_seed, tr["params"], args.lower_factor)
                  for s in _range(args.eval)]
+        c2fut = (pool.submit(_eval_task, 0, args.c2_check, tr["params"], args.lower_factor, "c2")
+                 if args.c2_check > 0 else None)
         evals = []
         for f in cf.as_completed(efuts):
             r = f.result()
@@ -140,6 +173,11 @@ def main(argv=None):
             say(f"evaluated seed {r['seed']}: iters plain {r['plain_fp32']['iters_lo_mean']:.2f} "
                 f"default {r['mixed_default']['iters_lo_mean']:.2f} "
                 f"learned {r['mixed_learned']['iters_lo_mean']:.2f}  ({len(evals)}/{len(efuts)})")
+        c2res = c2fut.result() if c2fut is not None else None
+        if c2res is not None:
+            say(f"4,096-molecule box: iters plain {c2res['plain_fp32']['iters_lo_mean']:.2f} "
+                f"default {c2res['mixed_default']['iters_lo_mean']:.2f} "
+                f"learned {c2res['mixed_learned']['iters_lo_mean']:.2f}")
     evals.sort(key=lambda r: r["seed"])
 
     def agg(name, key, fn=np.mean):
@@ -174,6 +212,8 @@ def main(argv=None):
                 "eval_seeds": args.eval, "per_seed": args.per_seed, "samples": int(len(x)),
                 "steps": args.steps, "lr": args.lr, "tol": args.tol, "extra": args.extra,
                 "lower_factor": args.lower_factor, "eval_per_seed": args.eval_per_seed,
+                "water_seeds": args.water_seeds, "water_nmol": WATER_NMOL,
+                "water_shift_range": [WATER_SHIFT_LO, WATER_SHIFT_HI],
                 "loss_first_last": [float(tr["loss"][0]), float(tr["loss"][-1])],
                 "train_rms_log10": float(np.sqrt(np.mean(resid ** 2)))}
         p = np.asarray(tr["params"], np.float32)
@@ -182,7 +222,7 @@ def main(argv=None):
         np.savez(args.out, params=p, nout=np.int32(1), sha256=np.array(digest),
                  meta=np.array(repr(meta)))
     report = {"meta": meta, "sha256": digest, "summary": summary, "per_seed": evals,
-              "wall_s": time.perf_counter() - t_all}
+              "box_4096": c2res, "wall_s": time.perf_counter() - t_all}
     rpath = os.path.splitext(args.out)[0] + "_report.json"
     with open(rpath, "w") as fh:
         json.dump(report, fh, indent=1, default=lambda o: o.tolist() if hasattr(o, "tolist") else str(o))
