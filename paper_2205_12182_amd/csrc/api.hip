@@ -141,18 +141,21 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
   // tiles of the symmetric sign-iteration products: upper triangle; small
   // submatrices use 128 x 128 tiles, the rest 256 x 256.  Executed flops skip the
   // 32 x 32 blocks that lie entirely in the padding.
-  // list 0: small submatrices, 128 tiles; list 1: large, 256 tiles; list 2: large, 128 tiles;
-  // list 3: every submatrix, every 128 tile (not only the upper triangle)
+  // list 0: small submatrices, 128 x 128 tiles; list 1: large, 256 x 128 tiles (rows x
+  // columns; kept when the tile reaches the upper triangle, 2 ti <= tj); list 2: large,
+  // 128 x 128 tiles (FP32); list 3: every submatrix, every 128 x 128 tile (not only the
+  // upper triangle)
   for (int list = 0; list < 4; ++list) {
-    const int T = list == 1 ? 256 : 128;
+    const int TR = list == 1 ? 256 : 128, TC = 128;
     for (int i = 0; i < K; ++i) {
       const int np = p->desc[i].npad;
       if (list < 3 && (np >= BIG_TILE_MIN_NPAD) != (list != 0)) continue;
-      const int nt = (np + T - 1) / T;
-      for (int ti = 0; ti < nt; ++ti)
-        for (int tj = list == 3 ? 0 : ti; tj < nt; ++tj) {
+      const int ntr = (np + TR - 1) / TR, ntc = (np + TC - 1) / TC;
+      for (int ti = 0; ti < ntr; ++ti)
+        for (int tj = 0; tj < ntc; ++tj) {
+          if (list != 3 && TR * ti > TC * tj + TC - 1) continue;    // below the diagonal
           p->tiles.push_back(Tile{i, ti, tj, 0});
-          const double rows = std::min(T, np - ti * T), cols = std::min(T, np - tj * T);
+          const double rows = std::min(TR, np - ti * TR), cols = std::min(TC, np - tj * TC);
           if (list < 2) p->gemm_flop += 2.0 * rows * cols * (double)np;
         }
     }

@@ -59,10 +59,9 @@ struct SubState {
 struct Tile { int32_t sub, ti, tj, pad; };
 
 // Tile lists: upper-triangle tiles of the symmetric products, t[0] the small
-// submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 256 tiles (FP16 and
-// BF16), t[2] the large ones in 128 x 128 tiles (FP32, whose 256 x 256 tile does
-// not fit the register file); t[3] every 128 x 128 tile of every submatrix (the
-// non-symmetric set-up product).
+// submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 128 tiles (FP16 and
+// BF16, two workgroups per CU), t[2] the large ones in 128 x 128 tiles (FP32);
+// t[3] every 128 x 128 tile of every submatrix (the non-symmetric set-up product).
 struct TileSet {
   const Tile *t[4];
   int n[4];
@@ -71,7 +70,7 @@ struct TileSet {
 // 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad
 // are multiples of these, so the count is exact)
 constexpr double FLOP_UNIT = 131072.0;
-constexpr int BIG_TILE_MIN_NPAD = 768;   // submatrices at least this large use 256 x 256 tiles
+constexpr int BIG_TILE_MIN_NPAD = 768;   // submatrices at least this large use 256 x 128 tiles
 
 // Host-side record of HIP event pairs around launch groups (measurement only).
 enum TimeCat { T_GATHER = 0, T_SETUP, T_SIGN, T_GEMM, T_PANEL, T_SCATTER, T_NCAT };

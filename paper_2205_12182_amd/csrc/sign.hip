@@ -21,6 +21,7 @@
 #include <type_traits>
 
 #include "ns_gemm.h"
+#include "ns_gemm_rect.h"
 
 namespace nolsm {
 
@@ -289,8 +290,9 @@ static void launch_ns_gemm_t(const TileSet &ts, const SubDesc *desc, SubState *s
       ns_gemm_kernel<TI, EPI, 2><<<ts.n[2], 256, 0, s>>>(ts.t[2], desc, st, ws, prec,
                                                          ts.flop_units);
   } else if (ts.n[1] > 0) {
-    ns_gemm_kernel<TI, EPI, (std::is_same<TI, float>::value ? 2 : 4)>
-        <<<ts.n[1], 256, 0, s>>>(ts.t[1], desc, st, ws, prec, ts.flop_units);
+    ns_gemm_rect_kernel<typename std::conditional<std::is_same<TI, float>::value, _Float16,
+                                                  TI>::type,
+                        EPI><<<ts.n[1], 256, 0, s>>>(ts.t[1], desc, st, ws, prec, ts.flop_units);
   }
 }
 
