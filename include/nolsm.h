@@ -146,6 +146,22 @@ typedef struct nolsm_plan nolsm_plan;
  * sizes, member lists and the GEMM tile work lists (host memory). */
 nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
                                int32_t K, nolsm_plan **plan /*host out*/);
+
+/* Planning options (GEMM performance depends on the submatrix size, Sec. III-B,
+ * Table II).  big_tile_min_npad: submatrices whose padded dimension is at least
+ * this use the 256 x 128 FP16/BF16 tiles (two workgroups per CU), smaller ones
+ * 128 x 128 tiles; a negative value selects the library default (768).  The
+ * value normally comes from the autotuner's measurement of both kernels. */
+typedef struct {
+  int32_t big_tile_min_npad;
+  int32_t reserved[7];            /* must be zero */
+} nolsm_plan_options;
+
+/* nolsm_plan_create with options (host pointer; NULL = defaults).
+ * NOLSM_EINVAL if a reserved field is non-zero. */
+nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
+                                  int32_t K, const nolsm_plan_options *options /*host*/,
+                                  nolsm_plan **plan /*host out*/);
 void nolsm_plan_destroy(nolsm_plan *plan);
 
 /* Device workspace bytes the plan needs: a 256-byte header shared by every plan

@@ -55,6 +55,10 @@ class SubInfo(ctypes.Structure):
                 ("off_dcol", ctypes.c_int64)]
 
 
+class PlanOptions(ctypes.Structure):
+    _fields_ = [("big_tile_min_npad", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+
+
 class Timings(ctypes.Structure):
     _fields_ = [("ms_gather", ctypes.c_double), ("ms_setup", ctypes.c_double),
                 ("ms_sign", ctypes.c_double), ("ms_gemm", ctypes.c_double),
@@ -88,6 +92,7 @@ def lib():
     P = ctypes.POINTER
     sigs = {
         "nolsm_plan_create": (i32, [P(Pattern), vp, i32, P(vp)]),
+        "nolsm_plan_create_ex": (i32, [P(Pattern), vp, i32, P(PlanOptions), P(vp)]),
         "nolsm_plan_destroy": (None, [vp]),
         "nolsm_plan_workspace_bytes": (sz, [vp]),
         "nolsm_plan_table_bytes": (sz, [vp]),
@@ -119,7 +124,7 @@ def lib():
     return L
 
 
-EXPORTED = ("nolsm_plan_create", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
+EXPORTED = ("nolsm_plan_create", "nolsm_plan_create_ex", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
             "nolsm_plan_table_bytes", "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
             "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_check",
             "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings",
@@ -198,11 +203,18 @@ def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=N
 
 # ----------------------------------------------------------------------------- entry points
 
-def nolsm_plan_create(host_pattern: HostPattern, mols) -> ctypes.c_void_p:
+def nolsm_plan_create(host_pattern: HostPattern, mols, big_tile_min_npad=None) -> ctypes.c_void_p:
+    """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy."""
     mols = np.ascontiguousarray(mols, dtype=np.int32)
     out = ctypes.c_void_p()
-    _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
-                                int(mols.size), ctypes.byref(out)))
+    if big_tile_min_npad is None:
+        _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
+                                    int(mols.size), ctypes.byref(out)))
+    else:
+        opt = PlanOptions()
+        opt.big_tile_min_npad = int(big_tile_min_npad)
+        _ok(lib().nolsm_plan_create_ex(ctypes.byref(host_pattern.struct), mols.ctypes.data,
+                                       int(mols.size), ctypes.byref(opt), ctypes.byref(out)))
     return out
 
 

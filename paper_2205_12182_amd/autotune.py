@@ -1,0 +1,97 @@
+"""Tile-shape autotuner for the sign-iteration GEMM.
+
+    python -m paper_2205_12182_amd.autotune --out paper_2205_12182_amd/data/tile_policy.json
+
+GEMM throughput depends on the submatrix size (paper, Sec. III-B and Table II).  For a
+sweep of sizes (water boxes of 1,024 molecules with 13+5+5 functions and a range of
+cutoff radii), the FP16 products of a fixed number of Newton-Schulz iterations are
+timed with every submatrix on 128 x 128 tiles and with every submatrix on 256 x 128
+tiles (HIP events around each launch; executed MFMA flops from the device counter).
+The policy is the smallest padded dimension from which the 256 x 128 kernel is faster
+at every measured size above it; the table of rates (this GPU's p(n)) is stored with
+it.  Runner applies the stored policy to every plan it creates.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+RADII = (4.5, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5, 8.0, 9.0, 10.0)
+NMOL, SHIFT, ITERS = 1024, 1.5, 4
+NEVER = 1 << 20
+
+
+def measure(r_cut: float, batch: int, say) -> dict:
+    import torch
+    from . import _lib as L
+    from .runner import Runner
+    from workloads.water import water_box
+    inst = water_box(NMOL, (13, 5, 5), r_cut, seed=7, shift=SHIFT, name="tune")
+    dims = inst.submatrix_dims()
+    npad = int((dims.max() + 63) // 64 * 64)
+    # keep the workspace (28 bytes per padded element and submatrix) near 60 GB
+    batch = max(64, min(batch, int(60e9 // (28 * npad * npad))))
+    mols = np.arange(min(batch, inst.nmol), dtype=np.int32)
+    sched = L.schedule([("fp16", ITERS, 0.0, 0)], fallback_iters=0, panel_steps=0)
+    rec = {"r_cut": r_cut, "submatrices": int(mols.size), "n_mean": float(dims[mols].mean()),
+           "npad_mean": float(((dims[mols] + 63) // 64 * 64).mean())}
+    for name, big in (("tile128", NEVER), ("tile256x128", 0)):
+        r = Runner(inst, mols=mols, big_tile_min_npad=big)
+        p = r.plans[0]
+        r.run(sched=sched, energy=False)
+        torch.cuda.synchronize()
+        L.nolsm_plan_get_timings(p, reset=True)
+        L.nolsm_plan_set_timing(p, True)
+        for _ in range(2):
+            r.run(sched=sched, energy=False)
+        torch.cuda.synchronize()
+        t = L.nolsm_plan_get_timings(p, reset=True).as_dict()
+        L.nolsm_plan_set_timing(p, False)
+        rec[name] = {"tflops_executed": t["gemm_flop"] / (t["ms_gemm"] * 1e-3) / 1e12,
+                     "ms_per_launch": t["ms_gemm"] / max(t["n_gemm"], 1)}
+        del r
+    say(f"r_c {r_cut}: n {rec['n_mean']:.0f}  128x128 {rec['tile128']['tflops_executed']:.0f} TF/s"
+        f"  256x128 {rec['tile256x128']['tflops_executed']:.0f} TF/s")
+    return rec
+
+
+def choose(recs) -> int:
+    """Smallest mean padded size from which the large tiles win at every larger size."""
+    recs = sorted(recs, key=lambda r: r["npad_mean"])
+    big_min = NEVER
+    for r in reversed(recs):
+        if r["tile256x128"]["tflops_executed"] > r["tile128"]["tflops_executed"]:
+            big_min = int(r["npad_mean"] // 64 * 64)
+        else:
+            break
+    return big_min
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--batch", type=int, default=512, help="submatrices per measurement")
+    args = ap.parse_args(argv)
+
+    def say(msg):
+        print(f"[autotune] {msg}", flush=True)
+
+    t0 = time.perf_counter()
+    recs = [measure(rc, args.batch, say) for rc in RADII]
+    big_min = choose(recs)
+    out = {"big_tile_min_npad": big_min, "iterations": ITERS, "batch": args.batch,
+           "measurements": recs, "wall_s": time.perf_counter() - t0}
+    os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
+    with open(args.out, "w") as fh:
+        json.dump(out, fh, indent=1)
+    say(f"big_tile_min_npad = {big_min}; wrote {args.out}")
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

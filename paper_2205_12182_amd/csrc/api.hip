@@ -86,8 +86,20 @@ const char *nolsm_last_error(void) { return g_err.c_str(); }
 
 nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, int32_t K,
                                nolsm_plan **out) {
+  return nolsm_plan_create_ex(pat, mols, K, nullptr, out);
+}
+
+nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols, int32_t K,
+                                  const nolsm_plan_options *opt, nolsm_plan **out) {
   if (!pat || !out || (K > 0 && !mols) || K < 0)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: null argument or K < 0");
+  int big_min = BIG_TILE_MIN_NPAD;
+  if (opt) {
+    for (int i = 0; i < 7; ++i)
+      if (opt->reserved[i] != 0)
+        return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: reserved option field %d is not zero", i);
+    if (opt->big_tile_min_npad >= 0) big_min = opt->big_tile_min_npad;
+  }
   if (!pat->blk_dim || !pat->blk_off || !pat->colptr || !pat->rowblk || !pat->valoff)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: pattern arrays must be set (host copies)");
   nolsm_plan *p = new (std::nothrow) nolsm_plan;
@@ -149,7 +161,7 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pat, const int32_t *mols, in
     const int TR = list == 1 ? 256 : 128, TC = 128;
     for (int i = 0; i < K; ++i) {
       const int np = p->desc[i].npad;
-      if (list < 3 && (np >= BIG_TILE_MIN_NPAD) != (list != 0)) continue;
+      if (list < 3 && (np >= big_min) != (list != 0)) continue;
       const int ntr = (np + TR - 1) / TR, ntc = (np + TC - 1) / TC;
       for (int ti = 0; ti < ntr; ++ti)
         for (int tj = 0; tj < ntc; ++tj) {

@@ -44,8 +44,20 @@ def plain_fp32_schedule(tol=1e-3, extra=2, cap=100):
     return L.schedule([("fp32", cap, tol, extra)], fallback_iters=0, panel_steps=0)
 
 
+def tuned_tile_policy():
+    """big_tile_min_npad from the autotuner's table (data/tile_policy.json), or None."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tile_policy.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        return int(json.load(fh)["big_tile_min_npad"])
+
+
 class Runner:
-    def __init__(self, inst, batch: int | None = None, mols=None, device="cuda"):
+    def __init__(self, inst, batch: int | None = None, mols=None, device="cuda",
+                 big_tile_min_npad="tuned"):
         if not torch.cuda.is_available():
             raise RuntimeError("the NOLSM path runs on the GPU only")
         L.lib()
@@ -60,7 +72,10 @@ class Runner:
         self.mols = mols
         batch = len(mols) if batch is None else batch
         self.batches = [mols[i:i + batch] for i in range(0, len(mols), batch)]
-        self.plans = [L.nolsm_plan_create(self.hpat, b) for b in self.batches]
+        if big_tile_min_npad == "tuned":
+            big_tile_min_npad = tuned_tile_policy()
+        self.big_tile_min_npad = big_tile_min_npad
+        self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad) for b in self.batches]
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
         self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
         self.tables = [torch.empty(L.nolsm_plan_table_bytes(p), dtype=torch.uint8, device=device)

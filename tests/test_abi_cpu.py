@@ -72,6 +72,28 @@ def test_bind_checks_buffers_before_any_device_work():
         L.nolsm_plan_destroy(plan)
 
 
+def test_plan_options_tile_policy():
+    """The tile policy changes the tile lists (so the table size); reserved fields must be zero."""
+    inst = get_config("t_23")
+    hp = L.HostPattern(inst)
+    mols = np.arange(inst.nmol, dtype=np.int32)
+    sizes = []
+    for big in (None, 0, 1 << 20):
+        plan = L.nolsm_plan_create(hp, mols, big)
+        sizes.append(L.nolsm_plan_table_bytes(plan))
+        L.nolsm_plan_destroy(plan)
+    # t_23 submatrices have npad < 768: the default and the "never" policy agree,
+    # "always large" produces different tile lists
+    assert sizes[0] == sizes[2] and sizes[1] != sizes[0]
+    opt = L.PlanOptions()
+    opt.big_tile_min_npad = 0
+    opt.reserved[3] = 1
+    out = ctypes.c_void_p()
+    rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
+                                      ctypes.byref(opt), ctypes.byref(out))
+    assert rc == L.EINVAL and "reserved" in L.nolsm_last_error()
+
+
 def test_plan_rejects_bad_molecule():
     inst = get_config("c1")
     hp = L.HostPattern(inst)

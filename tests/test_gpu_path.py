@@ -195,3 +195,17 @@ def test_nonconvergence_is_reported(gpu_ok):
     r = Runner(inst)
     r.run(sched=L.schedule([("fp32", 3, 1e-4, 2)], fallback_iters=0, panel_steps=0))
     assert r.check() == L.ENOCONV
+
+
+def test_tile_shapes_agree_bitwise(gpu_ok):
+    """256 x 128 and 128 x 128 tiles accumulate every element in the same order, so
+    the whole path gives bit-identical results under either tile policy."""
+    inst = get_config("t_23")
+    print_case("tile policies t_23")
+    out = []
+    for big in (0, 1 << 20):
+        r = Runner(inst, big_tile_min_npad=big)
+        r.run(sched=default_mixed_schedule())
+        assert r.check() == L.OK, L.nolsm_last_error()
+        out.append((r.D.clone(), r.energy_host()))
+    assert torch.equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
