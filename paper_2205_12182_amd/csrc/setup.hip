@@ -207,6 +207,90 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   });
 }
 
+// Trailing update of the outer Cholesky blocks on 128 x 128 tiles:
+//   A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s],  tiles (ti, tj) of 128 with ti >= tj
+// starting at row/column m0 (a multiple of 128).  A 64 x 64 FP64 tile reads
+// 6.5 flop per byte of its panels; the 128 x 128 tile doubles that and the next
+// k-stage is loaded into registers while the current one is multiplied (two LDS
+// buffers), with two workgroups per CU.  Wave w owns rows (w >> 1) * 64 and
+// columns (w & 1) * 64 as 4 x 4 blocks of 16 x 16 (layout as in gemm64_f64).
+constexpr int LDQ = 128 + 1;        // padded LDS row (doubles) of the 128-wide stages
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int m0,
+                       int rows) {
+  SUB_PTRS
+  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  if (ti < tj || k0 >= ld) return;
+  const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
+  if (r0 >= ld || c0 >= ld) return;
+  __shared__ double sA[2][KS64 * LDQ], sB[2][KS64 * LDQ];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  d4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  // element q of this thread's share of a stage: row m = idx & 127, k = idx >> 7
+  double ra[8], rb[8];
+  auto load = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q, m = idx & 127, kk = idx >> 7;
+      const int64_t o = (int64_t)(k + kk) * ld;
+      ra[q] = (r0 + m < ld) ? Sb[o + r0 + m] : 0.0;
+      rb[q] = (c0 + m < ld) ? Sb[o + c0 + m] : 0.0;
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int idx = tid + 256 * q, m = idx & 127, kk = idx >> 7;
+      sA[b][kk * LDQ + m] = ra[q];
+      sB[b][kk * LDQ + m] = rb[q];
+    }
+  };
+  load(k0);
+  store(0);
+  __syncthreads();
+  int b = 0;
+  for (int k = k0; k < k1; k += KS64) {
+    const bool more = k + KS64 < k1;
+    if (more) load(k + KS64);
+#pragma unroll
+    for (int kk = 0; kk < KS64; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      double a[4], bb[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = sA[b][kr * LDQ + wm + 16 * t + (lane & 15)];
+        bb[t] = sB[b][kr * LDQ + wn + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) store(b ^ 1);
+    __syncthreads();
+    b ^= 1;
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = r0 + wm + 16 * i + (lane >> 4) + 4 * q, c = c0 + wn + 16 * j + (lane & 15);
+        if (r < ld && c < ld) {
+          double *p = Sb + (int64_t)c * ld + r;
+          *p = *p - acc[i][j][q];
+        }
+      }
+}
+
 // ------------------------------------------------------------------ L^-1 in place
 
 __global__ __launch_bounds__(256) void trtri_diag_kernel(const SubDesc *__restrict__ desc,
@@ -333,9 +417,10 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
       }
     }
     if (Jend < nbmax) {
-      const int rows = nbmax - Jend;
-      chol_update_kernel<<<dim3(rows * rows, K), 256, 0, s>>>(desc, ws, J * NB, Jend * NB, Jend,
-                                                              nbmax, rows);
+      // Jend * 64 is a multiple of 256 here, so the 128-wide tiles start aligned
+      const int m0 = Jend * NB, rows = (max_npad - m0 + 127) / 128;
+      chol_trail_kernel<<<dim3(rows * rows, K), 256, 0, s>>>(desc, ws, J * NB, Jend * NB, m0,
+                                                             rows);
     }
   }
   trtri_diag_kernel<<<dim3(nbmax, K), 256, 0, s>>>(desc, ws);
