@@ -100,6 +100,25 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub):
     return cpu, err
 
 
+def measured_traffic(workload, schedule):
+    """HBM bytes per GEMM launch from the committed counter summary, if it was taken
+    for this kernel source, workload and schedule (otherwise None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "ns_gemm_rect_fp16_c2_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    h = hashlib.sha256()
+    for f in ("ns_gemm.h", "ns_gemm_rect.h"):
+        with open(os.path.join(ROOT, "paper_2205_12182_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if (h.hexdigest() != rec["kernel_sources_sha256"] or rec["workload"] != workload
+            or rec["schedule"] != schedule):
+        return None
+    return float(rec["per_launch_bytes"])
+
+
 def copy_calibration(torch, mib):
     """A plain elementwise copy of known size (read mib MiB, write mib MiB), run three
     times so that hardware byte counters can be scaled against it."""
@@ -274,8 +293,11 @@ def main():
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": round(plain["ms_per_step"] / (wall * 1e3), 3) if plain else None,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_PEAK,
-                     "unit": "TFLOP/s", "frac": round(achieved / FP16_PEAK, 4), "traffic": None,
-                     "kernel": "ns_gemm_kernel (symmetric upper-tile FP16 product)",
+                     "unit": "TFLOP/s", "frac": round(achieved / FP16_PEAK, 4),
+                     "traffic": measured_traffic(args.workload, args.schedule),
+                     "traffic_unit": "HBM bytes per launch (FETCH_SIZE x2.00 + WRITE_SIZE x1.00, "
+                                     "copy-calibrated; profiles/ns_gemm_rect_fp16_c2_traffic.json)",
+                     "kernel": "ns_gemm_rect_kernel (symmetric upper-tile FP16 product, 256x128 tiles)",
                      "launches_per_step": n_gemm,
                      "avg_launch_ms": round(gemm_ms / max(n_gemm, 1), 4),
                      "executed_flop_per_step": exec_flop_step,

@@ -133,7 +133,7 @@ typedef struct {
 typedef struct {
   int32_t n, npad, mol, m;        /* dimension, leading dimension, molecule, own columns */
   int32_t own_lo, nmem, pad0, pad1;
-  int64_t off_h;                  /* bytes: FP64 npad x npad, H_k then M_k (col major) */
+  int64_t off_h;                  /* bytes: H_k (FP64 npad x npad), then M_k (FP32)     */
   int64_t off_s;                  /* bytes: FP64 npad x npad, S_k then L^-1 (lower)    */
   int64_t off_lo;                 /* bytes: three npad x npad low-precision buffers     */
   int64_t off_dcol;               /* bytes: FP64 npad x m density columns               */

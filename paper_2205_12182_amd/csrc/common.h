@@ -30,7 +30,7 @@ enum Prec : int32_t { P_FP32 = 0, P_FP16 = 1, P_BF16 = 2 };
 struct SubDesc {
   int32_t n, npad, mol, m;          // dimension, leading dimension, molecule, own columns
   int32_t own_lo, nmem, mem_off, pad0;
-  int64_t off_h;                    // bytes from workspace base: FP64 npad^2 (H_k -> M_k)
+  int64_t off_h;                    // bytes from workspace base: FP64 npad^2 H_k, then FP32 M_k
   int64_t off_s;                    // FP64 npad^2 (S_k -> L -> L^-1)
   int64_t off_lo;                   // 3 x (4 npad^2) bytes: sign-iteration buffers / FP64 scratch
   int64_t off_diag;                 // FP64 2 x npad x NB: inverted diagonal blocks + panel temp

@@ -34,14 +34,14 @@ __global__ __launch_bounds__(256) void features_kernel(const SubDesc *__restrict
   const SubDesc d = desc[blockIdx.x];
   float *f = feat + (int64_t)blockIdx.x * NOLSM_NFEAT;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
   __shared__ ColAcc part[4];
   ColAcc a;
   acc_init(a);
   for (int c = w; c < d.n; c += 4) {
     double R = 0.0, f2 = 0.0, diag = 0.0;
     for (int r = lane; r < d.n; r += 64) {
-      double v = M[(int64_t)c * d.npad + r];
+      double v = (double)M[(int64_t)c * d.npad + r];
       if (r == c) { v -= mu; diag = v; } else R += fabs(v);
       f2 += v * v;
     }

@@ -378,11 +378,12 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
 }
 
 // Set-up products in FP32 (128 x 128 tiles), on the three FP32 buffers of the
-// iteration arena: buffer 0 = L^-T, buffer 1 = H (then M), buffer 2 = U.
+// iteration arena: buffer 0 = L^-T, buffer 1 = H, buffer 2 = U.
 //   PLAIN_FULL: U = H L^-T, every tile; L^-T(k, c) = 0 for k > c, so the
 //               contraction stops at the tile's last column.
-//   PLAIN_SYM:  M = L^-1 U (symmetric), upper tiles mirrored; L^-1(r, k) = 0 for
-//               k > r, so the contraction stops at the tile's last row.
+//   PLAIN_SYM:  M = L^-1 U (symmetric), upper tiles mirrored, written in FP32 over
+//               the FP64 H buffer (H is no longer needed); L^-1(r, k) = 0 for k > r,
+//               so the contraction stops at the tile's last row.
 template <int EPI>
 __global__ __launch_bounds__(256) void setup_gemm_kernel(const Tile *__restrict__ tiles,
                                                          const SubDesc *__restrict__ desc,
@@ -394,10 +395,11 @@ __global__ __launch_bounds__(256) void setup_gemm_kernel(const Tile *__restrict_
   const SubDesc d = desc[t.sub];
   const int ld = d.npad;
   float *Lt = buf_ptr<float>(ws, d, 0), *H = buf_ptr<float>(ws, d, 1), *U = buf_ptr<float>(ws, d, 2);
+  float *M = reinterpret_cast<float *>(ws + d.off_h);      // FP32 M over the FP64 H buffer
   const int i0 = t.ti * TILE, j0 = t.tj * TILE;
   const float *A = EPI == EPI_PLAIN_FULL ? H : Lt;
   const float *B = EPI == EPI_PLAIN_FULL ? Lt : U;
-  float *Out = EPI == EPI_PLAIN_FULL ? U : H;
+  float *Out = EPI == EPI_PLAIN_FULL ? U : M;
   const int kl = (EPI == EPI_PLAIN_FULL ? j0 : i0) + TILE;
   const int kend = kl < ld ? kl : ld;
   __shared__ uint4 s0[slot_u4<2>()], s1[slot_u4<2>()], s2[slot_u4<2>()], s3[slot_u4<2>()];

@@ -13,8 +13,7 @@
 //   trtri_*      L^-1 in place, block columns right to left            (FP64 MFMA)
 //   prep_products  L^-T and H rounded to FP32
 //   setup_gemm     U = H L^-T, then M = L^-1 U, upper tiles mirrored so that M is
-//                  exactly symmetric                                    (FP32 MFMA)
-//   widen_m        M to FP64 for the scaling and the first iterate
+//                  exactly symmetric; M is kept in FP32 over the H buffer (FP32 MFMA)
 // M only feeds the low-precision sign iteration and its scaling; the density
 // columns use the FP64 L^-1, so FP32 rounding in M (relative ~1e-7) stays far
 // below the FP16 rounding of the iteration.
@@ -369,16 +368,6 @@ __global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__res
   }
 }
 
-// M (FP32, buffer 1) widened to FP64 into the H buffer.
-__global__ __launch_bounds__(256) void widen_m_kernel(const SubDesc *__restrict__ desc,
-                                                      const SubState *__restrict__ st, char *ws) {
-  SUB_PTRS
-  if (st[blockIdx.y].status != 0) return;
-  const float *M32 = reinterpret_cast<const float *>(ws + d.off_lo) + (int64_t)ld * ld;
-  const int64_t tot = (int64_t)ld * ld;
-  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < tot; e += (int64_t)gridDim.x * 256)
-    Hb[e] = (double)M32[e];
-}
 
 
 // keep_spd = 0: clear every status (a new set-up); 1: clear only NOLSM_ENOCONV
@@ -438,7 +427,6 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     setup_gemm_kernel<EPI_PLAIN_SYM><<<ts.n[0], 256, 0, s>>>(ts.t[0], desc, st, ws);
   if (ts.n[2] > 0)
     setup_gemm_kernel<EPI_PLAIN_SYM><<<ts.n[2], 256, 0, s>>>(ts.t[2], desc, st, ws);
-  widen_m_kernel<<<dim3(256, K), 256, 0, s>>>(desc, st, ws);
 }
 
 }  // namespace nolsm

@@ -170,13 +170,13 @@ __global__ __launch_bounds__(256) void gersh_kernel(const SubDesc *__restrict__ 
                                                     double mu) {
   const SubDesc d = desc[blockIdx.y];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
   double best = 0.0;
   for (int c = blockIdx.x * 64 + w * 16; c < blockIdx.x * 64 + w * 16 + 16; ++c) {
     if (c >= d.n) break;
     double s = 0.0;
     for (int r = lane; r < d.n; r += 64) {
-      const double v = M[(int64_t)c * d.npad + r];
+      const double v = (double)M[(int64_t)c * d.npad + r];
       s += (r == c) ? fabs(v - mu) : fabs(v);
     }
     s = wave_sum(s);
@@ -216,10 +216,10 @@ __global__ void scale_init_kernel(const SubDesc *__restrict__ desc, SubState *__
 
 // X_0 = (M - mu I) / b in the submatrix's precision; zero outside n x n.
 template <typename TI>
-__device__ void cast_col(const double *M, TI *X, int n, int ld, int c, double mu, double inv_b) {
+__device__ void cast_col(const float *M, TI *X, int n, int ld, int c, double mu, double inv_b) {
   for (int r = threadIdx.x; r < ld; r += blockDim.x) {
     double v = 0.0;
-    if (r < n && c < n) v = (M[(int64_t)c * ld + r] - (r == c ? mu : 0.0)) * inv_b;
+    if (r < n && c < n) v = ((double)M[(int64_t)c * ld + r] - (r == c ? mu : 0.0)) * inv_b;
     X[(int64_t)c * ld + r] = from_f64<TI>(v);
   }
 }
@@ -232,7 +232,7 @@ __global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ d
   const int c = blockIdx.x;
   if (c >= d.npad || s.status != 0) return;
   if (only_fb && !s.fell_back) return;
-  const double *M = reinterpret_cast<const double *>(ws + d.off_h);
+  const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
   const double inv_b = 1.0 / s.scale;
   if (s.prec == P_FP32) cast_col<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
   else if (s.prec == P_FP16)

@@ -82,7 +82,7 @@ def test_setup_identities(gpu_ok):
         info = r.sub_info(0, i)
         npad, n = info.npad, info.n
         Li = col_major(r.ws_view(info.off_s, npad * npad, torch.float64), npad)[:n, :n]
-        M = col_major(r.ws_view(info.off_h, npad * npad, torch.float64), npad)
+        M = col_major(r.ws_view(info.off_h, npad * npad, torch.float32), npad).astype(np.float64)
         Hk, _ = O.gather(inst, inst.H_val, info.mol)
         Sk, _ = O.gather(inst, inst.S_val, info.mol)
         assert np.array_equal(Li, np.tril(Li))
