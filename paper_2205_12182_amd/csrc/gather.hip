@@ -23,7 +23,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
   const SubDesc d = desc[blockIdx.y];
   const int b = blockIdx.x;
   if (b > d.nmem) return;                       // b == nmem: padding columns
-  __shared__ int64_t s_t[GATHER_MAXMEM];        // block index of (J_a, J_b) or -1
+  __shared__ int64_t s_t[GATHER_MAXMEM];        // value offset of block (J_a, J_b) or -1
   __shared__ int32_t s_loc[GATHER_MAXMEM + 1];
   __shared__ int32_t s_dim[GATHER_MAXMEM];
   __shared__ uint16_t s_rowmem[GATHER_MAXN];    // row -> member
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
       const int64_t mid = (lo + hi) >> 1;
       if (rowblk[mid] < Ja) lo = mid + 1; else hi = mid;
     }
-    s_t[a] = (lo < c1 && rowblk[lo] == Ja) ? lo : -1;
+    s_t[a] = (lo < c1 && rowblk[lo] == Ja) ? valoff[lo] : -1;     // block values or absent
     s_loc[a] = mem_loc[d.mem_off + a];
     s_dim[a] = blk_dim[Ja];
   }
@@ -60,23 +60,25 @@ __global__ __launch_bounds__(256) void gather_kernel(
     for (int r = threadIdx.x; r < s_dim[a]; r += blockDim.x) s_rowmem[s_loc[a] + r] = (uint16_t)a;
   __syncthreads();
 
-  const int64_t total = (int64_t)ld * dJ;
-  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
-    const int c = (int)(e / ld);
-    const int i = (int)(e - (int64_t)c * ld);
-    const int64_t dst = (int64_t)(locb + c) * ld + i;
-    double h = 0.0, s = 0.0;
-    if (i < n) {
-      const int a = s_rowmem[i];
-      const int64_t t = s_t[a];
-      if (t >= 0) {
-        const int64_t src = valoff[t] + (int64_t)(i - s_loc[a]) + (int64_t)c * s_dim[a];
-        h = H_val[src];
-        s = S_val[src];
+  // column by column (32-bit index arithmetic, no per-element division); rows of
+  // one member are contiguous in both the stored block and the output column
+  for (int c = 0; c < dJ; ++c) {
+    double *hcol = Hk + (int64_t)(locb + c) * ld;
+    double *scol = Sk + (int64_t)(locb + c) * ld;
+    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
+      double h = 0.0, sv = 0.0;
+      if (i < n) {
+        const int a = s_rowmem[i];
+        const int64_t v0 = s_t[a];
+        if (v0 >= 0) {
+          const int64_t src = v0 + (i - s_loc[a]) + c * s_dim[a];
+          h = H_val[src];
+          sv = S_val[src];
+        }
       }
+      hcol[i] = h;
+      scol[i] = sv;
     }
-    Hk[dst] = h;
-    Sk[dst] = s;
   }
 }
 

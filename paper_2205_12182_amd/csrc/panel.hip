@@ -42,42 +42,24 @@ __global__ __launch_bounds__(256) void panel_v_kernel(const SubDesc *__restrict_
 constexpr int PANEL_ROWS = 128;
 constexpr int PANEL_K = 64;
 
-// One 16-byte piece of an X chunk per (thread, q): row idx / CPR, k-columns
-// (idx % CPR) * EPU .. + EPU - 1 of the PANEL_ROWS x PANEL_K chunk.
-template <typename TI> struct PanelChunk {
-  static constexpr int EPU = 16 / (int)sizeof(TI);             // elements per 16-byte load
-  static constexpr int CPR = PANEL_K / EPU;                    // loads per row
-  static constexpr int PER_T = PANEL_ROWS * CPR / 256;
-};
-
 template <typename TI>
-__device__ __forceinline__ void panel_fetch_x(const TI *__restrict__ X, int ld, int i0, int k0,
-                                              uint4 (&v)[PanelChunk<TI>::PER_T]) {
-  using C = PanelChunk<TI>;
+__device__ __forceinline__ void panel_load_x(const TI *__restrict__ X, int ld, int i0, int k0,
+                                             float (*sX)[PANEL_ROWS + 4]) {
+  constexpr int EPU = 16 / (int)sizeof(TI);                  // elements per 16-byte load
+  constexpr int CPR = PANEL_K / EPU;                         // loads per row
+  constexpr int PER_T = PANEL_ROWS * CPR / 256;
 #pragma unroll
-  for (int q = 0; q < C::PER_T; ++q) {
-    const int idx = threadIdx.x + 256 * q, row = idx / C::CPR, kc = idx % C::CPR;
-    v[q] = uint4{0u, 0u, 0u, 0u};
+  for (int q = 0; q < PER_T; ++q) {
+    const int idx = threadIdx.x + 256 * q, row = idx / CPR, kc = idx % CPR;
+    uint4 v = {0u, 0u, 0u, 0u};
     if (i0 + row < ld)
-      v[q] = *reinterpret_cast<const uint4 *>(X + (int64_t)(i0 + row) * ld + k0 + kc * C::EPU);
+      v = *reinterpret_cast<const uint4 *>(X + (int64_t)(i0 + row) * ld + k0 + kc * EPU);
+    const TI *e = reinterpret_cast<const TI *>(&v);
+#pragma unroll
+    for (int j = 0; j < EPU; ++j) sX[kc * EPU + j][row] = to_f32<TI>(e[j]);
   }
 }
 
-template <typename TI>
-__device__ __forceinline__ void panel_stage_x(const uint4 (&v)[PanelChunk<TI>::PER_T],
-                                              float (*sX)[PANEL_ROWS + 4]) {
-  using C = PanelChunk<TI>;
-#pragma unroll
-  for (int q = 0; q < C::PER_T; ++q) {
-    const int idx = threadIdx.x + 256 * q, row = idx / C::CPR, kc = idx % C::CPR;
-    const TI *e = reinterpret_cast<const TI *>(&v[q]);
-#pragma unroll
-    for (int j = 0; j < C::EPU; ++j) sX[kc * C::EPU + j][row] = to_f32<TI>(e[j]);
-  }
-}
-
-// The next chunk of X and P is loaded into registers while the current one is
-// multiplied from LDS, so the loads' latency overlaps the arithmetic.
 template <typename TI>
 __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict__ P,
                                const float *__restrict__ Q, float *__restrict__ O, int ld, int m,
@@ -86,36 +68,18 @@ __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * PANEL_ROWS;
   const int ti = tid & 31, tc = tid >> 5;         // rows 4 ti .. 4 ti + 3, columns 4 tc .. + 3
-  constexpr int PP = PANEL_K * MAXM / 256;        // P elements per thread and chunk
   float acc[4][4];
 #pragma unroll
   for (int r = 0; r < 4; ++r)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
-  uint4 xv[PanelChunk<TI>::PER_T];
-  float pv[PP];
-  auto fetch = [&](int k0) {
-    panel_fetch_x<TI>(X, ld, i0, k0, xv);
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      const int e = tid + 256 * q, kk = e % PANEL_K, c = e / PANEL_K;
-      pv[q] = c < m ? P[(int64_t)c * ld + k0 + kk] : 0.0f;
-    }
-  };
-  auto stage = [&]() {
-    panel_stage_x<TI>(xv, sX);
-#pragma unroll
-    for (int q = 0; q < PP; ++q) {
-      const int e = tid + 256 * q, kk = e % PANEL_K, c = e / PANEL_K;
-      sP[kk][c] = pv[q];
-    }
-  };
-  fetch(0);
-  stage();
-  __syncthreads();
   for (int k0 = 0; k0 < ld; k0 += PANEL_K) {
-    const bool more = k0 + PANEL_K < ld;
-    if (more) fetch(k0 + PANEL_K);
+    panel_load_x<TI>(X, ld, i0, k0, sX);
+    for (int e = tid; e < PANEL_K * MAXM; e += 256) {
+      const int kk = e % PANEL_K, c = e / PANEL_K;
+      sP[kk][c] = c < m ? P[(int64_t)c * ld + k0 + kk] : 0.0f;
+    }
+    __syncthreads();
 #pragma unroll 8
     for (int kk = 0; kk < PANEL_K; ++kk) {
       const float4 x = *reinterpret_cast<const float4 *>(&sX[kk][4 * ti]);
@@ -127,10 +91,6 @@ __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict
         for (int c = 0; c < 4; ++c) acc[r][c] += xs[r] * ps[c];
     }
     __syncthreads();
-    if (more) {
-      stage();
-      __syncthreads();
-    }
   }
 #pragma unroll
   for (int c = 0; c < 4; ++c) {

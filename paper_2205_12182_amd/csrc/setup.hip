@@ -37,44 +37,79 @@ template <bool TRANSB>
 __device__ __forceinline__ void gemm64_f64(const double *__restrict__ A, int64_t lda,
                                            const double *__restrict__ B, int64_t ldb, int k0,
                                            int k1, d4 acc[2][2], double *sA, double *sB) {
+  // sA, sB: two LDS buffers of KS64 x LDP each; the next k-stage is loaded into
+  // registers while the current one is multiplied.
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  for (int k = k0; k < k1; k += KS64) {
+  double ra[4], rb[4];
+  auto fetch = [&](int k) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {                      // A: 64 rows x 16 k
       const int m = tid & 63, kk = (tid >> 6) + 4 * q;
-      sA[kk * LDP + m] = A[(int64_t)(k + kk) * lda + m];
+      ra[q] = A[(int64_t)(k + kk) * lda + m];
     }
     if (!TRANSB) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {                    // B: contiguous in k
         const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
-        sB[kk * LDP + nn] = B[(int64_t)nn * ldb + k + kk];
+        rb[q] = B[(int64_t)nn * ldb + k + kk];
       }
     } else {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {                    // B: contiguous in n
         const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
-        sB[kk * LDP + nn] = B[(int64_t)(k + kk) * ldb + nn];
+        rb[q] = B[(int64_t)(k + kk) * ldb + nn];
       }
     }
-    __syncthreads();
+  };
+  auto stage = [&](int b) {
+    double *a = sA + b * KS64 * LDP, *bb = sB + b * KS64 * LDP;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
+      a[kk * LDP + m] = ra[q];
+    }
+    if (!TRANSB) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
+        bb[kk * LDP + nn] = rb[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
+        bb[kk * LDP + nn] = rb[q];
+      }
+    }
+  };
+  if (k0 >= k1) return;
+  fetch(k0);
+  stage(0);
+  __syncthreads();
+  int b = 0;
+  for (int k = k0; k < k1; k += KS64) {
+    const bool more = k + KS64 < k1;
+    if (more) fetch(k + KS64);
+    const double *a = sA + b * KS64 * LDP, *bb = sB + b * KS64 * LDP;
 #pragma unroll
     for (int kk = 0; kk < KS64; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[2], b[2];
+      double av[2], bv[2];
 #pragma unroll
       for (int t = 0; t < 2; ++t) {
-        a[t] = sA[kr * LDP + wm + 16 * t + (lane & 15)];
-        b[t] = sB[kr * LDP + wn + 16 * t + (lane & 15)];
+        av[t] = a[kr * LDP + wm + 16 * t + (lane & 15)];
+        bv[t] = bb[kr * LDP + wn + 16 * t + (lane & 15)];
       }
 #pragma unroll
       for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
         for (int bn = 0; bn < 2; ++bn)
-          acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bm], b[bn], acc[bm][bn], 0, 0, 0);
+          acc[bm][bn] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[bm], bv[bn], acc[bm][bn], 0, 0, 0);
     }
+    if (more) stage(b ^ 1);
     __syncthreads();
+    b ^= 1;
   }
 }
 
@@ -173,7 +208,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
   if (i0 >= ld) return;
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
   // out(r, c) = sum_s P(r, s) Linv_jj(c, s);  B(k=s, n=c) = Dinv[c + s*64]
@@ -194,7 +229,7 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   const int nb = ld / 64;
   if (ti < tj || ti >= nb || tj >= nb || k0 >= ld) return;
   const int r0 = ti * 64, c0 = tj * 64;
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
   // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
@@ -311,7 +346,7 @@ __global__ __launch_bounds__(256) void trtri_panel_kernel(const SubDesc *__restr
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
   if (i0 >= ld) return;
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
   gemm64_f64<false>(Sb + (int64_t)j * ld + i0, ld, Dinv + (int64_t)jb * NB * NB, NB, 0, NB, acc,
@@ -326,7 +361,7 @@ __global__ __launch_bounds__(256) void trtri_update_kernel(const SubDesc *__rest
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
   if (i0 >= ld) return;
-  __shared__ double sA[KS64 * LDP], sB[KS64 * LDP];
+  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
   gemm64_f64<false>(Sb + i0, ld, Tmp, ld, j + NB, i0 + 64, acc, sA, sB);
