@@ -151,10 +151,15 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
  * Table II).  big_tile_min_npad: submatrices whose padded dimension is at least
  * this use the 256 x 128 FP16/BF16 tiles (two workgroups per CU), smaller ones
  * 128 x 128 tiles; a negative value selects the library default (768).  The
- * value normally comes from the autotuner's measurement of both kernels. */
+ * value normally comes from the autotuner's measurement of both kernels.
+ * setup_products: how M_k = L^-1 T_k(H) L^-T is formed from the FP64 factor.
+ * 0 (default): FP16 MFMAs on split operands (x = hi + 2^-11 lo, three partial
+ * products, FP32 sums; every term within about 3 * 2^-22 of its exact value).
+ * 1: FP32 operands on FP32 MFMAs.  Other values: NOLSM_EINVAL. */
 typedef struct {
   int32_t big_tile_min_npad;
-  int32_t reserved[7];            /* must be zero */
+  int32_t setup_products;
+  int32_t reserved[6];            /* must be zero */
 } nolsm_plan_options;
 
 /* nolsm_plan_create with options (host pointer; NULL = defaults).

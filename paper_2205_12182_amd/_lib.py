@@ -56,7 +56,11 @@ class SubInfo(ctypes.Structure):
 
 
 class PlanOptions(ctypes.Structure):
-    _fields_ = [("big_tile_min_npad", ctypes.c_int32), ("reserved", ctypes.c_int32 * 7)]
+    _fields_ = [("big_tile_min_npad", ctypes.c_int32), ("setup_products", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
+
+
+SETUP_SPLIT_FP16, SETUP_FP32 = 0, 1
 
 
 class Timings(ctypes.Structure):
@@ -203,16 +207,19 @@ def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=N
 
 # ----------------------------------------------------------------------------- entry points
 
-def nolsm_plan_create(host_pattern: HostPattern, mols, big_tile_min_npad=None) -> ctypes.c_void_p:
-    """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy."""
+def nolsm_plan_create(host_pattern: HostPattern, mols, big_tile_min_npad=None,
+                      setup_products=None) -> ctypes.c_void_p:
+    """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy and
+    setup_products (optional) how M_k is formed (SETUP_SPLIT_FP16 or SETUP_FP32)."""
     mols = np.ascontiguousarray(mols, dtype=np.int32)
     out = ctypes.c_void_p()
-    if big_tile_min_npad is None:
+    if big_tile_min_npad is None and setup_products is None:
         _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                     int(mols.size), ctypes.byref(out)))
     else:
         opt = PlanOptions()
-        opt.big_tile_min_npad = int(big_tile_min_npad)
+        opt.big_tile_min_npad = -1 if big_tile_min_npad is None else int(big_tile_min_npad)
+        opt.setup_products = SETUP_SPLIT_FP16 if setup_products is None else int(setup_products)
         _ok(lib().nolsm_plan_create_ex(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                        int(mols.size), ctypes.byref(opt), ctypes.byref(out)))
     return out

@@ -15,7 +15,7 @@ void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mo
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
                    const double *S_val, char *ws, hipStream_t stream);
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  char *ws, hipStream_t s);
+                  bool fp32_products, char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                  char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
                  double flop, hipStream_t s);
@@ -43,8 +43,9 @@ struct nolsm_plan {
   int32_t max_npad = 0;
   std::vector<SubDesc> desc;
   std::vector<int32_t> mem_mol, mem_loc;
-  std::vector<Tile> tiles;      // the four tile lists of TileSet, back to back
-  int32_t list_end[4] = {0, 0, 0, 0};
+  std::vector<Tile> tiles;      // the tile lists of TileSet, back to back
+  int32_t list_end[NTILELIST] = {};
+  bool setup_fp32 = false;      // set-up products on FP32 MFMAs instead of split FP16
   // tables (bytes from the plan's table buffer)
   size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
   size_t tab_bytes = 0;
@@ -94,11 +95,16 @@ nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols,
   if (!pat || !out || (K > 0 && !mols) || K < 0)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: null argument or K < 0");
   int big_min = BIG_TILE_MIN_NPAD;
+  bool setup_fp32 = false;
   if (opt) {
-    for (int i = 0; i < 7; ++i)
+    for (int i = 0; i < 6; ++i)
       if (opt->reserved[i] != 0)
         return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: reserved option field %d is not zero", i);
+    if (opt->setup_products != 0 && opt->setup_products != 1)
+      return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: setup_products must be 0 or 1, got %d",
+                  opt->setup_products);
     if (opt->big_tile_min_npad >= 0) big_min = opt->big_tile_min_npad;
+    setup_fp32 = opt->setup_products == 1;
   }
   if (!pat->blk_dim || !pat->blk_off || !pat->colptr || !pat->rowblk || !pat->valoff)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: pattern arrays must be set (host copies)");
@@ -106,6 +112,7 @@ nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols,
   if (!p) return fail(NOLSM_ENOMEM, "nolsm_plan_create: out of host memory");
   p->K = K;
   p->nmol = pat->nmol;
+  p->setup_fp32 = setup_fp32;
   p->desc.resize(K);
   size_t off = 0;
   off += 0;  // offsets of tables are fixed after the member lists are known
@@ -156,16 +163,18 @@ nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols,
   // list 0: small submatrices, 128 x 128 tiles; list 1: large, 256 x 128 tiles (rows x
   // columns; kept when the tile reaches the upper triangle, 2 ti <= tj); list 2: large,
   // 128 x 128 tiles (FP32); list 3: every submatrix, every 128 x 128 tile (not only the
-  // upper triangle)
-  for (int list = 0; list < 4; ++list) {
-    const int TR = list == 1 ? 256 : 128, TC = 128;
+  // upper triangle); lists 4 and 5: every submatrix in 256 x 128 tiles, all of them
+  // (4) and the upper triangle (5), for the split-FP16 set-up products
+  for (int list = 0; list < NTILELIST; ++list) {
+    const int TR = (list == 1 || list >= 4) ? 256 : 128, TC = 128;
+    const bool every = list == 3 || list == 4;
     for (int i = 0; i < K; ++i) {
       const int np = p->desc[i].npad;
       if (list < 3 && (np >= big_min) != (list != 0)) continue;
       const int ntr = (np + TR - 1) / TR, ntc = (np + TC - 1) / TC;
       for (int ti = 0; ti < ntr; ++ti)
         for (int tj = 0; tj < ntc; ++tj) {
-          if (list != 3 && TR * ti > TC * tj + TC - 1) continue;    // below the diagonal
+          if (!every && TR * ti > TC * tj + TC - 1) continue;    // below the diagonal
           p->tiles.push_back(Tile{i, ti, tj, 0});
           const double rows = std::min(TR, np - ti * TR), cols = std::min(TC, np - tj * TC);
           if (list < 2) p->gemm_flop += 2.0 * rows * cols * (double)np;
@@ -286,7 +295,7 @@ nolsm_status nolsm_plan_query(const nolsm_plan *p, int32_t i, nolsm_sub_info *in
 
 static TileSet tile_set(const nolsm_plan *p, const Tile *tiles) {
   TileSet ts;
-  for (int l = 0; l < 4; ++l) {
+  for (int l = 0; l < NTILELIST; ++l) {
     const int b = l ? p->list_end[l - 1] : 0;
     ts.t[l] = tiles + b;
     ts.n[l] = p->list_end[l] - b;
@@ -344,7 +353,7 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   const TileSet ts = tile_set(p, tiles);
   if (!p->setup_done) {
     ev = p->log.begin(T_SETUP, s);
-    launch_setup(desc, st, p->K, p->max_npad, ts, p->ws, s);
+    launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, p->ws, s);
     p->log.end(ev, s);
     p->setup_done = true;
   }
@@ -366,7 +375,7 @@ nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   const int ev = p->log.begin(T_SETUP, s);
-  launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->ws, s);
+  launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->setup_fp32, p->ws, s);
   p->log.end(ev, s);
   p->setup_done = true;
   return hip_check("nolsm_setup_batched");

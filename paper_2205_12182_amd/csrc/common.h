@@ -61,10 +61,13 @@ struct Tile { int32_t sub, ti, tj, pad; };
 // Tile lists: upper-triangle tiles of the symmetric products, t[0] the small
 // submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 128 tiles (FP16 and
 // BF16, two workgroups per CU), t[2] the large ones in 128 x 128 tiles (FP32);
-// t[3] every 128 x 128 tile of every submatrix (the non-symmetric set-up product).
+// t[3] every 128 x 128 tile of every submatrix (the non-symmetric FP32 set-up
+// product); t[4] every 256 x 128 tile and t[5] the upper-triangle 256 x 128 tiles of
+// every submatrix (the split-FP16 set-up products).
+constexpr int NTILELIST = 6;
 struct TileSet {
-  const Tile *t[4];
-  int n[4];
+  const Tile *t[NTILELIST];
+  int n[NTILELIST];
   unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
 };
 // 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad

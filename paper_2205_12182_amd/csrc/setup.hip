@@ -11,14 +11,19 @@
 //   chol_panel   A[j+64:, j] <- A[j+64:, j] L_jj^-T                  (FP64 MFMA)
 //   chol_update  A[j+64:, j+64:] -= P P^T, lower tiles                 (FP64 MFMA)
 //   trtri_*      L^-1 in place, block columns right to left            (FP64 MFMA)
-//   prep_products  L^-T and H rounded to FP32
-//   setup_gemm     U = H L^-T, then M = L^-1 U, upper tiles mirrored so that M is
-//                  exactly symmetric; M is kept in FP32 over the H buffer (FP32 MFMA)
+//   prep_split     L^-1 and H split into FP16 pairs (x = hi + 2^-11 lo), by rows
+//   split_gemm     U = H L^-T, then M = L^-1 U, upper tiles mirrored so that M is
+//                  exactly symmetric; M is kept in FP32 over the H buffer (FP16 MFMA,
+//                  three partial products per term, FP32 sums)
+//   prep_products / setup_gemm   the same two products on FP32 operands and FP32
+//                  MFMAs (plan option)
 // M only feeds the low-precision sign iteration and its scaling; the density
-// columns use the FP64 L^-1, so FP32 rounding in M (relative ~1e-7) stays far
-// below the FP16 rounding of the iteration.
+// columns use the FP64 L^-1, so the rounding in M (relative ~1e-7 with FP32
+// operands, a few 1e-7 with split FP16 operands) stays far below the FP16
+// rounding of the iteration.
 #include "common.h"
 #include "ns_gemm.h"
+#include "ns_gemm_split.h"
 
 namespace nolsm {
 
@@ -404,6 +409,39 @@ __global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__res
 }
 
 
+// Split FP16 operands of the set-up products (buffer 0: row r = L^-1(r, :), through
+// an LDS tile since L^-1 is stored by columns; buffer 1: row r = H(r, :) = H(:, r)).
+// Each row holds the npad hi parts, then the npad lo parts.
+__global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restrict__ desc,
+                                                         char *ws) {
+  SUB_PTRS
+  const int nt = ld / 64;
+  if ((int)blockIdx.x >= nt * nt) return;
+  const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
+  _Float16 *Ls = reinterpret_cast<_Float16 *>(ws + d.off_lo);
+  _Float16 *Hs = Ls + 2 * (int64_t)ld * ld;
+  const int64_t lds = 2 * (int64_t)ld;
+  __shared__ double tile[64][65];
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    const int64_t o = (int64_t)(bj * 64 + c) * ld + bi * 64 + r;   // (bi 64 + r, bj 64 + c)
+    tile[c][r] = Sb[o];
+    _Float16 hi, lo;
+    split_f16(Hb[o], hi, lo);                     // H(bj 64 + c, bi 64 + r) by symmetry
+    _Float16 *hrow = Hs + (int64_t)(bj * 64 + c) * lds + bi * 64 + r;
+    hrow[0] = hi;
+    hrow[ld] = lo;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e & 63, r = e >> 6;
+    _Float16 hi, lo;
+    split_f16(tile[c][r], hi, lo);                // L^-1(bi 64 + r, bj 64 + c)
+    _Float16 *lrow = Ls + (int64_t)(bi * 64 + r) * lds + bj * 64 + c;
+    lrow[0] = hi;
+    lrow[ld] = lo;
+  }
+}
 
 // keep_spd = 0: clear every status (a new set-up); 1: clear only NOLSM_ENOCONV
 __global__ void reset_status_kernel(SubState *__restrict__ st, int K, int keep_spd) {
@@ -419,7 +457,7 @@ void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s) {
 // ------------------------------------------------------------------ host launcher
 
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  char *ws, hipStream_t s) {
+                  bool fp32_products, char *ws, hipStream_t s) {
   const int nbmax = max_npad / NB;
   launch_reset_status(st, K, 0, s);
   // Right-looking blocked Cholesky with two levels: inside an outer block of OB
@@ -454,7 +492,15 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     trtri_update_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
   }
   zero_upper_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, ws);
-  // M = L^-1 H L^-T as two FP32 products: U = H L^-T, then M = L^-1 U
+  // M = L^-1 H L^-T as two products: U = H L^-T, then M = L^-1 U
+  if (!fp32_products) {
+    prep_split_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
+    if (ts.n[4] > 0)
+      split_gemm_kernel<SPLIT_FULL><<<ts.n[4], 256, 0, s>>>(ts.t[4], desc, st, ws);
+    if (ts.n[5] > 0)
+      split_gemm_kernel<SPLIT_SYM><<<ts.n[5], 256, 0, s>>>(ts.t[5], desc, st, ws);
+    return;
+  }
   prep_products_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
   if (ts.n[3] > 0)
     setup_gemm_kernel<EPI_PLAIN_FULL><<<ts.n[3], 256, 0, s>>>(ts.t[3], desc, st, ws);

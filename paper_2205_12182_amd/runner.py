@@ -57,7 +57,7 @@ def tuned_tile_policy():
 
 class Runner:
     def __init__(self, inst, batch: int | None = None, mols=None, device="cuda",
-                 big_tile_min_npad="tuned"):
+                 big_tile_min_npad="tuned", setup_products=None):
         if not torch.cuda.is_available():
             raise RuntimeError("the NOLSM path runs on the GPU only")
         L.lib()
@@ -75,7 +75,9 @@ class Runner:
         if big_tile_min_npad == "tuned":
             big_tile_min_npad = tuned_tile_policy()
         self.big_tile_min_npad = big_tile_min_npad
-        self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad) for b in self.batches]
+        self.setup_products = setup_products
+        self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad, setup_products)
+                      for b in self.batches]
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
         self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
         self.tables = [torch.empty(L.nolsm_plan_table_bytes(p), dtype=torch.uint8, device=device)

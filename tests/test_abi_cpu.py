@@ -92,6 +92,14 @@ def test_plan_options_tile_policy():
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
     assert rc == L.EINVAL and "reserved" in L.nolsm_last_error()
+    opt.reserved[3] = 0
+    opt.setup_products = 2
+    rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
+                                      ctypes.byref(opt), ctypes.byref(out))
+    assert rc == L.EINVAL and "setup_products" in L.nolsm_last_error()
+    for sp in (L.SETUP_SPLIT_FP16, L.SETUP_FP32):
+        plan = L.nolsm_plan_create(hp, mols, setup_products=sp)
+        L.nolsm_plan_destroy(plan)
 
 
 def test_plan_rejects_bad_molecule():

@@ -69,13 +69,19 @@ def test_gather_bit_exact(gpu_ok):
         assert info.own_lo == int(O.own_columns(inst, info.mol, offs)[0])
 
 
-def test_setup_identities(gpu_ok):
+@pytest.mark.parametrize("setup", [L.SETUP_SPLIT_FP16, L.SETUP_FP32])
+def test_setup_identities(gpu_ok, setup):
     """L^-1 S L^-T = I in FP64; M = L^-1 H L^-T exactly symmetric and within the
-    FP32 rounding bound of its two products (operands rounded to FP32, FP32
-    accumulation over at most n terms each)."""
+    rounding bound of its two products C = A B.  FP32 operands: each operand
+    rounded to FP32 (u = 2^-24), FP32 accumulation over at most n terms, so
+    |dC| <= (n + 2) u |A| |B| per product.  Split FP16 operands: an operand is
+    represented within 2^-22 |x| + 2^-36 (the absolute term covers values in the
+    FP16 subnormal range), each term keeps three of its four partial products, so
+    |dC| <= (n + 14) u |A| |B| + 2^-36 (|A| J + J |B|) per product (J: all ones),
+    and the first product's error is carried through L^-1 by the second."""
     inst = get_config("t_23")
-    print_case("setup t_23")
-    r = Runner(inst)
+    print_case("setup t_23", setup)
+    r = Runner(inst, setup_products=setup)
     r.run(sched=plain_fp32_schedule(), energy=False)
     torch.cuda.synchronize()
     for i in [0, inst.nmol // 3, inst.nmol - 1]:
@@ -88,9 +94,21 @@ def test_setup_identities(gpu_ok):
         assert np.array_equal(Li, np.tril(Li))
         assert np.abs(Li @ Sk @ Li.T - np.eye(n)).max() < 1e-11
         assert np.array_equal(M, M.T)
-        u = 2.0 ** -24
-        bound = (2 * n + 4) * u * (np.abs(Li) @ np.abs(Hk) @ np.abs(Li).T)
-        assert np.all(np.abs(M[:n, :n] - Li @ Hk @ Li.T) <= bound)
+        u, t = 2.0 ** -24, 2.0 ** -36
+        aL, aH = np.abs(Li), np.abs(Hk)
+        if setup == L.SETUP_FP32:
+            bound = 2 * (n + 2) * u * (aL @ aH @ aL.T)
+        else:
+            J = np.ones((n, n))
+            aU = aH @ aL.T
+            e1 = (n + 14) * u * aU + t * (aH @ J + J @ aL.T)
+            bound = (n + 14) * u * (aL @ aU) + t * (aL @ J + J @ aU) + aL @ e1
+        err = np.abs(M[:n, :n] - Li @ Hk @ Li.T)
+        pos = bound > 0
+        assert not err[~pos].any()              # exact where every term is zero
+        ratio = err[pos] / bound[pos]
+        print_case(f"sub {i}: max error / bound {ratio.max():.3f}")
+        assert ratio.max() <= 1.0
         assert not M[n:, :].any()
 
 
