@@ -246,50 +246,53 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   });
 }
 
-// Trailing update of the outer Cholesky blocks on 128 x 128 tiles:
-//   A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s],  tiles (ti, tj) of 128 with ti >= tj
-// starting at row/column m0 (a multiple of 128).  A 64 x 64 FP64 tile reads
-// 6.5 flop per byte of its panels; the 128 x 128 tile doubles that and the next
-// k-stage is loaded into registers while the current one is multiplied (two LDS
-// buffers), with two workgroups per CU.  Wave w owns rows (w >> 1) * 64 and
-// columns (w & 1) * 64 as 4 x 4 blocks of 16 x 16 (layout as in gemm64_f64).
+// 128 x 128 FP64 tile product for the blocked set-up steps:
+//   acc(r, c) += sum_{k0 <= k < k1} A[k lda + r] B(k, c),   0 <= r, c < 128,
+// B(k, c) = B[k ldb + c], or B[c ldb + k] when TB; rows r >= nA and columns
+// c >= nB read as zero (k1 - k0: a multiple of KS64).
+// An FP64 MFMA issues at about half rate from a single wave (measured: 35 TF/s with
+// one wave per SIMD, 75-78 TF/s with two), so the workgroup has eight waves, two
+// per SIMD; wave w owns rows 32 (w >> 1) .. + 31 and columns 64 (w & 1) .. + 63 as
+// 2 x 4 blocks of 16 x 16 (layout as in gemm64_f64).  The next k-stage is loaded
+// into registers while the current one is multiplied (two LDS buffers).
 constexpr int LDQ = 128 + 1;        // padded LDS row (doubles) of the 128-wide stages
+constexpr int T128_THREADS = 512;
+typedef double Stage128[KS64 * LDQ];
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
-void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int m0,
-                       int rows) {
-  SUB_PTRS
-  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
-  if (ti < tj || k0 >= ld) return;
-  const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
-  if (r0 >= ld || c0 >= ld) return;
-  __shared__ double sA[2][KS64 * LDQ], sB[2][KS64 * LDQ];
+template <bool TB>
+__device__ __forceinline__ void tile128_f64(const double *__restrict__ A, int64_t lda,
+                                            const double *__restrict__ B, int64_t ldb, int nA,
+                                            int nB, int k0, int k1, d4 acc[2][4], Stage128 *sA,
+                                            Stage128 *sB) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
-  d4 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
   // element q of this thread's share of a stage: row m = idx & 127, k = idx >> 7
-  double ra[8], rb[8];
+  double ra[4], rb[4];
   auto load = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q, m = idx & 127, kk = idx >> 7;
-      const int64_t o = (int64_t)(k + kk) * ld;
-      ra[q] = (r0 + m < ld) ? Sb[o + r0 + m] : 0.0;
-      rb[q] = (c0 + m < ld) ? Sb[o + c0 + m] : 0.0;
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
+      ra[q] = (m < nA) ? A[(int64_t)(k + kk) * lda + m] : 0.0;
+      if (!TB) {
+        rb[q] = (m < nB) ? B[(int64_t)(k + kk) * ldb + m] : 0.0;
+      } else {                                   // 16 contiguous k of one column
+        const int kt = idx & 15, n = idx >> 4;
+        rb[q] = (n < nB) ? B[(int64_t)n * ldb + k + kt] : 0.0;
+      }
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int idx = tid + 256 * q, m = idx & 127, kk = idx >> 7;
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
       sA[b][kk * LDQ + m] = ra[q];
-      sB[b][kk * LDQ + m] = rb[q];
+      if (!TB)
+        sB[b][kk * LDQ + m] = rb[q];
+      else
+        sB[b][(idx & 15) * LDQ + (idx >> 4)] = rb[q];
     }
   };
+  if (k0 >= k1) return;
   load(k0);
   store(0);
   __syncthreads();
@@ -300,14 +303,13 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
 #pragma unroll
     for (int kk = 0; kk < KS64; kk += 4) {
       const int kr = kk + (lane >> 4);
-      double a[4], bb[4];
+      double a[2], bb[4];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        a[t] = sA[b][kr * LDQ + wm + 16 * t + (lane & 15)];
-        bb[t] = sB[b][kr * LDQ + wn + 16 * t + (lane & 15)];
-      }
+      for (int t = 0; t < 2; ++t) a[t] = sA[b][kr * LDQ + wm + 16 * t + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int t = 0; t < 4; ++t) bb[t] = sB[b][kr * LDQ + wn + 16 * t + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
@@ -316,18 +318,47 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
     __syncthreads();
     b ^= 1;
   }
+}
+
+// Visit this thread's elements of a 128 x 128 tile: f(r, c, value).
+template <typename F>
+__device__ __forceinline__ void acc128_foreach(d4 acc[2][4], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = r0 + wm + 16 * i + (lane >> 4) + 4 * q, c = c0 + wn + 16 * j + (lane & 15);
-        if (r < ld && c < ld) {
-          double *p = Sb + (int64_t)c * ld + r;
-          *p = *p - acc[i][j][q];
-        }
-      }
+      for (int q = 0; q < 4; ++q)
+        f(wm + 16 * i + (lane >> 4) + 4 * q, wn + 16 * j + (lane & 15), acc[i][j][q]);
+}
+
+// Trailing update of the outer Cholesky blocks on 128 x 128 tiles:
+//   A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s],  tiles (ti, tj) of 128 with ti >= tj
+// starting at row/column m0 (a multiple of 128).  A 64 x 64 FP64 tile reads
+// 6.5 flop per byte of its panels; the 128 x 128 tile doubles that.
+__global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int m0,
+                       int rows) {
+  SUB_PTRS
+  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  if (ti < tj || k0 >= ld) return;
+  const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
+  if (r0 >= ld || c0 >= ld) return;
+  __shared__ Stage128 sA[2], sB[2];
+  d4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  tile128_f64<false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, acc, sA, sB);
+  acc128_foreach(acc, [&](int r, int c, double v) {
+    if (r0 + r < ld && c0 + c < ld) {
+      double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
+      *p = *p - v;
+    }
+  });
 }
 
 // ------------------------------------------------------------------ L^-1 in place
@@ -344,13 +375,13 @@ __global__ __launch_bounds__(256) void trtri_diag_kernel(const SubDesc *__restri
   }
 }
 
-// Tmp[i, c] = sum_s L[i, j + s] Linv_jj[s, c]  for rows i >= j + 64
+// Tmp[i, c] = sum_s L[i, j + s] Linv_jj[s, c]  for rows j + 64 <= i < iend
 __global__ __launch_bounds__(256) void trtri_panel_kernel(const SubDesc *__restrict__ desc,
-                                                          char *ws, int jb) {
+                                                          char *ws, int jb, int iend) {
   SUB_PTRS
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
-  if (i0 >= ld) return;
+  if (i0 >= ld || i0 >= iend) return;
   __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
@@ -359,18 +390,71 @@ __global__ __launch_bounds__(256) void trtri_panel_kernel(const SubDesc *__restr
   acc_foreach(acc, [&](int r, int c, double v) { Tmp[(int64_t)c * ld + i0 + r] = v; });
 }
 
-// Linv[i, j-block] = - sum_{k = j+64}^{i-block end} Linv[i, k] Tmp[k, :]
+// Linv[i, j-block] = - sum_{k = j+64}^{i-block end} Linv[i, k] Tmp[k, :],  j + 64 <= i < iend
 __global__ __launch_bounds__(256) void trtri_update_kernel(const SubDesc *__restrict__ desc,
-                                                           char *ws, int jb) {
+                                                           char *ws, int jb, int iend) {
   SUB_PTRS
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
-  if (i0 >= ld) return;
+  if (i0 >= ld || i0 >= iend) return;
   __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
   d4 acc[2][2];
   acc_zero(acc);
   gemm64_f64<false>(Sb + i0, ld, Tmp, ld, j + NB, i0 + 64, acc, sA, sB);
   acc_foreach(acc, [&](int r, int c, double v) { Sb[(int64_t)(j + c) * ld + i0 + r] = -v; });
+}
+
+// Outer step of the two-level inverse.  Once the diagonal block X_JJ = L_JJ^-1 of
+// the outer block J = [J0, J0 + TW) is in place and the columns right of it hold
+// L^-1, the rows i >= J1 = J0 + TW of block column J follow from X L = I:
+//   X[i, J] = - sum_{J1 <= k <= i} X[i, k] T[k, :],   T = L[J1:, J] X_JJ.
+// T (rows k >= J1, TW columns, row major) lives in the iteration arena, which is
+// free until the set-up products.  Both products run on 128 x 128 tiles
+// (blockIdx.x = row tile + rows * column tile, two column tiles).
+constexpr int TW = 256;                 // outer block width of the inverse
+
+__global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
+  SUB_PTRS
+  const int J1 = J0 + TW;
+  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  const int r0 = J1 + ti * 128, c0 = tj * 128;
+  if (r0 >= ld) return;
+  double *T = reinterpret_cast<double *>(ws + d.off_lo);
+  __shared__ Stage128 sA[2], sB[2];
+  d4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  // T[r0 + r, c0 + c] = sum_s L[r0 + r, J0 + s] X_JJ[s, c0 + c];  X_JJ[s, c] = 0 for s < c
+  tile128_f64<true>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
+                    ld - r0, 128, c0, TW, acc, sA, sB);
+  acc128_foreach(acc, [&](int r, int c, double v) {
+    if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = v;
+  });
+}
+
+__global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
+  SUB_PTRS
+  const int J1 = J0 + TW;
+  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  const int r0 = J1 + ti * 128, c0 = tj * 128;
+  if (r0 >= ld) return;
+  const double *T = reinterpret_cast<const double *>(ws + d.off_lo);
+  const int kend = (r0 + 128 < ld ? r0 + 128 : ld) - J1;       // X[i, k] = 0 for k > i
+  __shared__ Stage128 sA[2], sB[2];
+  d4 acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  tile128_f64<false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, acc, sA,
+                     sB);
+  acc128_foreach(acc, [&](int r, int c, double v) {
+    if (r0 + r < ld) Sb[(int64_t)(J0 + c0 + c) * ld + r0 + r] = -v;
+  });
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restrict__ desc,
@@ -481,17 +565,32 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     if (Jend < nbmax) {
       // Jend * 64 is a multiple of 256 here, so the 128-wide tiles start aligned
       const int m0 = Jend * NB, rows = (max_npad - m0 + 127) / 128;
-      chol_trail_kernel<<<dim3(rows * rows, K), 256, 0, s>>>(desc, ws, J * NB, Jend * NB, m0,
+      chol_trail_kernel<<<dim3(rows * rows, K), T128_THREADS, 0, s>>>(desc, ws, J * NB, Jend * NB, m0,
                                                              rows);
     }
   }
-  trtri_diag_kernel<<<dim3(nbmax, K), 256, 0, s>>>(desc, ws);
-  for (int jb = nbmax - 2; jb >= 0; --jb) {
-    const int rem = nbmax - jb - 1;
-    trtri_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
-    trtri_update_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
-  }
+  // L^-1 in place, outer blocks of TW columns right to left: the 64-wide steps
+  // invert the outer diagonal block, then two 128 x 128-tile products give the
+  // block column below it (each outer step reads the finished part of L^-1 once,
+  // instead of once per 64-wide column block).
+  // the upper triangle still holds S: clear it first, so that the outer steps can
+  // read the diagonal block X_JJ as a full (lower-triangular) square
   zero_upper_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, ws);
+  trtri_diag_kernel<<<dim3(nbmax, K), 256, 0, s>>>(desc, ws);
+  for (int J0 = (max_npad - 1) / TW * TW; J0 >= 0; J0 -= TW) {
+    const int J1 = J0 + TW, iend = J1 < max_npad ? J1 : max_npad;
+    for (int jb = iend / NB - 1; jb >= J0 / NB; --jb) {
+      const int rem = iend / NB - jb - 1;
+      if (rem <= 0) continue;
+      trtri_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb, J1);
+      trtri_update_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb, J1);
+    }
+    if (J1 < max_npad) {
+      const int rows = (max_npad - J1 + 127) / 128;
+      trtri_outer_t_kernel<<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
+      trtri_outer_x_kernel<<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
+    }
+  }
   // M = L^-1 H L^-T as two products: U = H L^-T, then M = L^-1 U
   if (!fp32_products) {
     prep_split_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);
