@@ -50,7 +50,8 @@ struct nolsm_plan {
   size_t off_desc = 0, off_mem_mol = 0, off_mem_loc = 0, off_tiles = 0, off_state = 0;
   size_t tab_bytes = 0;
   // workspace (bytes from the workspace base)
-  size_t off_counter = 0;       // unsigned long long: executed sign-GEMM work (FLOP_UNIT)
+  size_t off_counter = 0;       // unsigned long long: executed sign-GEMM work (FLOP_UNIT),
+                                // then an unsigned count of FP32 restarts
   size_t bytes = 0;
   char *tab = nullptr;          // table buffer the tables were last uploaded to
   char *ws = nullptr;
@@ -199,7 +200,7 @@ nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols,
   // executed-flop counter), then the per-submatrix arenas
   off = 0;
   p->off_counter = off;
-  off = align256(off + sizeof(unsigned long long));
+  off = align256(off + sizeof(unsigned long long) + sizeof(unsigned));
   for (int i = 0; i < K; ++i) {
     SubDesc &d = p->desc[i];
     const size_t np = (size_t)d.npad;
@@ -301,6 +302,7 @@ static TileSet tile_set(const nolsm_plan *p, const Tile *tiles) {
     ts.n[l] = p->list_end[l] - b;
   }
   ts.flop_units = reinterpret_cast<unsigned long long *>(p->ws + p->off_counter);
+  ts.fb_count = reinterpret_cast<unsigned *>(p->ws + p->off_counter + sizeof(unsigned long long));
   return ts;
 }
 

@@ -69,6 +69,7 @@ struct TileSet {
   const Tile *t[NTILELIST];
   int n[NTILELIST];
   unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
+  unsigned *fb_count;               // submatrices selected for the FP32 restart
 };
 // 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad
 // are multiples of these, so the count is exact)

@@ -96,8 +96,10 @@ __host__ __device__ constexpr int wait_vm_lgkm0(int vm) {
 
 // C(m, c) = sum_{k < kend} A[m ld + k] B[c ld + k] for the tile at (i0, j0), i.e.
 // C = A^T B for column-major A, B with leading dimension ld (kend: a multiple of
-// the stage depth, at most ld).
-template <typename TI, int EPI, int BMB, bool PARTIAL>
+// the stage depth, at most ld).  TAG only separates instantiations made from
+// different kernels (the host compilation pass rejects a second kernel that
+// instantiates the same specialisation of this body).
+template <typename TI, int EPI, int BMB, bool PARTIAL, int TAG = 0>
 __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI *__restrict__ B,
                                              TI *__restrict__ Out, int ld, int kend, int n, int i0,
                                              int j0,
@@ -375,6 +377,47 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
   else
     ns_gemm_body<TI, EPI, BMB, true>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, s3, red,
                                      &S.racc);
+}
+
+// FP32 products of the restart phase.  Usually no submatrix restarts, so the
+// launches are gated: a small grid (at most FB_GRID workgroups, two per CU) walks
+// the tile list in rounds and every workgroup returns at once when the restart
+// count is zero.  Within a round, consecutive tiles go to one XCD as above.
+constexpr int FB_GRID = 512;
+
+template <int EPI>
+__global__ __launch_bounds__(256) void ns_gemm_gated_kernel(
+    const Tile *__restrict__ tiles, int ntiles, const SubDesc *__restrict__ desc,
+    SubState *__restrict__ st, char *ws, const unsigned *__restrict__ gate,
+    unsigned long long *__restrict__ flop_units) {
+  if (*gate == 0u) return;
+  __shared__ uint4 s0[slot_u4<2>()], s1[slot_u4<2>()], s2[slot_u4<2>()], s3[slot_u4<2>()];
+  __shared__ float red[4];
+  for (int base = 0; base < ntiles; base += gridDim.x) {
+    const int cnt = ntiles - base < (int)gridDim.x ? ntiles - base : (int)gridDim.x;
+    if ((int)blockIdx.x >= cnt) break;
+    const Tile t = tiles[base + xcd_remap(blockIdx.x, cnt)];
+    SubState &S = st[t.sub];
+    if (!S.active || S.prec != P_FP32) continue;
+    const SubDesc d = desc[t.sub];
+    const int ld = d.npad;
+    const int cur = S.cur;
+    const float *A = buf_ptr<float>(ws, d, cur);
+    const float *B = (EPI == EPI_SQUARE) ? A : buf_ptr<float>(ws, d, (cur + 1) % 3);
+    float *Out = buf_ptr<float>(ws, d, (cur + (EPI == EPI_SQUARE ? 1 : 2)) % 3);
+    const int i0 = t.ti * 128, j0 = t.tj * 128;
+    if (threadIdx.x == 0) {
+      const int rows = (ld - i0 < 128 ? ld - i0 : 128), cols = (ld - j0 < 128 ? ld - j0 : 128);
+      atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
+    }
+    if (i0 + 128 <= ld && j0 + 128 <= ld)
+      ns_gemm_body<float, EPI, 2, false, 1>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1,
+                                            s2, s3, red, &S.racc);
+    else
+      ns_gemm_body<float, EPI, 2, true, 1>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1,
+                                           s2, s3, red, &S.racc);
+    __syncthreads();             // the ring slots are refilled by the next tile
+  }
 }
 
 // Set-up products in FP32 (128 x 128 tiles), on the three FP32 buffers of the

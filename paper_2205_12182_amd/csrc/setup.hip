@@ -158,51 +158,64 @@ __device__ __forceinline__ void tri_index(int x, int &ti, int &tj) {   // x -> (
 
 // ------------------------------------------------------------------ Cholesky
 
+// Unblocked Cholesky of the 64 x 64 diagonal block j and the inverse of its factor,
+// both right-looking with one barrier per column:
+//   factor:  A[r][s] -= A[r][c] A[s][c] / A[c][c]  (r >= s > c); afterwards
+//            L[c][c] = sqrt(A[c][c]), L[r][c] = A[r][c] / L[c][c]
+//   inverse: Y = I;  Y[r][k] -= A[r][q] Y[q][k] / A[q][q]  (r > q >= k); afterwards
+//            L^-1[r][k] = Y[r][k] / L[r][r]
+// (L X = I solved row by row: row q of Y is final once the columns before q are done).
 __global__ __launch_bounds__(256) void chol_diag_kernel(const SubDesc *__restrict__ desc,
                                                         SubState *__restrict__ st, char *ws,
                                                         int jb) {
   SUB_PTRS
   const int j = jb * NB;
   if (j >= ld) return;
-  __shared__ double sL[NB * LDP];
-  __shared__ double sI[NB * LDP];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    sL[r * LDP + c] = Sb[(int64_t)(j + c) * ld + j + r];
-  }
-  __syncthreads();
+  __shared__ double sA[NB * LDP];
+  __shared__ double sY[NB * LDP];
+  __shared__ double sD[NB];
   __shared__ int bad;
+  const int tid = threadIdx.x;
   if (tid == 0) bad = 0;
+  for (int e = tid; e < NB * NB; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    sA[r * LDP + c] = Sb[(int64_t)(j + c) * ld + j + r];
+    sY[r * LDP + c] = (r == c) ? 1.0 : 0.0;
+  }
+  __syncthreads();
   for (int c = 0; c < NB; ++c) {
-    if (tid == 0) {
-      double p = sL[c * LDP + c];
-      if (!(p > 0.0)) { bad = 1; p = 1.0; }
-      sL[c * LDP + c] = sqrt(p);
+    double dc = sA[c * LDP + c];
+    if (!(dc > 0.0)) {                    // not positive definite: flag, keep going finite
+      if (tid == 0) bad = 1;
+      dc = 1.0;
     }
-    __syncthreads();
-    if (tid > c && tid < NB) sL[tid * LDP + c] /= sL[c * LDP + c];
-    __syncthreads();
+    const double inv = 1.0 / dc;
     for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e >> 6, s = e & 63;
-      if (s > c && r >= s) sL[r * LDP + s] -= sL[r * LDP + c] * sL[s * LDP + c];
+      const int r = e >> 6, s2 = e & 63;
+      if (s2 > c && r >= s2) sA[r * LDP + s2] -= sA[r * LDP + c] * sA[s2 * LDP + c] * inv;
     }
     __syncthreads();
   }
-  if (tid < NB) {                                   // column tid of L_jj^-1
-    const int c = tid;
-    for (int r = 0; r < NB; ++r) {
-      if (r < c) { sI[r * LDP + c] = 0.0; continue; }
-      double s = (r == c) ? 1.0 : 0.0;
-      for (int q = c; q < r; ++q) s -= sL[r * LDP + q] * sI[q * LDP + c];
-      sI[r * LDP + c] = s / sL[r * LDP + r];
+  if (tid < NB) {
+    const double dc = sA[tid * LDP + tid];
+    sD[tid] = dc > 0.0 ? sqrt(dc) : 1.0;
+  }
+  for (int q = 0; q < NB - 1; ++q) {
+    double dq = sA[q * LDP + q];
+    if (!(dq > 0.0)) dq = 1.0;
+    const double inv = 1.0 / dq;
+    for (int e = tid; e < NB * NB; e += 256) {
+      const int r = e >> 6, k = e & 63;
+      if (r > q && k <= q) sY[r * LDP + k] -= sA[r * LDP + q] * sY[q * LDP + k] * inv;
     }
+    __syncthreads();
   }
   __syncthreads();
   for (int e = tid; e < NB * NB; e += 256) {
     const int r = e & 63, c = e >> 6;
-    Sb[(int64_t)(j + c) * ld + j + r] = (r >= c) ? sL[r * LDP + c] : 0.0;
-    Dinv[(int64_t)jb * NB * NB + r + c * NB] = sI[r * LDP + c];
+    const double l = r > c ? sA[r * LDP + c] / sD[c] : (r == c ? sD[c] : 0.0);
+    Sb[(int64_t)(j + c) * ld + j + r] = l;
+    Dinv[(int64_t)jb * NB * NB + r + c * NB] = r >= c ? sY[r * LDP + c] / sD[r] : 0.0;
   }
   if (tid == 0 && bad) st[blockIdx.y].status = NOLSM_ENOTSPD;
 }
@@ -495,7 +508,10 @@ __global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__res
 
 // Split FP16 operands of the set-up products (buffer 0: row r = L^-1(r, :), through
 // an LDS tile since L^-1 is stored by columns; buffer 1: row r = H(r, :) = H(:, r)).
-// Each row holds the npad hi parts, then the npad lo parts.
+// Each row holds the npad hi parts, then the npad lo parts.  Every thread converts
+// four consecutive elements: 32-byte reads, 8-byte stores of hi and of lo.
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+
 __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restrict__ desc,
                                                          char *ws) {
   SUB_PTRS
@@ -506,24 +522,38 @@ __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restri
   _Float16 *Hs = Ls + 2 * (int64_t)ld * ld;
   const int64_t lds = 2 * (int64_t)ld;
   __shared__ double tile[64][65];
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    const int64_t o = (int64_t)(bj * 64 + c) * ld + bi * 64 + r;   // (bi 64 + r, bj 64 + c)
-    tile[c][r] = Sb[o];
-    _Float16 hi, lo;
-    split_f16(Hb[o], hi, lo);                     // H(bj 64 + c, bi 64 + r) by symmetry
-    _Float16 *hrow = Hs + (int64_t)(bj * 64 + c) * lds + bi * 64 + r;
-    hrow[0] = hi;
-    hrow[ld] = lo;
+  for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+    const int r4 = (e & 15) * 4, c = e >> 4;
+    const int64_t o = (int64_t)(bj * 64 + c) * ld + bi * 64 + r4;   // (bi 64 + r4, bj 64 + c)
+    const d4 sv = *reinterpret_cast<const d4 *>(Sb + o);
+    const d4 hv = *reinterpret_cast<const d4 *>(Hb + o);
+    h4 hh, hl;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      tile[c][r4 + q] = sv[q];
+      _Float16 a, b;
+      split_f16(hv[q], a, b);                     // H(bj 64 + c, bi 64 + r4 + q) by symmetry
+      hh[q] = a;
+      hl[q] = b;
+    }
+    _Float16 *hrow = Hs + (int64_t)(bj * 64 + c) * lds + bi * 64 + r4;
+    *reinterpret_cast<h4 *>(hrow) = hh;
+    *reinterpret_cast<h4 *>(hrow + ld) = hl;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int c = e & 63, r = e >> 6;
-    _Float16 hi, lo;
-    split_f16(tile[c][r], hi, lo);                // L^-1(bi 64 + r, bj 64 + c)
-    _Float16 *lrow = Ls + (int64_t)(bi * 64 + r) * lds + bj * 64 + c;
-    lrow[0] = hi;
-    lrow[ld] = lo;
+  for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+    const int c4 = (e & 15) * 4, r = e >> 4;
+    h4 lh, ll;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      _Float16 a, b;
+      split_f16(tile[c4 + q][r], a, b);           // L^-1(bi 64 + r, bj 64 + c4 + q)
+      lh[q] = a;
+      ll[q] = b;
+    }
+    _Float16 *lrow = Ls + (int64_t)(bi * 64 + r) * lds + bj * 64 + c4;
+    *reinterpret_cast<h4 *>(lrow) = lh;
+    *reinterpret_cast<h4 *>(lrow + ld) = ll;
   }
 }
 

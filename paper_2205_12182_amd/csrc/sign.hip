@@ -242,13 +242,35 @@ __global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ d
 
 // Fallback selection: not converged in a tolerance phase and residual above tol
 // (or non-finite) -> restart from X_0 in FP32 with the Gershgorin scale.
-__global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol) {
+// The selected submatrices are counted in *cnt (cleared by clear_count_kernel).
+__global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol,
+                                 unsigned *__restrict__ cnt) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
   s.active = 0;
   if (s.status != 0) return;
-  if (!s.converged && !(s.resid <= tol)) s.fell_back = 1;
+  if (!s.converged && !(s.resid <= tol)) {
+    s.fell_back = 1;
+    atomicAdd(cnt, 1u);
+  }
+}
+
+__global__ void clear_count_kernel(unsigned *__restrict__ cnt) { *cnt = 0u; }
+
+// X_0 of the restarting submatrices: one workgroup per submatrix, all columns;
+// returns at once when nothing restarts.
+__global__ __launch_bounds__(256) void cast_fb_kernel(const SubDesc *__restrict__ desc,
+                                                      const SubState *__restrict__ st, char *ws,
+                                                      double mu, const unsigned *__restrict__ cnt) {
+  if (*cnt == 0u) return;
+  const SubDesc d = desc[blockIdx.x];
+  const SubState &s = st[blockIdx.x];
+  if (s.status != 0 || !s.fell_back) return;
+  const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
+  const double inv_b = 1.0 / s.scale;
+  for (int c = 0; c < d.npad; ++c)
+    cast_col<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
 }
 
 __global__ void fb_finish_kernel(SubState *__restrict__ st, int K) {
@@ -315,9 +337,29 @@ void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s) {
 }
 
 // One phase of the iteration (host loop of launches; no host synchronisation).
+// FP32 restart products: tile lists 0 and 2 through the gated kernel.
+static void gated_gemm(int epi, const TileSet &ts, const SubDesc *desc, SubState *st, char *ws,
+                       hipStream_t s) {
+  for (int l : {0, 2}) {
+    if (ts.n[l] == 0) continue;
+    const int grid = ts.n[l] < FB_GRID ? ts.n[l] : FB_GRID;
+    if (epi == EPI_SQUARE)
+      ns_gemm_gated_kernel<EPI_SQUARE><<<grid, 256, 0, s>>>(ts.t[l], ts.n[l], desc, st, ws,
+                                                            ts.fb_count, ts.flop_units);
+    else
+      ns_gemm_gated_kernel<EPI_UPDATE><<<grid, 256, 0, s>>>(ts.t[l], ts.n[l], desc, st, ws,
+                                                            ts.fb_count, ts.flop_units);
+  }
+}
+
 static void timed_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc,
-                       SubState *st, char *ws, EventLog *log, double flop, hipStream_t s) {
+                       SubState *st, char *ws, EventLog *log, double flop, int fallback,
+                       hipStream_t s) {
   (void)flop;
+  if (fallback) {
+    gated_gemm(epi, ts, desc, st, ws, s);
+    return;
+  }
   const int e = log ? log->begin(T_GEMM, s) : -1;
   ns_gemm(epi, prec, ts, desc, st, ws, s);
   if (log && log->on) {
@@ -338,9 +380,9 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
   const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
   for (int t = 0; t <= last; ++t) {
     p.t = t;
-    timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, s);
+    timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
     ns_check_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, p);
-    timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, s);
+    timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
     ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback);
   }
   phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
@@ -367,10 +409,11 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     launch_phase(desc, st, K, ts, ws, ph, scaled, 0, log, flop, s);
   }
   if (sch.fallback_iters > 0) {
-    fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol);
+    clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count);
+    fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol, ts.fb_count);
     scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, nullptr, 0.0f,
                                               P_FP32, 1);
-    cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 1);
+    cast_fb_kernel<<<K, 256, 0, s>>>(desc, st, ws, mu, ts.fb_count);
     nolsm_phase fb;
     fb.prec = P_FP32;
     fb.iters = sch.fallback_iters;
