@@ -165,58 +165,110 @@ __device__ __forceinline__ void tri_index(int x, int &ti, int &tj) {   // x -> (
 //   inverse: Y = I;  Y[r][k] -= A[r][q] Y[q][k] / A[q][q]  (r > q >= k); afterwards
 //            L^-1[r][k] = Y[r][k] / L[r][r]
 // (L X = I solved row by row: row q of Y is final once the columns before q are done).
+// The block lives in registers: thread (tr, tc) = (tid / 16, tid % 16) holds rows
+// tr + 16 i and columns tc + 16 jj (i, jj < 4); column c of A (row q of Y) is
+// published through a double-buffered LDS vector by the threads that hold it.
 __global__ __launch_bounds__(256) void chol_diag_kernel(const SubDesc *__restrict__ desc,
                                                         SubState *__restrict__ st, char *ws,
                                                         int jb) {
   SUB_PTRS
   const int j = jb * NB;
   if (j >= ld) return;
-  __shared__ double sA[NB * LDP];
-  __shared__ double sY[NB * LDP];
+  __shared__ double sA[NB * LDP];       // the factored block (for the inverse)
+  __shared__ double vec[2][NB];
   __shared__ double sD[NB];
   __shared__ int bad;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, tr = tid >> 4, tc = tid & 15;
   if (tid == 0) bad = 0;
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    sA[r * LDP + c] = Sb[(int64_t)(j + c) * ld + j + r];
-    sY[r * LDP + c] = (r == c) ? 1.0 : 0.0;
+  double a[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj)
+      a[i][jj] = Sb[(int64_t)(j + tc + 16 * jj) * ld + j + tr + 16 * i];
+  // factor: step c = 16 jj + cc; the holders of column c (tc == cc) publish it
+#pragma unroll
+  for (int jj = 0; jj < 4; ++jj) {
+#pragma unroll 1
+    for (int cc = 0; cc < 16; ++cc) {
+      const int c = 16 * jj + cc, b = c & 1;
+      if (tc == cc) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) vec[b][tr + 16 * i] = a[i][jj];
+      }
+      __syncthreads();
+      double dc = vec[b][c];
+      if (!(dc > 0.0)) {                  // not positive definite: flag, keep going finite
+        if (tid == 0) bad = 1;
+        dc = 1.0;
+      }
+      const double inv = 1.0 / dc;
+      double cr[4], cs[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) cr[i] = vec[b][tr + 16 * i] * inv;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cs[q] = vec[b][tc + 16 * q];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int r = tr + 16 * i, s2 = tc + 16 * q;
+          if (s2 > c && r >= s2) a[i][q] -= cr[i] * cs[q];
+        }
+    }
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) sA[(tr + 16 * i) * LDP + tc + 16 * jj] = a[i][jj];
   __syncthreads();
-  for (int c = 0; c < NB; ++c) {
-    double dc = sA[c * LDP + c];
-    if (!(dc > 0.0)) {                    // not positive definite: flag, keep going finite
-      if (tid == 0) bad = 1;
-      dc = 1.0;
-    }
-    const double inv = 1.0 / dc;
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e >> 6, s2 = e & 63;
-      if (s2 > c && r >= s2) sA[r * LDP + s2] -= sA[r * LDP + c] * sA[s2 * LDP + c] * inv;
-    }
-    __syncthreads();
-  }
   if (tid < NB) {
     const double dc = sA[tid * LDP + tid];
     sD[tid] = dc > 0.0 ? sqrt(dc) : 1.0;
   }
-  for (int q = 0; q < NB - 1; ++q) {
-    double dq = sA[q * LDP + q];
-    if (!(dq > 0.0)) dq = 1.0;
-    const double inv = 1.0 / dq;
-    for (int e = tid; e < NB * NB; e += 256) {
-      const int r = e >> 6, k = e & 63;
-      if (r > q && k <= q) sY[r * LDP + k] -= sA[r * LDP + q] * sY[q * LDP + k] * inv;
+  double y[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) y[i][jj] = (tr + 16 * i == tc + 16 * jj) ? 1.0 : 0.0;
+  // inverse: step q = 16 ii + qq; the holders of row q of Y (tr == qq) publish it
+#pragma unroll
+  for (int ii = 0; ii < 4; ++ii) {
+#pragma unroll 1
+    for (int qq = 0; qq < 16; ++qq) {
+      const int q = 16 * ii + qq, b = q & 1;
+      if (tr == qq) {
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) vec[b][tc + 16 * jj] = y[ii][jj];
+      }
+      __syncthreads();
+      double dq = sA[q * LDP + q];
+      if (!(dq > 0.0)) dq = 1.0;
+      const double inv = 1.0 / dq;
+      double ar[4], yq[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) ar[i] = sA[(tr + 16 * i) * LDP + q] * inv;
+#pragma unroll
+      for (int jj = 0; jj < 4; ++jj) yq[jj] = vec[b][tc + 16 * jj];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const int r = tr + 16 * i, k = tc + 16 * jj;
+          if (r > q && k <= q) y[i][jj] -= ar[i] * yq[jj];
+        }
     }
-    __syncthreads();
   }
   __syncthreads();
-  for (int e = tid; e < NB * NB; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    const double l = r > c ? sA[r * LDP + c] / sD[c] : (r == c ? sD[c] : 0.0);
-    Sb[(int64_t)(j + c) * ld + j + r] = l;
-    Dinv[(int64_t)jb * NB * NB + r + c * NB] = r >= c ? sY[r * LDP + c] / sD[r] : 0.0;
-  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int jj = 0; jj < 4; ++jj) {
+      const int r = tr + 16 * i, c = tc + 16 * jj;
+      const double l = r > c ? sA[r * LDP + c] / sD[c] : (r == c ? sD[c] : 0.0);
+      Sb[(int64_t)(j + c) * ld + j + r] = l;
+      Dinv[(int64_t)jb * NB * NB + r + c * NB] = r >= c ? y[i][jj] / sD[r] : 0.0;
+    }
   if (tid == 0 && bad) st[blockIdx.y].status = NOLSM_ENOTSPD;
 }
 
