@@ -30,8 +30,8 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
                   hipStream_t s);
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
-void launch_features(const SubDesc *desc, const SubState *st, int K, const char *ws, double mu,
-                     float *feat, hipStream_t s);
+void launch_features(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+                     double mu, float *feat, hipStream_t s);
 }  // namespace nolsm
 
 using namespace nolsm;
@@ -393,7 +393,7 @@ nolsm_status nolsm_features(nolsm_plan *p, double mu, float *feat, hipStream_t s
     if (r != NOLSM_OK) return r;
   }
   PLAN_PTRS
-  launch_features(desc, st, p->K, p->ws, mu, feat, s);
+  launch_features(desc, st, p->K, p->max_npad, p->ws, mu, feat, s);
   return hip_check("nolsm_features");
 }
 

@@ -1,11 +1,10 @@
 // Per-submatrix descriptors of A_k = M_k - mu I for the learned schedule.
 //
-// One workgroup per submatrix; wave w handles columns c = w, w + 4, ... (A is
-// symmetric, so column statistics are row statistics), lanes stride down a
-// column.  Per column: the diagonal d = A_cc and the off-diagonal absolute sum
-// R_c; per submatrix: Gershgorin bound b = max_c (|d| + R_c) and edges
-// min (d - R), max (d + R), Tr A, ||A||_F^2 and diagonal moments.  The fixed
-// thread-to-column assignment and combine order make the result reproducible.
+// A is symmetric, so column statistics are row statistics.  Per column: the
+// diagonal d = A_cc, the off-diagonal absolute sum R_c and the squared norm; per
+// submatrix: Gershgorin bound b = max_c (|d| + R_c) and edges min (d - R),
+// max (d + R), Tr A, ||A||_F^2 and diagonal moments.  The fixed thread-to-column
+// assignment and combine order make the result reproducible.
 #include <cfloat>
 
 #include "common.h"
@@ -27,18 +26,22 @@ __device__ __forceinline__ void acc_merge(ColAcc &a, const ColAcc &b) {
   a.sR += b.sR; a.maxR = fmax(a.maxR, b.maxR); a.neg += b.neg; a.f2 += b.f2;
 }
 
-__global__ __launch_bounds__(256) void features_kernel(const SubDesc *__restrict__ desc,
-                                                       const SubState *__restrict__ st,
-                                                       const char *ws, double mu,
-                                                       float *__restrict__ feat) {
-  const SubDesc d = desc[blockIdx.x];
-  float *f = feat + (int64_t)blockIdx.x * NOLSM_NFEAT;
+// Pass 1: grid (npad / 64, K); workgroup x covers columns 64 x .. 64 x + 63, wave w
+// columns 64 x + 16 w .. + 15, lanes stride down a column.  The workgroup's partial
+// (waves combined in order) goes to the submatrix's set-up scratch (free once M is
+// formed).
+__global__ __launch_bounds__(256) void features_part_kernel(const SubDesc *__restrict__ desc,
+                                                            char *ws, double mu) {
+  const SubDesc d = desc[blockIdx.y];
+  if ((int)blockIdx.x * 64 >= d.npad) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
-  __shared__ ColAcc part[4];
+  ColAcc *part = reinterpret_cast<ColAcc *>(ws + d.off_diag);
+  __shared__ ColAcc wp[4];
   ColAcc a;
   acc_init(a);
-  for (int c = w; c < d.n; c += 4) {
+  const int cb = blockIdx.x * 64 + w * 16;
+  for (int c = cb; c < cb + 16 && c < d.n; ++c) {
     double R = 0.0, f2 = 0.0, diag = 0.0;
     for (int r = lane; r < d.n; r += 64) {
       double v = (double)M[(int64_t)c * d.npad + r];
@@ -57,14 +60,30 @@ __global__ __launch_bounds__(256) void features_kernel(const SubDesc *__restrict
     a.neg += diag < 0.0 ? 1.0 : 0.0;
     a.f2 += f2;
   }
-  if (lane == 0) part[w] = a;
+  if (lane == 0) wp[w] = a;
   __syncthreads();
   if (threadIdx.x != 0) return;
-  ColAcc t = part[0];
-  acc_merge(t, part[1]);
-  acc_merge(t, part[2]);
-  acc_merge(t, part[3]);
-  const bool bad = st[blockIdx.x].status != 0 || d.n == 0;
+  ColAcc t = wp[0];
+  acc_merge(t, wp[1]);
+  acc_merge(t, wp[2]);
+  acc_merge(t, wp[3]);
+  part[blockIdx.x] = t;
+}
+
+// Pass 2: one thread per submatrix combines the partials in column order.
+__global__ __launch_bounds__(256) void features_final_kernel(const SubDesc *__restrict__ desc,
+                                                             const SubState *__restrict__ st,
+                                                             const char *ws, int K,
+                                                             float *__restrict__ feat) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const SubDesc d = desc[k];
+  float *f = feat + (int64_t)k * NOLSM_NFEAT;
+  const ColAcc *part = reinterpret_cast<const ColAcc *>(ws + d.off_diag);
+  ColAcc t;
+  acc_init(t);
+  for (int x = 0; x < d.npad / 64; ++x) acc_merge(t, part[x]);
+  const bool bad = st[k].status != 0 || d.n == 0;
   const double n = d.n > 0 ? (double)d.n : 1.0;
   const double b = t.bmax > 0.0 ? t.bmax : 1.0;
   const double rms = sqrt(t.f2 / n);
@@ -79,9 +98,10 @@ __global__ __launch_bounds__(256) void features_kernel(const SubDesc *__restrict
   for (int i = 0; i < NOLSM_NFEAT; ++i) f[i] = bad ? 0.0f : v[i];
 }
 
-void launch_features(const SubDesc *desc, const SubState *st, int K, const char *ws, double mu,
-                     float *feat, hipStream_t s) {
-  features_kernel<<<K, 256, 0, s>>>(desc, st, ws, mu, feat);
+void launch_features(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+                     double mu, float *feat, hipStream_t s) {
+  features_part_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, ws, mu);
+  features_final_kernel<<<(K + 255) / 256, 256, 0, s>>>(desc, st, ws, K, feat);
 }
 
 }  // namespace nolsm

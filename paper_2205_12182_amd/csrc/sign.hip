@@ -224,20 +224,45 @@ __device__ void cast_col(const float *M, TI *X, int n, int ld, int c, double mu,
   }
 }
 
+// One wave per column, four consecutive rows per lane (16-byte reads of M).
+template <typename TI>
+__device__ __forceinline__ void cast_col4(const float *M, TI *X, int n, int ld, int c, double mu,
+                                          double inv_b) {
+  typedef TI v4 __attribute__((ext_vector_type(4)));
+  const int lane = threadIdx.x & 63;
+  for (int q = lane; q < ld / 4; q += 64) {
+    const int r = 4 * q;
+    const float4 m = *reinterpret_cast<const float4 *>(M + (int64_t)c * ld + r);
+    const float mv[4] = {m.x, m.y, m.z, m.w};
+    v4 o;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      double v = 0.0;
+      if (r + e < n && c < n) v = ((double)mv[e] - (r + e == c ? mu : 0.0)) * inv_b;
+      o[e] = from_f64<TI>(v);
+    }
+    *reinterpret_cast<v4 *>(X + (int64_t)c * ld + r) = o;
+  }
+}
+
+constexpr int CAST_COLS = 8;            // columns per workgroup (two per wave)
+
 __global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ desc,
                                                    const SubState *__restrict__ st, char *ws,
-                                                   double mu, int only_fb) {
+                                                   double mu) {
   const SubDesc d = desc[blockIdx.y];
   const SubState &s = st[blockIdx.y];
-  const int c = blockIdx.x;
-  if (c >= d.npad || s.status != 0) return;
-  if (only_fb && !s.fell_back) return;
+  if (s.status != 0) return;
   const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
   const double inv_b = 1.0 / s.scale;
-  if (s.prec == P_FP32) cast_col<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
-  else if (s.prec == P_FP16)
-    cast_col<_Float16>(M, buf_ptr<_Float16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
-  else cast_col<__bf16>(M, buf_ptr<__bf16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+  for (int c = blockIdx.x * CAST_COLS + (threadIdx.x >> 6); c < (blockIdx.x + 1) * CAST_COLS;
+       c += 4) {
+    if (c >= d.npad) break;
+    if (s.prec == P_FP32) cast_col4<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+    else if (s.prec == P_FP16)
+      cast_col4<_Float16>(M, buf_ptr<_Float16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+    else cast_col4<__bf16>(M, buf_ptr<__bf16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+  }
 }
 
 // Fallback selection: not converged in a tolerance phase and residual above tol
@@ -397,7 +422,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
   gersh_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, mu);
   scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower, sch.lower_log10,
                                             sch.lower_factor, sch.phase[0].prec, 0);
-  cast_kernel<<<dim3(max_npad, K), 256, 0, s>>>(desc, st, ws, mu, 0);
+  cast_kernel<<<dim3((max_npad + CAST_COLS - 1) / CAST_COLS, K), 256, 0, s>>>(desc, st, ws, mu);
   for (int q = 0; q < sch.nphase; ++q) {
     const nolsm_phase &ph = sch.phase[q];
     if (q > 0 && ph.prec != sch.phase[q - 1].prec) {

@@ -91,3 +91,37 @@ def test_training_reduces_loss(gpu_ok):
     net = ScheduleMLP(nout=1, seed=3)
     hist = net.fit(x, t, steps=400, lr=3e-3)
     assert hist[-1] < 0.05 * hist[0]
+
+
+def reference_features(Mk, n, nmem, m, mu):
+    """The 16 descriptors written out from their definitions (A = M_k - mu I, n x n)."""
+    A = Mk[:n, :n].astype(np.float64) - mu * np.eye(n)
+    d = np.diag(A)
+    R = np.abs(A).sum(axis=0) - np.abs(d)
+    f2 = (A * A).sum()
+    b = np.max(np.abs(d) + R)
+    mean, rms = d.mean(), np.sqrt(f2 / n)
+    var = max((d * d).mean() - mean * mean, 0.0)
+    mind = np.abs(d).min()
+    return np.array([np.log(n), nmem / 100.0, m / 32.0, np.log(b), (d - R).min() / b,
+                     (d + R).max() / b, mean / b, rms / b, np.sqrt(var) / b, mind / b,
+                     R.sum() / n / b, R.max() / b, (d < 0).mean(), np.abs(d).mean() / b,
+                     mind / rms, 1.0])
+
+
+def test_features_match_definition(gpu_ok):
+    """nolsm_features (two passes over M_k, partials combined in column order) against
+    the descriptors computed in FP64 from the same FP32 M_k read back."""
+    from paper_2205_12182_amd import learn
+    from paper_2205_12182_amd.runner import Runner
+    from workloads import get_config
+    inst = get_config("t_slab")
+    r = Runner(inst)
+    L.nolsm_build_submatrices(r.plans[0], r.dpat, r.H, r.S)
+    feat = learn.features(r, 0, inst.mu).cpu().numpy()
+    for i in [0, 7, inst.nmol // 2, inst.nmol - 1]:
+        info = r.sub_info(0, i)
+        Mk = r.ws_view(info.off_h, info.npad * info.npad, torch.float32).reshape(
+            info.npad, info.npad).T.cpu().numpy()
+        ref = reference_features(Mk, info.n, info.nmem, info.m, inst.mu)
+        assert np.allclose(feat[i], ref, rtol=2e-6, atol=2e-6), (i, feat[i], ref)
