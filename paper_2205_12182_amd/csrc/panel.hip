@@ -107,13 +107,14 @@ __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict
   }
 }
 
+// FP32 and BF16 iterates (FP16 ones go to panel_mfma_kernel).
 __global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restrict__ desc,
                                                         const SubState *__restrict__ st, char *ws,
                                                         int qp, int qq, int qo, float alpha,
                                                         float beta) {
   const SubDesc d = desc[blockIdx.y];
   const SubState &s = st[blockIdx.y];
-  if (s.status != 0 || blockIdx.x * PANEL_ROWS >= (unsigned)d.npad) return;
+  if (s.status != 0 || s.prec == P_FP16 || blockIdx.x * PANEL_ROWS >= (unsigned)d.npad) return;
   __shared__ float sX[PANEL_K][PANEL_ROWS + 4];
   __shared__ float sP[PANEL_K][MAXM];
   const float *P = panel_ptr(ws, d, qp);
@@ -129,6 +130,91 @@ __global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restric
   else
     panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, d.m, alpha,
                            beta, sX, sP);
+}
+
+// O = alpha X P + beta Q for submatrices iterating in FP16, on MFMAs.  X is exactly
+// FP16; P (FP32) is split as P = hi + 2^-11 lo with hi, lo FP16, so
+//   X P = X hi + 2^-11 X lo,
+// every term within 2^-22 of its exact value, sums in FP32 (two
+// v_mfma_f32_32x32x16_f16 per 32 x 32 block and 16 k).  A wave owns PM_BLK blocks
+// of 32 rows and all m <= 32 columns, so each B fragment (P, split in registers)
+// serves PM_BLK row blocks; A fragments come straight from X (row i of X is column
+// i, contiguous in k), B fragments from P (column c is contiguous in k).  Lane
+// (h, c) supplies k = 8 h .. 8 h + 7 of its row (A) and of column c (B); the result
+// D(r, c) of register q sits in lane c + 32 h with r = 8 (q / 4) + 4 h + q % 4.
+typedef _Float16 ph8 __attribute__((ext_vector_type(8)));
+typedef float pf16 __attribute__((ext_vector_type(16)));
+constexpr float PANEL_LO_SCALE = 2048.0f;
+constexpr int PM_BLK = 2;                         // 32-row blocks per wave
+constexpr int PM_ROWS = 4 * 32 * PM_BLK;          // rows per workgroup
+
+__global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restrict__ desc,
+                                                         const SubState *__restrict__ st,
+                                                         char *ws, int qp, int qq, int qo,
+                                                         float alpha, float beta) {
+  const SubDesc d = desc[blockIdx.y];
+  const SubState &s = st[blockIdx.y];
+  if (s.status != 0 || s.prec != P_FP16) return;
+  const int ld = d.npad, m = d.m;
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
+  const int i0 = blockIdx.x * PM_ROWS + 32 * PM_BLK * w;
+  if (i0 >= ld) return;                                   // the whole wave
+  int nb = (ld - i0) / 32;                                // row blocks inside the matrix
+  nb = nb > PM_BLK ? PM_BLK : nb;
+  const _Float16 *X = reinterpret_cast<const _Float16 *>(ws + d.off_lo) +
+                      (int64_t)s.cur * 2 * ld * ld;
+  const float *P = panel_ptr(ws, d, qp);
+  const float *Q = panel_ptr(ws, d, qq);
+  float *O = panel_ptr(ws, d, qo);
+  const bool live = c < m;
+  const _Float16 *xr = X + (int64_t)(i0 + c) * ld + 8 * h;
+  const float *pc = P + (int64_t)(live ? c : 0) * ld + 8 * h;
+  pf16 ah[PM_BLK], al[PM_BLK];
+#pragma unroll
+  for (int b = 0; b < PM_BLK; ++b)
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      ah[b][q] = 0.0f;
+      al[b][q] = 0.0f;
+    }
+#pragma unroll 4
+  for (int k = 0; k < ld; k += 16) {
+    float4 p0 = {0.0f, 0.0f, 0.0f, 0.0f}, p1 = p0;
+    if (live) {
+      p0 = *reinterpret_cast<const float4 *>(pc + k);
+      p1 = *reinterpret_cast<const float4 *>(pc + k + 4);
+    }
+    ph8 a[PM_BLK];
+#pragma unroll
+    for (int b = 0; b < PM_BLK; ++b)
+      if (b < nb) a[b] = *reinterpret_cast<const ph8 *>(xr + (int64_t)32 * b * ld + k);
+    const float pv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
+    ph8 bh, bl;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const _Float16 hi = (_Float16)pv[e];
+      bh[e] = hi;
+      bl[e] = (_Float16)((pv[e] - (float)hi) * PANEL_LO_SCALE);
+    }
+#pragma unroll
+    for (int b = 0; b < PM_BLK; ++b)
+      if (b < nb) {
+        ah[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[b], bh, ah[b], 0, 0, 0);
+        al[b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(a[b], bl, al[b], 0, 0, 0);
+      }
+  }
+  if (!live) return;
+#pragma unroll
+  for (int b = 0; b < PM_BLK; ++b) {
+    if (b >= nb) continue;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int r = i0 + 32 * b + 8 * (q >> 2) + 4 * h + (q & 3);
+      float v = alpha * (ah[b][q] + al[b][q] * (1.0f / PANEL_LO_SCALE));
+      if (beta != 0.0f) v += beta * Q[(int64_t)c * ld + r];
+      O[(int64_t)c * ld + r] = v;
+    }
+  }
 }
 
 // Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c]); the next 64-row chunk of
@@ -338,6 +424,8 @@ struct PanelCtx {
     const dim3 grid((max_npad + PANEL_ROWS - 1) / PANEL_ROWS, K);
     if (steps == 0) {
       const int qo = alloc();
+      panel_mfma_kernel<<<dim3((max_npad + PM_ROWS - 1) / PM_ROWS, K), 256, 0, s>>>(
+          desc, st, ws, qin, qin, qo, 1.0f, 0.0f);
       panel_mul_kernel<<<grid, 256, 0, s>>>(desc, st, ws, qin, qin, qo, 1.0f, 0.0f);
       return qo;
     }
