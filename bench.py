@@ -100,20 +100,72 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub):
     return cpu, err
 
 
-def measured_traffic(workload, schedule):
-    """HBM bytes per GEMM launch from the committed counter summary, if it was taken
-    for this kernel source, workload and schedule (otherwise None)."""
+TRAFFIC_PATH = os.path.join(ROOT, "profiles", "ns_gemm_rect_fp16_c2_traffic.json")
+
+
+def kernel_sources_sha256():
     import hashlib
-    path = os.path.join(ROOT, "profiles", "ns_gemm_rect_fp16_c2_traffic.json")
-    if not os.path.exists(path):
-        return None
-    with open(path) as fh:
-        rec = json.load(fh)
     h = hashlib.sha256()
     for f in ("ns_gemm.h", "ns_gemm_rect.h"):
         with open(os.path.join(ROOT, "paper_2205_12182_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    if (h.hexdigest() != rec["kernel_sources_sha256"] or rec["workload"] != workload
+    return h.hexdigest()
+
+
+def traffic_summary(fetch_db, write_db, workload, schedule, calib_mib, command):
+    """Write the sign GEMM's HBM bytes per launch from two rocprofv3 --pmc databases
+    (FETCH_SIZE, then WRITE_SIZE, in KiB per dispatch), each scaled by what the same
+    counter reads for the plain copy of calib_mib MiB that --calibrate-copy runs."""
+    import sqlite3
+
+    def per_kernel(db, counter):
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, kernel_name, value from counters_collection "
+                           "where counter_name = ?", (counter,)).fetchall()
+        con.close()
+        acc = {}
+        for did, name, v in rows:
+            key = ("square" if "ns_gemm_rect_kernel" in name and "Li0E" in name else
+                   "update" if "ns_gemm_rect_kernel" in name and "Li1E" in name else
+                   "copy" if "elementwise" in name and "MulFunctor" in name else None)
+            if key is None:
+                continue
+            acc.setdefault(key, {}).setdefault(did, 0.0)
+            acc[key][did] += v                   # summed over the counter's instances
+        return {k: sorted(d.values()) for k, d in acc.items()}
+
+    f, w = per_kernel(fetch_db, "FETCH_SIZE"), per_kernel(write_db, "WRITE_SIZE")
+    nbytes = calib_mib * (1 << 20)
+    f_copy, w_copy = f["copy"][len(f["copy"]) // 2], w["copy"][len(w["copy"]) // 2]
+    fs, ws = nbytes / (f_copy * 1024.0), nbytes / (w_copy * 1024.0)
+    rec = {"kernel": "ns_gemm_rect_kernel<_Float16> (SQUARE and UPDATE), 256x128 tiles",
+           "kernel_sources_sha256": kernel_sources_sha256(), "workload": workload,
+           "schedule": schedule, "command": command,
+           "calibration": {"copy_bytes_read": nbytes, "fetch_kib_read": f_copy,
+                           "fetch_scale": round(fs, 3), "copy_bytes_written": nbytes,
+                           "write_kib_read": w_copy, "write_scale": round(ws, 3)},
+           "dispatches_per_product": len(f["square"])}
+    tot = 0.0
+    for k in ("square", "update"):
+        fb = float(np.mean(f[k])) * 1024.0 * round(fs, 3)
+        wb = float(np.mean(w[k])) * 1024.0 * round(ws, 3)
+        rec[k] = {"fetch_bytes": fb, "write_bytes": wb}
+        tot += fb + wb
+    rec["per_launch_bytes"] = tot / 2.0
+    with open(TRAFFIC_PATH, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    log(f"wrote {TRAFFIC_PATH}: {rec['per_launch_bytes'] / 1e9:.2f} GB per launch "
+        f"(fetch x{fs:.3f}, write x{ws:.3f})")
+
+
+def measured_traffic(workload, schedule):
+    """HBM bytes per GEMM launch from the committed counter summary, if it was taken
+    for this kernel source, workload and schedule (otherwise None)."""
+    if not os.path.exists(TRAFFIC_PATH):
+        return None
+    with open(TRAFFIC_PATH) as fh:
+        rec = json.load(fh)
+    if (kernel_sources_sha256() != rec["kernel_sources_sha256"] or rec["workload"] != workload
             or rec["schedule"] != schedule):
         return None
     return float(rec["per_launch_bytes"])
@@ -150,11 +202,20 @@ def main():
                     help="timed replays of the step captured as a HIP graph (0: skip)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, three elementwise copies of MIB MiB (counter scaling)")
+    ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="write the GEMM traffic profile from two rocprofv3 --pmc databases "
+                         "(runs nothing on the GPU); with --calibrate-copy, --workload, "
+                         "--schedule and --traffic-command")
+    ap.add_argument("--traffic-command", default="", help="command recorded in the profile")
     args = ap.parse_args()
+    if args.traffic_summary:
+        traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.workload,
+                        args.schedule or "learned", args.calibrate_copy or 1024,
+                        args.traffic_command)
+        return
     if args.gpus != 1:
-        print("bench.py measures one GPU: the method's submatrices are independent, so the "
-              "multi-GPU path is a design note, not part of this build (run with --gpus 1)",
-              file=sys.stderr)
+        print("bench.py runs on one GPU only (with more GPUs each would take its own share of "
+              "the independent submatrices); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -279,7 +340,8 @@ def main():
                                 (", learned lower bound -> scaled iteration (cap 16)"
                                  if args.schedule == "learned" else ", unscaled") +
                                 ", Gershgorin scale, FP32 fallback and panel step, FP64 "
-                                "Cholesky/L^-1/D columns/traces, FP32 set-up products"),
+                                "Cholesky/L^-1/D columns/traces, set-up and panel products on "
+                                "FP16 MFMAs with split (hi + 2^-11 lo) FP32-class operands"),
                    "iters_mean": round(float(st["iters_lo"].mean()), 2),
                    "fallbacks": int(st["fell_back"].sum()),
                    "parallelism": "none (1 GPU)"},
