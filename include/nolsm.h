@@ -133,9 +133,11 @@ typedef struct {
 typedef struct {
   int32_t n, npad, mol, m;        /* dimension, leading dimension, molecule, own columns */
   int32_t own_lo, nmem, pad0, pad1;
-  int64_t off_h;                  /* bytes: H_k (FP64 npad x npad), then M_k (FP32)     */
+  int64_t off_h;                  /* bytes: M_k (FP32 npad x npad); H_k (FP64) before it
+                                     with FP32 set-up products                          */
   int64_t off_s;                  /* bytes: FP64 npad x npad, S_k then L^-1 (lower)    */
-  int64_t off_lo;                 /* bytes: three npad x npad low-precision buffers     */
+  int64_t off_lo;                 /* bytes: three 4 npad^2-byte buffers: split FP16 rows
+                                     of L^-1, H, U during the set-up, then the iterates */
   int64_t off_dcol;               /* bytes: FP64 npad x m density columns               */
 } nolsm_sub_info;
 

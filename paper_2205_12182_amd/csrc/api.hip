@@ -13,7 +13,7 @@
 namespace nolsm {
 void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
-                   const double *S_val, char *ws, hipStream_t stream);
+                   const double *S_val, bool split_h, char *ws, hipStream_t stream);
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                   bool fp32_products, char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
@@ -314,7 +314,8 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, co
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   const int ev = p->log.begin(T_GATHER, s);
-  launch_gather(desc, p->K, p->maxmem, mem_mol, mem_loc, pat, H_val, S_val, p->ws, s);
+  launch_gather(desc, p->K, p->maxmem, mem_mol, mem_loc, pat, H_val, S_val, !p->setup_fp32,
+                p->ws, s);
   p->log.end(ev, s);
   p->setup_done = false;
   return hip_check("nolsm_build_submatrices");

@@ -7,6 +7,10 @@
 // output column is a contiguous run of n doubles, so writes are coalesced, and
 // each stored block is read contiguously.  The padding rows/columns (n..npad) are
 // written as well: zero for H, the identity for S.
+//
+// SPLIT_H: T_k(H0) goes straight into the split FP16 operand of the set-up products
+// (row j = column j by symmetry, npad hi parts then npad lo parts, x = hi + 2^-11 lo)
+// instead of the FP64 H buffer.
 #include "common.h"
 
 namespace nolsm {
@@ -14,6 +18,7 @@ namespace nolsm {
 constexpr int GATHER_MAXMEM = 1024;     // members per submatrix held in LDS
 constexpr int GATHER_MAXN = 8192;       // submatrix dimension held in the LDS row map
 
+template <bool SPLIT_H>
 __global__ __launch_bounds__(256) void gather_kernel(
     const SubDesc *__restrict__ desc, const int32_t *__restrict__ mem_mol,
     const int32_t *__restrict__ mem_loc, const int32_t *__restrict__ blk_dim,
@@ -30,11 +35,17 @@ __global__ __launch_bounds__(256) void gather_kernel(
   double *Hk = reinterpret_cast<double *>(ws + d.off_h);
   double *Sk = reinterpret_cast<double *>(ws + d.off_s);
   const int n = d.n, ld = d.npad;
+  _Float16 *Hs = reinterpret_cast<_Float16 *>(ws + d.off_lo) + 2 * (int64_t)ld * ld;   // buffer 1
 
   if (b == d.nmem) {                            // columns n..npad: zero / identity
     for (int c = n; c < ld; ++c)
       for (int r = threadIdx.x; r < ld; r += blockDim.x) {
-        Hk[(int64_t)c * ld + r] = 0.0;
+        if (SPLIT_H) {
+          Hs[(int64_t)c * 2 * ld + r] = (_Float16)0.0f;
+          Hs[(int64_t)c * 2 * ld + ld + r] = (_Float16)0.0f;
+        } else {
+          Hk[(int64_t)c * ld + r] = 0.0;
+        }
         Sk[(int64_t)c * ld + r] = (r == c) ? 1.0 : 0.0;
       }
     return;
@@ -64,6 +75,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
   // one member are contiguous in both the stored block and the output column
   for (int c = 0; c < dJ; ++c) {
     double *hcol = Hk + (int64_t)(locb + c) * ld;
+    _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
     double *scol = Sk + (int64_t)(locb + c) * ld;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
       double h = 0.0, sv = 0.0;
@@ -76,7 +88,13 @@ __global__ __launch_bounds__(256) void gather_kernel(
           sv = S_val[src];
         }
       }
-      hcol[i] = h;
+      if (SPLIT_H) {
+        const _Float16 hi = (_Float16)h;                 // one rounding from FP64
+        hrow[i] = hi;
+        hrow[ld + i] = (_Float16)((h - (double)hi) * 2048.0);
+      } else {
+        hcol[i] = h;
+      }
       scol[i] = sv;
     }
   }
@@ -84,10 +102,16 @@ __global__ __launch_bounds__(256) void gather_kernel(
 
 void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
-                   const double *S_val, char *ws, hipStream_t stream) {
+                   const double *S_val, bool split_h, char *ws, hipStream_t stream) {
   dim3 grid(maxmem + 1, K);
-  gather_kernel<<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim, pat->colptr,
-                                          pat->rowblk, pat->valoff, H_val, S_val, ws);
+  if (split_h)
+    gather_kernel<true><<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim,
+                                                  pat->colptr, pat->rowblk, pat->valoff, H_val,
+                                                  S_val, ws);
+  else
+    gather_kernel<false><<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim,
+                                                   pat->colptr, pat->rowblk, pat->valoff, H_val,
+                                                   S_val, ws);
 }
 
 }  // namespace nolsm

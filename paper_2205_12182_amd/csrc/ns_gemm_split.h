@@ -43,8 +43,8 @@ __device__ __forceinline__ void split_f16(float v, _Float16 &hi, _Float16 &lo) {
   lo = (_Float16)((v - (float)hi) * SPLIT_LO_SCALE);
 }
 __device__ __forceinline__ void split_f16(double v, _Float16 &hi, _Float16 &lo) {
-  hi = (_Float16)(float)v;
-  lo = (_Float16)(float)((v - (double)(float)hi) * (double)SPLIT_LO_SCALE);
+  hi = (_Float16)v;                               // one rounding from FP64
+  lo = (_Float16)((v - (double)hi) * (double)SPLIT_LO_SCALE);
 }
 
 // C(m, c) = sum_k A(m, k) B(c, k) over k < kend for the tile at (i0, j0); A and B

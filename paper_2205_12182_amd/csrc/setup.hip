@@ -558,10 +558,10 @@ __global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__res
 }
 
 
-// Split FP16 operands of the set-up products (buffer 0: row r = L^-1(r, :), through
-// an LDS tile since L^-1 is stored by columns; buffer 1: row r = H(r, :) = H(:, r)).
-// Each row holds the npad hi parts, then the npad lo parts.  Every thread converts
-// four consecutive elements: 32-byte reads, 8-byte stores of hi and of lo.
+// Split FP16 operand of the set-up products for L^-1: buffer 0, row r = L^-1(r, :)
+// (through an LDS tile, since L^-1 is stored by columns), npad hi parts then npad lo
+// parts.  (Buffer 1, the rows of H, is written by the gather.)  Every thread
+// converts four consecutive elements: 8-byte stores of hi and of lo.
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restrict__ desc,
@@ -571,26 +571,14 @@ __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restri
   if ((int)blockIdx.x >= nt * nt) return;
   const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
   _Float16 *Ls = reinterpret_cast<_Float16 *>(ws + d.off_lo);
-  _Float16 *Hs = Ls + 2 * (int64_t)ld * ld;
   const int64_t lds = 2 * (int64_t)ld;
   __shared__ double tile[64][65];
   for (int e = threadIdx.x; e < 64 * 16; e += 256) {
     const int r4 = (e & 15) * 4, c = e >> 4;
     const int64_t o = (int64_t)(bj * 64 + c) * ld + bi * 64 + r4;   // (bi 64 + r4, bj 64 + c)
     const d4 sv = *reinterpret_cast<const d4 *>(Sb + o);
-    const d4 hv = *reinterpret_cast<const d4 *>(Hb + o);
-    h4 hh, hl;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      tile[c][r4 + q] = sv[q];
-      _Float16 a, b;
-      split_f16(hv[q], a, b);                     // H(bj 64 + c, bi 64 + r4 + q) by symmetry
-      hh[q] = a;
-      hl[q] = b;
-    }
-    _Float16 *hrow = Hs + (int64_t)(bj * 64 + c) * lds + bi * 64 + r4;
-    *reinterpret_cast<h4 *>(hrow) = hh;
-    *reinterpret_cast<h4 *>(hrow + ld) = hl;
+    for (int q = 0; q < 4; ++q) tile[c][r4 + q] = sv[q];
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 64 * 16; e += 256) {

@@ -48,23 +48,45 @@ def print_case(*a):
     print("[case]", *a, flush=True)
 
 
-def test_gather_bit_exact(gpu_ok):
+def split_rows(r, info):
+    """The split FP16 rows of H (hi parts, lo parts) the gather writes for the split
+    set-up products: iteration buffer 1, npad rows of 2 npad values."""
+    npad = info.npad
+    v = r.ws_view(info.off_lo + 4 * npad * npad, 2 * npad * npad, torch.float16)
+    v = v.reshape(npad, 2 * npad).cpu().numpy()
+    return v[:, :npad], v[:, npad:]
+
+
+@pytest.mark.parametrize("setup", [L.SETUP_SPLIT_FP16, L.SETUP_FP32])
+def test_gather_bit_exact(gpu_ok, setup):
+    """S_k in FP64 and H_k in FP64 (FP32 set-up option) equal the oracle's gather bit
+    for bit; with split set-up products, H_k arrives as hi = fp16(H), lo = fp16(2^11
+    (H - hi)), each rounded once from FP64, also bit for bit."""
     inst = get_config("t_slab")
-    print_case("gather t_slab")
-    r = Runner(inst)
+    print_case("gather t_slab", setup)
+    r = Runner(inst, setup_products=setup)
     L.nolsm_build_submatrices(r.plans[0], r.dpat, r.H, r.S)
     torch.cuda.synchronize()
     for i in [0, 1, inst.nmol // 2, inst.nmol - 1]:
         info = r.sub_info(0, i)
         npad, n = info.npad, info.n
-        Hk = col_major(r.ws_view(info.off_h, npad * npad, torch.float64), npad)
         Sk = col_major(r.ws_view(info.off_s, npad * npad, torch.float64), npad)
         Href, offs = O.gather(inst, inst.H_val, info.mol)
         Sref, _ = O.gather(inst, inst.S_val, info.mol)
         assert n == Href.shape[0]
-        assert np.array_equal(Hk[:n, :n], Href)
+        if setup == L.SETUP_FP32:
+            Hk = col_major(r.ws_view(info.off_h, npad * npad, torch.float64), npad)
+            assert np.array_equal(Hk[:n, :n], Href)
+            assert not Hk[n:, :].any() and not Hk[:, n:].any()
+        else:
+            hi, lo = split_rows(r, info)
+            ref_hi = Href.astype(np.float16)
+            ref_lo = ((Href - ref_hi.astype(np.float64)) * 2048.0).astype(np.float16)
+            assert np.array_equal(hi[:n, :n].view(np.uint16), ref_hi.view(np.uint16))
+            assert np.array_equal(lo[:n, :n].view(np.uint16), ref_lo.view(np.uint16))
+            assert not hi[n:, :].any() and not hi[:, n:].any()
+            assert not lo[n:, :].any() and not lo[:, n:].any()
         assert np.array_equal(Sk[:n, :n], Sref)
-        assert not Hk[n:, :].any() and not Hk[:, n:].any()
         assert np.array_equal(Sk[n:, n:], np.eye(npad - n)) and not Sk[n:, :n].any()
         assert info.own_lo == int(O.own_columns(inst, info.mol, offs)[0])
 
