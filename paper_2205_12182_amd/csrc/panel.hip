@@ -16,6 +16,8 @@
 
 namespace nolsm {
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ float *panel_ptr(char *ws, const SubDesc &d, int q) {
   return reinterpret_cast<float *>(ws + d.off_panel) + (int64_t)q * d.npad * d.m;
 }
@@ -217,8 +219,11 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
   }
 }
 
-// Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c]); the next 64-row chunk of
-// L^-1 and V - W is loaded into registers while the current one is used.
+// Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c]) in FP64; the next 64-row
+// chunk of L^-1 and V - W is loaded into registers while the current one is used.
+// The contraction runs on v_mfma_f64_16x16x4_f64: wave w owns rows i0 + 16 w .. + 15
+// and the two 16-column blocks; A(i, k) = L^-1(k, i) comes from lane i + 16 k and
+// B(k, c) from lane c + 16 k, and D(i, c) sits in lane c + 16 (i % 4), register i / 4.
 __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ desc,
                                                    const SubState *__restrict__ st, char *ws,
                                                    int qv, int qw) {
@@ -233,10 +238,8 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
   double *Dc = reinterpret_cast<double *>(ws + d.off_dcol);
   __shared__ double sL[64][65];     // sL[i][k] = Linv[k0 + k, i0 + i]
   __shared__ double sU[64][33];
-  const int tid = threadIdx.x, il = tid & 63, cg = tid >> 6;
-  double acc[8];
-#pragma unroll
-  for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
   double lv[16], uv[8];
   auto fetch = [&](int k0) {
 #pragma unroll
@@ -269,13 +272,14 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
   for (int k0 = i0; k0 < ld; k0 += 64) {
     const bool more = k0 + 64 < ld;
     if (more) fetch(k0 + 64);
-    for (int kk = 0; kk < 64; ++kk) {
-      const double l = sL[il][kk];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const int c = cg + 4 * q;
-        if (c < m) acc[q] += l * sU[kk][c];
-      }
+    for (int kk = 0; kk < 64; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      const double a = sL[16 * w + (lane & 15)][kr];
+#pragma unroll
+      for (int t = 0; t < 2; ++t)
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sU[kr][16 * t + (lane & 15)], acc[t],
+                                                       0, 0, 0);
     }
     __syncthreads();
     if (more) {
@@ -284,9 +288,12 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
     }
   }
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int c = cg + 4 * q;
-    if (c < m) Dc[(int64_t)c * ld + i0 + il] = 0.5 * acc[q];
+  for (int t = 0; t < 2; ++t) {
+    const int c = 16 * t + (lane & 15);
+    if (c >= m) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      Dc[(int64_t)c * ld + i0 + 16 * w + 4 * q + (lane >> 4)] = 0.5 * acc[t][q];
   }
 }
 

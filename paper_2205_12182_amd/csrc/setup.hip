@@ -614,23 +614,24 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
                   bool fp32_products, char *ws, hipStream_t s) {
   const int nbmax = max_npad / NB;
   launch_reset_status(st, K, 0, s);
-  // Right-looking blocked Cholesky with two levels: inside an outer block of OB
-  // columns the 64-wide steps update only the outer block's own columns; the
-  // trailing matrix receives the outer block's OB columns in one update (k = OB),
-  // which reads and writes it OB / 64 times less often.
+  // Blocked Cholesky with two levels: inside an outer block of OB columns each
+  // 64-wide column block first receives the earlier panels of the same outer block
+  // in one update (k = 64, 128, 192: left-looking inside the block), then is
+  // factored; the trailing matrix receives the outer block's OB columns in one
+  // update (k = OB, right-looking between blocks), which reads and writes it OB / 64
+  // times less often than 64-wide steps would.
   constexpr int OBB = 4;                        // outer block = 4 x 64 columns
   for (int J = 0; J < nbmax; J += OBB) {
     const int Jend = J + OBB < nbmax ? J + OBB : nbmax;
     for (int jb = J; jb < Jend; ++jb) {
+      if (jb > J) {
+        const int rows = nbmax - jb;
+        chol_update_kernel<<<dim3(rows, K), 256, 0, s>>>(desc, ws, J * NB, jb * NB, jb, jb + 1,
+                                                         rows);
+      }
       chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
       const int rem = nbmax - jb - 1;
-      if (rem > 0) {
-        chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
-        const int cb0 = jb + 1, cb1 = Jend, rows = nbmax - cb0;
-        if (cb1 > cb0)
-          chol_update_kernel<<<dim3(rows * (cb1 - cb0), K), 256, 0, s>>>(
-              desc, ws, jb * NB, (jb + 1) * NB, cb0, cb1, rows);
-      }
+      if (rem > 0) chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
     }
     if (Jend < nbmax) {
       // Jend * 64 is a multiple of 256 here, so the 128-wide tiles start aligned
