@@ -324,13 +324,18 @@ constexpr int LDQ = 128 + 1;        // padded LDS row (doubles) of the 128-wide 
 constexpr int T128_THREADS = 512;
 typedef double Stage128[KS64 * LDQ];
 
+// A wave whose rows all lie at or past nA, whose columns all lie at or past nB, or
+// (lower) whose block lies above the diagonal of a diagonal tile issues no MFMAs (its
+// accumulators stay zero and the function returns true); it still loads its share of
+// every stage, so the MFMA pipe of its SIMD serves the other waves.
 template <bool TB>
-__device__ __forceinline__ void tile128_f64(const double *__restrict__ A, int64_t lda,
+__device__ __forceinline__ bool tile128_f64(const double *__restrict__ A, int64_t lda,
                                             const double *__restrict__ B, int64_t ldb, int nA,
                                             int nB, int k0, int k1, d4 acc[2][4], Stage128 *sA,
-                                            Stage128 *sB) {
+                                            Stage128 *sB, bool lower = false) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
+  const bool idle = wm >= nA || wn >= nB || (lower && wm + 31 < wn);
   // element q of this thread's share of a stage: row m = idx & 127, k = idx >> 7
   double ra[4], rb[4];
   auto load = [&](int k) {
@@ -357,7 +362,7 @@ __device__ __forceinline__ void tile128_f64(const double *__restrict__ A, int64_
         sB[b][(idx & 15) * LDQ + (idx >> 4)] = rb[q];
     }
   };
-  if (k0 >= k1) return;
+  if (k0 >= k1) return idle;
   load(k0);
   store(0);
   __syncthreads();
@@ -365,24 +370,27 @@ __device__ __forceinline__ void tile128_f64(const double *__restrict__ A, int64_
   for (int k = k0; k < k1; k += KS64) {
     const bool more = k + KS64 < k1;
     if (more) load(k + KS64);
+    if (!idle) {
 #pragma unroll
-    for (int kk = 0; kk < KS64; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      double a[2], bb[4];
+      for (int kk = 0; kk < KS64; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        double a[2], bb[4];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) a[t] = sA[b][kr * LDQ + wm + 16 * t + (lane & 15)];
+        for (int t = 0; t < 2; ++t) a[t] = sA[b][kr * LDQ + wm + 16 * t + (lane & 15)];
 #pragma unroll
-      for (int t = 0; t < 4; ++t) bb[t] = sB[b][kr * LDQ + wn + 16 * t + (lane & 15)];
+        for (int t = 0; t < 4; ++t) bb[t] = sB[b][kr * LDQ + wn + 16 * t + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], bb[j], acc[i][j], 0, 0, 0);
+      }
     }
     if (more) store(b ^ 1);
     __syncthreads();
     b ^= 1;
   }
+  return idle;
 }
 
 // Visit this thread's elements of a 128 x 128 tile: f(r, c, value).
@@ -417,7 +425,9 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  tile128_f64<false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, acc, sA, sB);
+  if (tile128_f64<false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, acc, sA, sB,
+                         ti == tj))
+    return;                                       // nothing to subtract
   acc128_foreach(acc, [&](int r, int c, double v) {
     if (r0 + r < ld && c0 + c < ld) {
       double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
