@@ -1,0 +1,56 @@
+"""The benchmark workload at full size (needs an MI355X).
+
+All 4,096 molecules of the c2 water box (n 1,679-1,863) go through the path in the
+configuration bench.py times (batches of 1,024 submatrices sharing one workspace, the
+learned schedule when trained weights are committed).  Every submatrix must finish
+without error and sampled molecules from every batch must match the FP64 oracle to
+the accuracy target: every written density element within 1e-3 and the energy of
+the sampled molecules within 1e-5 Ha/atom.
+"""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import nolsm_oracle as O
+from paper_2205_12182_amd import learn
+from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, learned_schedule
+from workloads import get_config
+
+pytestmark = pytest.mark.gpu
+
+D_TOL, E_TOL = 1e-3, 1e-5
+WEIGHTS = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
+
+
+def test_c2_full_size_sampled_parity(gpu_ok):
+    inst = get_config("c2")
+    print(f"[case] c2 full size: {inst.nmol} molecules in batches of 1024", flush=True)
+    r = Runner(inst, batch=1024)
+    if os.path.exists(WEIGHTS):
+        model, sched = learn.ScheduleMLP.load(WEIGHTS), learned_schedule()
+    else:
+        model, sched = None, default_mixed_schedule()
+    r.run(sched=sched, predictor=model)
+    torch.cuda.synchronize()
+    st = r.stats_host()
+    assert (st["status"] == 0).all()
+    D = r.D.cpu().numpy()
+    picks = [0, 700, 1024, 1800, 2048, 2900, 3072, 4095]     # two per batch
+    dmax, de, atoms = 0.0, 0.0, 0
+    for k in picks:
+        ref = O.submatrix_result(inst, k)
+        got = np.zeros_like(ref["D_cols"])
+        for a, I in enumerate(ref["members"]):
+            t = int(inst.colptr[k]) + a
+            dI, m = int(inst.blk_dim[I]), int(inst.blk_dim[k])
+            got[ref["offs"][a]:ref["offs"][a + 1], :] = \
+                D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
+        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
+        de += float(st["tr_dh"][k]) - ref["tr_dh"]
+        atoms += int(inst.atoms[k])
+    print(f"[case] c2 vs oracle: dD {dmax:.2e} dE/atom {abs(de) / atoms:.2e} "
+          f"(iterations {st['iters_lo'].mean():.2f}, restarts {int(st['fell_back'].sum())})",
+          flush=True)
+    assert dmax <= D_TOL and abs(de) / atoms <= E_TOL

@@ -249,3 +249,49 @@ def test_tile_shapes_agree_bitwise(gpu_ok):
         assert r.check() == L.OK, L.nolsm_last_error()
         out.append((r.D.clone(), r.energy_host()))
     assert torch.equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+
+
+@pytest.mark.parametrize("nmol,r_cut,seed", [(27, 2.0, 3), (64, 3.6, 5)])
+def test_single_tile_submatrices(gpu_ok, nmol, r_cut, seed):
+    """Submatrices smaller than one 64-wide block (n = 6: each molecule alone; n = 30-42):
+    every tile is a ragged edge tile, the factorisation and inverse are one diagonal
+    block, and the FP32 and mixed schedules still match the oracle."""
+    from workloads.water import water_box
+    inst = water_box(nmol, (4, 1, 1), r_cut, seed=seed, name="tiny")
+    dims = inst.submatrix_dims()
+    print_case(f"tiny water box: {nmol} molecules, n {dims.min()}-{dims.max()}")
+    D_ref, _ = O.density_matrix(inst)
+    e_ref, _ = O.traces(inst, D_ref, inst.H_val, inst.S_val)
+    for sched, dtol, etol in ((plain_fp32_schedule(), 1e-4, 1e-6),
+                              (default_mixed_schedule(), D_TOL, E_TOL)):
+        r = Runner(inst)
+        r.run(sched=sched)
+        assert r.check() == L.OK, L.nolsm_last_error()
+        dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+        print_case("dD", dmax, "dE/atom", de)
+        assert dmax < dtol and de < etol
+
+
+def test_empty_plan(gpu_ok):
+    """A plan of no molecules binds and runs every entry point as a no-op."""
+    inst = get_config("c1")
+    hp = L.HostPattern(inst)
+    dp = L.DevicePattern(inst, "cuda")
+    plan = L.nolsm_plan_create(hp, np.zeros(0, dtype=np.int32))
+    try:
+        tab = torch.empty(max(L.nolsm_plan_table_bytes(plan), 256), dtype=torch.uint8,
+                          device="cuda")
+        ws = torch.empty(max(L.nolsm_plan_workspace_bytes(plan), 256), dtype=torch.uint8,
+                         device="cuda")
+        H = torch.from_numpy(inst.H_val).cuda()
+        S = torch.from_numpy(inst.S_val).cuda()
+        D = torch.full_like(H, 7.0)
+        L.nolsm_plan_bind(plan, tab, ws)
+        L.nolsm_build_submatrices(plan, dp, H, S)
+        L.nolsm_sign_batched(plan, inst.mu, default_mixed_schedule())
+        L.nolsm_scatter_density(plan, dp, D, H, S)
+        torch.cuda.synchronize()
+        assert L.nolsm_check(plan) == L.OK
+        assert bool((D == 7.0).all())                  # nothing written
+    finally:
+        L.nolsm_plan_destroy(plan)
