@@ -6,7 +6,9 @@
 // the column-major block column into the dense column-major submatrix: each
 // output column is a contiguous run of n doubles, so writes are coalesced, and
 // each stored block is read contiguously.  The padding rows/columns (n..npad) are
-// written as well: zero for H, the identity for S.
+// written as well: zero for H, the identity for S.  Of T_k(S) only the lower
+// triangle (with the diagonal) is written: the factorisation reads nothing else,
+// and the upper triangle is cleared before the inverse.
 //
 // SPLIT_H: T_k(H0) goes straight into the split FP16 operand of the set-up products
 // (row j = column j by symmetry, npad hi parts then npad lo parts, x = hi + 2^-11 lo)
@@ -77,6 +79,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
     double *hcol = Hk + (int64_t)(locb + c) * ld;
     _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
     double *scol = Sk + (int64_t)(locb + c) * ld;
+    const int col = locb + c;
     for (int i = threadIdx.x; i < ld; i += blockDim.x) {
       double h = 0.0, sv = 0.0;
       if (i < n) {
@@ -85,7 +88,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
         if (v0 >= 0) {
           const int64_t src = v0 + (i - s_loc[a]) + c * s_dim[a];
           h = H_val[src];
-          sv = S_val[src];
+          if (i >= col) sv = S_val[src];
         }
       }
       if (SPLIT_H) {
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
       } else {
         hcol[i] = h;
       }
-      scol[i] = sv;
+      if (i >= col) scol[i] = sv;               // the factorisation reads the lower triangle
     }
   }
 }
