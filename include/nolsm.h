@@ -215,7 +215,10 @@ nolsm_status nolsm_setup_batched(nolsm_plan *plan, hipStream_t stream);
  * row k = (log n, members/100, m/32, log b, Gershgorin lower and upper edge / b,
  * Tr A/(n b), ||A||_F/(sqrt(n) b), std diag/b, min|A_ii|/b, mean and max
  * off-diagonal row sum / b, fraction of negative diagonal entries,
- * mean|A_ii|/b, min|A_ii| / (||A||_F/sqrt(n)), 1), with b the Gershgorin bound. */
+ * mean|A_ii|/b, min|A_ii| / (||A||_F/sqrt(n)), 1), with b the Gershgorin bound.
+ * The bounds b also stay in the plan's state: a following nolsm_sign_batched with
+ * the same mu (and no new gather or set-up in between) scales by them instead of
+ * making its own pass over M_k. */
 #define NOLSM_NFEAT 16
 nolsm_status nolsm_features(nolsm_plan *plan, double mu, float *feat, hipStream_t stream);
 

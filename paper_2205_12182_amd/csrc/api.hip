@@ -17,8 +17,8 @@ void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mo
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                   bool fp32_products, char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                 char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
-                 double flop, hipStream_t s);
+                 char *ws, double mu, const nolsm_schedule &sch, bool have_scale,
+                 EventLog *log, double flop, hipStream_t s);
 void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
                             char *ws, int panel_steps, hipStream_t s);
 void launch_scatter(const SubDesc *desc, const SubState *st, int K, const int32_t *mem_mol,
@@ -30,7 +30,7 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
                   hipStream_t s);
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
-void launch_features(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+void launch_features(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
                      double mu, float *feat, hipStream_t s);
 }  // namespace nolsm
 
@@ -57,6 +57,8 @@ struct nolsm_plan {
   char *ws = nullptr;
   bool bound = false;
   bool setup_done = false;      // M_k and L^-1 are current (set-up ran after the last gather)
+  bool scale_ready = false;     // the Gershgorin bounds of M_k - scale_mu I are in the state
+  double scale_mu = 0.0;        //   (written by nolsm_features after the last set-up)
   double gemm_flop = 0.0;       // executed MFMA flops of one sign GEMM launch (all tiles)
   EventLog log;
 };
@@ -264,6 +266,7 @@ nolsm_status nolsm_plan_bind(nolsm_plan *p, void *tables, size_t table_bytes, vo
     p->tab = tab;
   }
   p->setup_done = false;        // the workspace may have served another plan since
+  p->scale_ready = false;
   p->ws = static_cast<char *>(workspace);
   p->bound = true;
   return NOLSM_OK;
@@ -318,6 +321,7 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, co
                 p->ws, s);
   p->log.end(ev, s);
   p->setup_done = false;
+  p->scale_ready = false;
   return hip_check("nolsm_build_submatrices");
 }
 
@@ -359,9 +363,12 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
     launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, p->ws, s);
     p->log.end(ev, s);
     p->setup_done = true;
+    p->scale_ready = false;
   }
   ev = p->log.begin(T_SIGN, s);
-  launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, &p->log, p->gemm_flop, s);
+  const bool have_scale = p->scale_ready && p->scale_mu == mu;
+  launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, have_scale, &p->log,
+              p->gemm_flop, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
   p->log.end(ev, s);
@@ -381,6 +388,7 @@ nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
   launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->setup_fp32, p->ws, s);
   p->log.end(ev, s);
   p->setup_done = true;
+  p->scale_ready = false;
   return hip_check("nolsm_setup_batched");
 }
 
@@ -395,6 +403,8 @@ nolsm_status nolsm_features(nolsm_plan *p, double mu, float *feat, hipStream_t s
   }
   PLAN_PTRS
   launch_features(desc, st, p->K, p->max_npad, p->ws, mu, feat, s);
+  p->scale_ready = true;              // the descriptors include the Gershgorin bounds
+  p->scale_mu = mu;
   return hip_check("nolsm_features");
 }
 

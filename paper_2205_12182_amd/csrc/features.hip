@@ -70,9 +70,11 @@ __global__ __launch_bounds__(256) void features_part_kernel(const SubDesc *__res
   part[blockIdx.x] = t;
 }
 
-// Pass 2: one thread per submatrix combines the partials in column order.
+// Pass 2: one thread per submatrix combines the partials in column order.  The
+// Gershgorin bound b = max_c sum_r |A_rc| also goes to the state as the scale of
+// the sign iteration (the same quantity the sign call would otherwise compute).
 __global__ __launch_bounds__(256) void features_final_kernel(const SubDesc *__restrict__ desc,
-                                                             const SubState *__restrict__ st,
+                                                             SubState *__restrict__ st,
                                                              const char *ws, int K,
                                                              float *__restrict__ feat) {
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -96,9 +98,10 @@ __global__ __launch_bounds__(256) void features_final_kernel(const SubDesc *__re
       (float)(t.neg / n), (float)(t.sabsd / n / b), (float)(rms > 0.0 ? t.mind / rms : 0.0),
       1.0f};
   for (int i = 0; i < NOLSM_NFEAT; ++i) f[i] = bad ? 0.0f : v[i];
+  st[k].scale_bits = t.bmax > 0.0 ? (unsigned long long)__double_as_longlong(t.bmax) : 0ull;
 }
 
-void launch_features(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+void launch_features(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
                      double mu, float *feat, hipStream_t s) {
   features_part_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, ws, mu);
   features_final_kernel<<<(K + 255) / 256, 256, 0, s>>>(desc, st, ws, K, feat);

@@ -414,12 +414,16 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
 }
 
 // flop: executed MFMA flops of one GEMM launch over every tile of the plan.
+// have_scale: the Gershgorin bounds for this mu are already in the state (written with
+// the descriptors of the learned schedule), so the pass over M_k is skipped.
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                 char *ws, double mu, const nolsm_schedule &sch, EventLog *log,
-                 double flop, hipStream_t s) {
+                 char *ws, double mu, const nolsm_schedule &sch, bool have_scale,
+                 EventLog *log, double flop, hipStream_t s) {
   launch_reset_status(st, K, 1, s);
-  clear_scale_kernel<<<nblk(K), 256, 0, s>>>(st, K);
-  gersh_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, mu);
+  if (!have_scale) {
+    clear_scale_kernel<<<nblk(K), 256, 0, s>>>(st, K);
+    gersh_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, mu);
+  }
   scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower, sch.lower_log10,
                                             sch.lower_factor, sch.phase[0].prec, 0);
   cast_kernel<<<dim3((max_npad + CAST_COLS - 1) / CAST_COLS, K), 256, 0, s>>>(desc, st, ws, mu);
