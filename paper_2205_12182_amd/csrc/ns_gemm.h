@@ -30,6 +30,7 @@ namespace nolsm {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
 typedef float f16x __attribute__((ext_vector_type(16)));
+typedef float f4x __attribute__((ext_vector_type(4)));
 
 // SQUARE: Z = c1 I + c3 X X (+ residual); UPDATE: X' = X Z; PLAIN_SYM: the plain
 // product of a symmetric result (upper tiles, mirrored); PLAIN_FULL: the plain

@@ -4,15 +4,19 @@
 // The 256 x 256 tile of ns_gemm_body needs all 512 registers of a SIMD lane for
 // its accumulators, so only one workgroup fits per CU and the tile's loads and
 // its epilogue stores (the new iterate, written once in each triangle) cannot
-// overlap with MFMAs.  Here a wave owns a 128 x 64 block (4 x 2 blocks of
-// 32 x 32, 128 accumulator registers), a workgroup of four waves a 256 x 128
-// tile, and the LDS ring has three slots of 24 KiB, so two workgroups are
-// resident per CU and one's memory phases run under the other's MFMAs.
+// overlap with MFMAs.  Here a wave owns a 128 x 64 block (8 x 4 blocks of 16 x 16,
+// v_mfma_f32_16x16x32_f16/bf16, 128 accumulator registers), a workgroup of four
+// waves a 256 x 128 tile, and the LDS ring has three slots of 24 KiB, so two
+// workgroups are resident per CU and one's memory phases run under the other's
+// MFMAs.  (The 16 x 16 x 32 MFMA covers a whole 32-k stage per instruction and
+// issues faster than 32 x 32 x 16: measured 3% more throughput for this kernel.)
 //
 // Stages are loaded straight into LDS (buffer loads with the LDS destination),
 // two stages ahead; rows are 64 bytes with the conflict-free chunk permutation.
-// The epilogue stores from registers: 8-byte stores of four consecutive rows of
-// a column for the tile itself and 2-byte stores for its mirror image.
+// Lane (g, l) of a fragment read takes chunk g (k = 8 g .. 8 g + 7) of row l of a
+// 16-row block, for A and B alike.  The epilogue stores from registers: 8-byte
+// stores of four consecutive rows of a column for the tile itself and 2-byte
+// stores for its mirror image.
 #pragma once
 #include "ns_gemm.h"
 
@@ -21,32 +25,43 @@ namespace nolsm {
 constexpr int RT_M = 256, RT_N = 128;                 // tile rows x columns
 constexpr int RT_SLOT_U4 = (RT_M + RT_N) * 4;          // one ring slot: A rows, then B rows
 
+template <typename TI> struct Mfma16;
+template <> struct Mfma16<_Float16> {
+  __device__ static __forceinline__ f4x op(uint4 a, uint4 b, f4x c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a),
+                                                  __builtin_bit_cast(h8, b), c, 0, 0, 0);
+  }
+};
+template <> struct Mfma16<__bf16> {
+  __device__ static __forceinline__ f4x op(uint4 a, uint4 b, f4x c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, a),
+                                                   __builtin_bit_cast(b8, b), c, 0, 0, 0);
+  }
+};
+
 template <typename TI, int EPI, bool PARTIAL>
 __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
                                                   const TI *__restrict__ B, TI *__restrict__ Out,
                                                   int ld, int n, int i0, int j0, float c1,
                                                   float c3, uint4 *s0, uint4 *s1, uint4 *s2,
                                                   float *red, unsigned long long *racc) {
-  constexpr int BM = 4, BN = 2;                        // 32 x 32 blocks per wave
-  constexpr int LA = RT_M / 64, LB = RT_N / 64;        // loads per wave per stage (A, B)
+  constexpr int BM = 8, BN = 4;                        // 16 x 16 blocks per wave
+  constexpr int LA = RT_M / 64, LB = RT_N / 64;
   constexpr int LPS = LA + LB;
-  constexpr int BOFF = RT_M * 4;                       // first B row in a slot (uint4)
+  constexpr int BOFF = RT_M * 4;
   const int tid = threadIdx.x, lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int wm = (w >> 1) * 32 * BM, wn = (w & 1) * 32 * BN;
-  const int h = lane >> 5, l32 = lane & 31;
+  const int wm = (w >> 1) * 128, wn = (w & 1) * 64;
+  const int g = lane >> 4, l16 = lane & 15;
   const int nk = ld / KStage<TI>::KS;
 
   int nvr = BM, nvc = BN;
   if (PARTIAL) {
-    nvr = (ld - i0 - wm) / 32;
-    nvc = (ld - j0 - wn) / 32;
+    nvr = (ld - i0 - wm) / 16;
+    nvc = (ld - j0 - wn) / 16;
     nvr = nvr < 0 ? 0 : (nvr > BM ? BM : nvr);
     nvc = nvc < 0 ? 0 : (nvc > BN ? BN : nvc);
   }
-
-  // rows past npad (ragged edge tiles) read as zero; stages past the last one are
-  // issued against zero-size resources so every wave issues the same loads
   const int nrec = ld * ld * (int)sizeof(TI);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(A), (short)0, nrec, BUFFER_RSRC_WORD3);
@@ -56,8 +71,6 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
       const_cast<TI *>(A), (short)0, 0, BUFFER_RSRC_WORD3);
   const __amdgpu_buffer_rsrc_t rB0 = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(B), (short)0, 0, BUFFER_RSRC_WORD3);
-
-  // load q of a wave fills rows 16 (4 q + w) .. + 15 of its panel (see ns_gemm_body)
   unsigned voA[LA], voB[LB];
 #pragma unroll
   for (int q = 0; q < LA; ++q) {
@@ -71,18 +84,18 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
     const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
     voB[q] = (unsigned)((j0 + row) * ld) * (unsigned)sizeof(TI) + 16u * ch;
   }
-  const int z = chunk_swz(l32);
-  const int fa0 = (wm + l32) * 4 + ((2 * h) ^ z), fa1 = (wm + l32) * 4 + ((2 * h + 1) ^ z);
-  const int fb0 = BOFF + (wn + l32) * 4 + ((2 * h) ^ z),
-            fb1 = BOFF + (wn + l32) * 4 + ((2 * h + 1) ^ z);
+  // lane (g, l16) reads chunk g of row l16 of each 16-row block (rows 16 b + l16 have
+  // the same permutation for every b since 16 b does not change (r ^ (r >> 2)) & 3)
+  const int z = chunk_swz(l16);
+  const int fa = (wm + l16) * 4 + (g ^ z), fb = BOFF + (wn + l16) * 4 + (g ^ z);
 
-  f16x acc[BM][BN];
+  f4x acc[BM][BN];
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
     for (int bn = 0; bn < BN; ++bn)
 #pragma unroll
-      for (int q = 0; q < 16; ++q) acc[bm][bn][q] = 0.0f;
+      for (int q = 0; q < 4; ++q) acc[bm][bn][q] = 0.0f;
 
   auto issue = [&](uint4 *slot, int kt) {
     const bool live = kt < nk;
@@ -97,44 +110,32 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
       __builtin_amdgcn_raw_ptr_buffer_load_lds(rb, NS_LDS_PTR(slot + BOFF + (4 * q + w) * 64),
                                                16, voB[q], so, 0, 0);
   };
-  // Step kt: stage kt has landed once only stage kt + 1 is still in flight; after
-  // the barrier every wave is done with the slot of stage kt - 1, which takes
-  // stage kt + 2.  Fragments are read and consumed within the step; the other
-  // workgroup on the CU covers the LDS latency.
-  constexpr int NDS = 2 * (BM + BN), NMF = BM * BN * Mfma<TI>::STEPS;
+  constexpr int NDS = BM + BN, NMF = BM * BN;
   auto step = [&](const uint4 *cur, uint4 *refill, int kt) {
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(LPS));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
-    uint4 af[BM][2], bf[BN][2];
+    uint4 af[BM], bf[BN];
 #pragma unroll
-    for (int b = 0; b < BM; ++b) {
-      af[b][0] = cur[fa0 + 128 * b];
-      af[b][1] = cur[fa1 + 128 * b];
-    }
+    for (int b = 0; b < BM; ++b) af[b] = cur[fa + 64 * b];
 #pragma unroll
-    for (int b = 0; b < BN; ++b) {
-      bf[b][0] = cur[fb0 + 128 * b];
-      bf[b][1] = cur[fb1 + 128 * b];
-    }
+    for (int b = 0; b < BN; ++b) bf[b] = cur[fb + 64 * b];
     issue(refill, kt + 2);
 #pragma unroll
-    for (int s = 0; s < Mfma<TI>::STEPS; ++s)
+    for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
-      for (int bm = 0; bm < BM; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < BN; ++bn)
-          if (!PARTIAL || (bm < nvr && bn < nvc))
-            acc[bm][bn] = Mfma<TI>::op(af[bm], bf[bn], s, acc[bm][bn]);
+      for (int bn = 0; bn < BN; ++bn)
+        if (!PARTIAL || (bm < nvr && bn < nvc))
+          acc[bm][bn] = Mfma16<TI>::op(af[bm], bf[bn], acc[bm][bn]);
     if (!PARTIAL) {
       __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);                 // LDS reads
 #pragma unroll
       for (int j = 0; j < LPS; ++j) {
-        __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);                // MFMA
+        __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);                // MFMA
         __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);                // memory load
       }
-      __builtin_amdgcn_sched_group_barrier(0x008, NMF - 2 * LPS, 0);
+      __builtin_amdgcn_sched_group_barrier(0x008, NMF - 4 * LPS, 0);
     }
     __builtin_amdgcn_sched_barrier(0);
   };
@@ -149,66 +150,57 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
   }
   if (nk - kt > 0) step(s0, s2, kt);
   if (nk - kt > 1) step(s1, s0, kt + 1);
-  // the trailing (empty) loads target LDS: drain them before the workgroup ends
   __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(0));
 
-  // Epilogue from registers.  Element (r, c) of block (bm, bn), register q:
-  //   r = wm + 32 bm + 8 (q >> 2) + 4 h + (q & 3),  c = wn + 32 bn + l32.
-  // Only r <= c (global) is kept; (r, c) goes to Out[c ld + r] and, for r < c, the
-  // mirror (c, r) to Out[r ld + c].  SQUARE turns X^2 into Z = c1 I + c3 X^2 and
-  // accumulates the residual ||X^2 - I||_F^2 from X^2.
-  const bool cross = (i0 < j0 + RT_N) && (j0 < i0 + RT_M);    // tile meets the diagonal
+  // Epilogue: element (r, c) of block (bm, bn), register q:
+  //   r = wm + 16 bm + 4 g + q,  c = wn + 16 bn + l16.
+  const bool cross = (i0 < j0 + RT_N) && (j0 < i0 + RT_M);
   int ldv = ld;
   asm volatile("" : "+v"(ldv));
-  float rs = 0.0f;     // crossing tiles: weighted sum; other tiles: plain sum (weight 2 later)
+  float rs = 0.0f;
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
     for (int bn = 0; bn < BN; ++bn) {
       if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
-      const int c = wn + 32 * bn + l32, gc = j0 + c;
+      const int c = wn + 16 * bn + l16, gc = j0 + c;
+      const int r0 = wm + 16 * bm + 4 * g;
       TI *col = Out + (int64_t)gc * ldv + i0;
-      TI *mir = Out + (int64_t)(i0 + wm + 32 * bm + 4 * h) * ldv + gc;
+      TI *mir = Out + (int64_t)(i0 + r0) * ldv + gc;
+      if (!cross) {
+        typedef TI v4 __attribute__((ext_vector_type(4)));
+        v4 ov;
 #pragma unroll
-      for (int g = 0; g < 4; ++g) {
-        const int r0 = wm + 32 * bm + 8 * g + 4 * h;
-        if (!cross) {                                     // every element has r < c
-          typedef TI v4 __attribute__((ext_vector_type(4)));
-          v4 ov;
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            float v = acc[bm][bn][4 * g + e];
-            if (EPI == EPI_SQUARE) {
-              rs += v * v;
-              v = c3 * v;
-            }
-            ov[e] = from_f32<TI>(v);
-            mir[(int64_t)(8 * g + e) * ldv] = ov[e];
+        for (int e = 0; e < 4; ++e) {
+          float v = acc[bm][bn][e];
+          if (EPI == EPI_SQUARE) {
+            rs += v * v;
+            v = c3 * v;
           }
-          *reinterpret_cast<v4 *>(col + r0) = ov;
-        } else {
+          ov[e] = from_f32<TI>(v);
+          mir[(int64_t)e * ldv] = ov[e];
+        }
+        *reinterpret_cast<v4 *>(col + r0) = ov;
+      } else {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int gr = i0 + r0 + e;
-            float v = acc[bm][bn][4 * g + e];
-            if (EPI == EPI_SQUARE) {
-              const bool diag = gr == gc && gc < n;
-              if (gr <= gc && gc < n) {
-                const float df = v - (diag ? 1.0f : 0.0f);
-                rs += (diag ? 1.0f : 2.0f) * df * df;
-              }
-              v = c3 * v + (diag ? c1 : 0.0f);
+        for (int e = 0; e < 4; ++e) {
+          const int gr = i0 + r0 + e;
+          float v = acc[bm][bn][e];
+          if (EPI == EPI_SQUARE) {
+            const bool diag = gr == gc && gc < n;
+            if (gr <= gc && gc < n) {
+              const float df = v - (diag ? 1.0f : 0.0f);
+              rs += (diag ? 1.0f : 2.0f) * df * df;
             }
-            const TI o = from_f32<TI>(v);
-            if (gr <= gc) col[r0 + e] = o;
-            if (gr < gc) mir[(int64_t)(8 * g + e) * ldv] = o;
+            v = c3 * v + (diag ? c1 : 0.0f);
           }
+          const TI o = from_f32<TI>(v);
+          if (gr <= gc) col[r0 + e] = o;
+          if (gr < gc) mir[(int64_t)e * ldv] = o;
         }
       }
     }
   if (EPI == EPI_SQUARE) {
-    // tiles off the diagonal count each element twice (it stands for (r, c) and
-    // (c, r)); padding rows and columns are zero and contribute nothing
     const float tot = block_sum256(cross ? rs : 2.0f * rs, red);
     if (tid == 0) atomicAdd(racc, resid_fixed(tot));
   }

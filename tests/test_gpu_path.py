@@ -237,18 +237,24 @@ def test_nonconvergence_is_reported(gpu_ok):
     assert r.check() == L.ENOCONV
 
 
-def test_tile_shapes_agree_bitwise(gpu_ok):
-    """256 x 128 and 128 x 128 tiles accumulate every element in the same order, so
-    the whole path gives bit-identical results under either tile policy."""
-    inst = get_config("t_23")
+def test_tile_shapes_agree(gpu_ok):
+    """The 256 x 128 tiles (16 x 16 x 32 MFMAs) and the 128 x 128 tiles (32 x 32 x 16
+    MFMAs) sum each element's products in different orders, so the FP16 iterates
+    differ by rounding only: under either tile policy the whole path matches the
+    oracle, and the two results agree with each other to the same tolerance."""
+    inst, D_ref, e_ref, ne_ref, _ = oracle("t_23")
     print_case("tile policies t_23")
     out = []
     for big in (0, 1 << 20):
         r = Runner(inst, big_tile_min_npad=big)
         r.run(sched=default_mixed_schedule())
         assert r.check() == L.OK, L.nolsm_last_error()
-        out.append((r.D.clone(), r.energy_host()))
-    assert torch.equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+        dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+        print_case("policy", big, "dD", dmax, "dE/atom", de)
+        assert dmax < D_TOL and de < E_TOL
+        out.append((r.D.clone(), e))
+    assert float((out[0][0] - out[1][0]).abs().max()) < D_TOL
+    assert abs(out[0][1] - out[1][1]) / inst.natoms < E_TOL
 
 
 @pytest.mark.parametrize("nmol,r_cut,seed", [(27, 2.0, 3), (64, 3.6, 5)])
