@@ -131,14 +131,22 @@ def density_literal(Hk: np.ndarray, Sk: np.ndarray, mu: float) -> np.ndarray:
 
 
 def newton_schulz_sign(A: np.ndarray, scale: float | None = None, tol: float = 1e-12,
-                       maxit: int = 100):
+                       maxit: int = 100, order: int = 2):
     """Eq. 6-7: X0 = A / b, X_{k+1} = 1/2 X_k (3 I - X_k^2), sign(A) = lim X_k.
+
+    order = 3 takes the next member of the same family of matrix-polynomial sign
+    iterations (the higher-order schemes Sec. II mentions): the odd polynomial of
+    degree 5 with p(1) = 1 and p'(1) = p''(1) = 0,
+        X_{k+1} = 1/8 X_k (15 I - 10 X_k^2 + 3 X_k^4),
+    which converges cubically from the same basin.
 
     b defaults to the infinity norm (a Gershgorin bound on the spectral radius,
     valid for the real spectra of S^-1 H - mu I), which keeps every eigenvalue of
-    X0 inside the convergence basin (0, sqrt(3)) in modulus.  Stops when
+    X0 inside the convergence basin in modulus.  Stops when
     ||X^2 - I||_F / sqrt(n) <= tol.  Returns (X, iterations, residual history).
     """
+    if order not in (2, 3):
+        raise ValueError("order must be 2 or 3")
     n = A.shape[0]
     b = np.abs(A).sum(axis=1).max() if scale is None else scale
     X = A / b
@@ -150,7 +158,10 @@ def newton_schulz_sign(A: np.ndarray, scale: float | None = None, tol: float = 1
         hist.append(r)
         if r <= tol or it == maxit:
             return X, it, hist
-        X = 0.5 * X @ (3.0 * eye - X2)
+        if order == 2:
+            X = 0.5 * X @ (3.0 * eye - X2)
+        else:
+            X = 0.125 * X @ (15.0 * eye - 10.0 * X2 + 3.0 * X2 @ X2)
     return X, maxit, hist
 
 

@@ -122,18 +122,18 @@ def check_tiny_bruteforce(seed):
     assert np.allclose(D_eig, D_ns, atol=1e-8, rtol=0)
 
 
-def check_sign_invariants(seed):
+def check_sign_invariants(seed, order=2):
     rng = np.random.default_rng(seed)
     n = 24
     A = rng.standard_normal((n, n))
     A = 0.5 * (A + A.T)
-    X, it, hist = O.newton_schulz_sign(A)
+    X, it, hist = O.newton_schulz_sign(A, order=order)
     eye = np.eye(n)
     assert np.abs(X @ X - eye).max() < 1e-10                         # sign(A)^2 = I
     assert np.abs(A @ X - X @ A).max() < 1e-9                        # commutes with A
     lam = np.linalg.eigvalsh(A)
     assert abs(np.trace(X) - (np.sum(lam > 0) - np.sum(lam < 0))) < 1e-9
-    X3, _, _ = O.newton_schulz_sign(3.7 * A)
+    X3, _, _ = O.newton_schulz_sign(3.7 * A, order=order)
     assert np.abs(X3 - X).max() < 1e-9                               # sign(cA) = sign(A)
     assert hist[-1] <= 1e-12 and it < 100
 
@@ -350,7 +350,7 @@ def test_planted_wrong_own_columns(monkeypatch):
 def test_planted_ns_missing_half(monkeypatch):
     orig = O.newton_schulz_sign
 
-    def bad(A, scale=None, tol=1e-12, maxit=100):
+    def bad(A, scale=None, tol=1e-12, maxit=100, order=2):
         n = A.shape[0]
         b = np.abs(A).sum(axis=1).max() if scale is None else scale
         X = A / b
@@ -377,3 +377,53 @@ def test_planted_trace_wrong_matrix(monkeypatch):
         return math.fsum(eh), math.fsum(es)
     monkeypatch.setattr(O, "column_traces", bad)
     assert _fails(check_whole_system) and _fails(check_chain_truncation)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_third_order_sign_invariants(seed):
+    """The order-3 polynomial iteration reaches the same sign (X^2 = I, commutes with
+    A, integer trace, scale invariance)."""
+    check_sign_invariants(seed, order=3)
+
+
+def test_third_order_polynomial_and_rate():
+    """The order-3 step on scalars is p(x) = x (15 - 10 x^2 + 3 x^4) / 8: p(1) = 1,
+    p'(1) = p''(1) = 0 (so 1 - p(1 - e) = O(e^3)), p(-x) = -p(x); on a matrix it
+    needs fewer steps than Newton-Schulz and agrees with the eigen-decomposition."""
+    x = np.array([0.3, 0.9, 1.0, -0.7])
+    A = np.diag(x)
+    X, _, _ = O.newton_schulz_sign(A, scale=1.0, maxit=1, tol=0.0, order=3)
+    p = x * (15 - 10 * x ** 2 + 3 * x ** 4) / 8
+    assert np.allclose(np.diag(X), p, rtol=0, atol=1e-15)
+    for e in (1e-2, 1e-3):
+        y = 1 - e
+        assert abs(1 - y * (15 - 10 * y ** 2 + 3 * y ** 4) / 8) < 20 * e ** 3
+    rng = np.random.default_rng(7)
+    n = 40
+    B = rng.standard_normal((n, n))
+    A = 0.5 * (B + B.T)
+    lam, V = np.linalg.eigh(A)
+    ref = V @ np.diag(np.sign(lam)) @ V.T
+    X2, it2, _ = O.newton_schulz_sign(A, tol=1e-12, maxit=300)
+    X3, it3, _ = O.newton_schulz_sign(A, tol=1e-12, maxit=300, order=3)
+    assert np.abs(X3 - ref).max() < 1e-8 and np.abs(X2 - ref).max() < 1e-8
+    assert it3 < it2
+
+
+def test_planted_third_order_coefficient(monkeypatch):
+    orig = O.newton_schulz_sign
+
+    def bad(A, scale=None, tol=1e-12, maxit=100, order=2):
+        n = A.shape[0]
+        b = np.abs(A).sum(axis=1).max() if scale is None else scale
+        X = A / b
+        for it in range(maxit):
+            X2 = X @ X
+            X = 0.125 * X @ (15.0 * np.eye(n) - 10.0 * X2 + 2.0 * X2 @ X2)   # 3 -> 2
+            if not np.all(np.isfinite(X)):
+                break
+        r = np.linalg.norm(X @ X - np.eye(n)) / math.sqrt(n)
+        return X, maxit, [r]
+    monkeypatch.setattr(O, "newton_schulz_sign", bad)
+    assert _fails(check_sign_invariants, 0, 3)
+    monkeypatch.setattr(O, "newton_schulz_sign", orig)
