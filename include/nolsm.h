@@ -85,11 +85,17 @@ typedef enum {
  *
  * Phases run in order.  A phase with tol > 0 stops a submatrix once
  * ||X^2 - I||_F <= tol (then runs `extra` more iterations); with
- * tol == 0 it runs exactly `iters` iterations.  Every phase uses the step
+ * tol == 0 it runs exactly `iters` iterations.  A phase of order 2 (or 0) uses the
+ * step
  *   X <- c1 X + c3 X X^2,  (c1, c3) = (3/2 a, -1/2 a^3)
  * with a = 1 (Newton-Schulz, Eq. 6) unless `lower` gives l_k, a lower bound on
  * min |eig(X_0)|, in which case a = sqrt(3 / (1 + l + l^2)) and l is advanced by
  * the same map each iteration (spectrum-interval scaling of Newton-Schulz).
+ * A phase of order 3 uses the next member of the same polynomial family (Sec. II),
+ *   X <- 1/8 X (15 I - 10 X^2 + 3 X^4),
+ * which converges cubically at three products per step (two for order 2); it is
+ * unscaled, so a schedule with an order-3 phase takes neither `lower` nor
+ * `lower_log10` (NOLSM_EINVAL).
  *
  * After the phases, submatrices whose residual exceeds `fallback_tol` continue in
  * FP32 (at most `fallback_iters` iterations, a = 1).  Finally `panel_steps`
@@ -100,6 +106,7 @@ typedef struct {
   int32_t iters;     /* iteration count (tol == 0) or cap (tol > 0) */
   float tol;         /* convergence threshold on ||X^2 - I||_F, 0 = fixed count */
   int32_t extra;     /* iterations after reaching tol */
+  int32_t order;     /* 0 or 2: Newton-Schulz; 3: the third-order polynomial step */
 } nolsm_phase;
 
 typedef struct {

@@ -36,7 +36,7 @@ class Pattern(ctypes.Structure):
 
 class Phase(ctypes.Structure):
     _fields_ = [("prec", ctypes.c_int32), ("iters", ctypes.c_int32), ("tol", ctypes.c_float),
-                ("extra", ctypes.c_int32)]
+                ("extra", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class Schedule(ctypes.Structure):
@@ -185,15 +185,19 @@ class DevicePattern:
 
 def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=None,
              lower=None, lower_log10=None, lower_factor=1.0):
-    """nolsm_schedule from [(prec, iters, tol, extra), ...].
+    """nolsm_schedule from [(prec, iters, tol, extra[, order]), ...].
 
-    scale, lower: device FP64 tensors [K]; lower_log10: device FP32 tensor [K].
+    order 2 (the default) is the Newton-Schulz step, order 3 the third-order
+    polynomial step.  scale, lower: device FP64 tensors [K]; lower_log10: device
+    FP32 tensor [K].
     """
     s = Schedule()
     s.nphase = len(phases)
-    for i, (prec, iters, tol, extra) in enumerate(phases):
+    for i, ph in enumerate(phases):
+        prec, iters, tol, extra = ph[:4]
+        order = ph[4] if len(ph) > 4 else 2
         p = PREC_NAMES[prec] if isinstance(prec, str) else prec
-        s.phase[i] = Phase(p, iters, tol, extra)
+        s.phase[i] = Phase(p, iters, tol, extra, order)
     s.fallback_tol = fallback_tol
     s.fallback_iters = fallback_iters
     s.panel_steps = panel_steps

@@ -328,17 +328,25 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, co
 nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *sched,
                                 nolsm_stats *stats, hipStream_t s) {
   if (!p) return fail(NOLSM_EINVAL, "nolsm_sign_batched: null plan");
-  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_sign_batched: plan not bound");
   if (!std::isfinite(mu)) return fail(NOLSM_EINVAL, "nolsm_sign_batched: mu not finite");
+  // the schedule is checked before the plan's buffers (nothing is enqueued either way)
   nolsm_schedule sch;
   if (sched) {
     sch = *sched;
     if (sch.nphase < 1 || sch.nphase > 4) return fail(NOLSM_EINVAL, "nolsm_sign_batched: nphase");
+    const bool scaled = sch.lower != nullptr || sch.lower_log10 != nullptr;
     for (int q = 0; q < sch.nphase; ++q) {
-      const nolsm_phase &ph = sch.phase[q];
+      nolsm_phase &ph = sch.phase[q];
       if (ph.prec < 0 || ph.prec > 2 || ph.iters < 0 || ph.iters > 1000 || ph.extra < 0 ||
           !(ph.tol >= 0.0f))
         return fail(NOLSM_EINVAL, "nolsm_sign_batched: bad phase %d", q);
+      if (ph.order == 0) ph.order = 2;
+      if (ph.order != 2 && ph.order != 3)
+        return fail(NOLSM_EINVAL, "nolsm_sign_batched: phase %d order must be 0, 2 or 3", q);
+      if (ph.order == 3 && scaled)
+        return fail(NOLSM_EINVAL,
+                    "nolsm_sign_batched: phase %d: the order-3 step is unscaled (no lower bounds)",
+                    q);
     }
     if (sch.panel_steps < 0 || sch.panel_steps > 2)
       return fail(NOLSM_EINVAL, "nolsm_sign_batched: panel_steps must be 0..2");
@@ -351,9 +359,11 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
     sch.phase[0].iters = 100;
     sch.phase[0].tol = 1.0e-3f;
     sch.phase[0].extra = 2;
+    sch.phase[0].order = 2;
     sch.panel_steps = 0;
     sch.fallback_iters = 0;
   }
+  if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_sign_batched: plan not bound");
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   int ev;

@@ -13,6 +13,17 @@
 //   ns_gemm<UPDATE>   X' = X Z               (Newton-Schulz: c1 = 3/2, c3 = -1/2)
 //   ns_advance        X <- X', advance the spectral lower bound, next (c1, c3)
 //
+// The third-order step X' = 1/8 X (15 I - 10 X^2 + 3 X^4) uses the same two
+// epilogues: since 15 - 10 y + 3 y^2 = 3 (y - 5/3)^2 + 20/3,
+//   ns_gemm<SQUARE>   W = X X - 5/3 I        (residual of X X)
+//   ns_check          residual, stop rule; the state now points at W
+//   ns_gemm<SQUARE>   Z = 3/8 W W + 5/6 I
+//   ns_shift          the state points at Z
+//   ns_gemm<UPDATE>   X' = Z X  (= X Z: both are polynomials in the same M)
+//   ns_advance
+// The three buffers rotate so that the update writes W's buffer and the advance
+// moves the state by two buffers, as for the Newton-Schulz step.
+//
 // Operands: both factors are read as column panels (A(m, k) = X(k, m) by
 // symmetry), so every lane's MFMA fragment is a run of consecutive k.  The k
 // order inside an LDS stage is permuted identically for A and B, which leaves the
@@ -28,9 +39,13 @@ namespace nolsm {
 // ------------------------------------------------------------------ per-submatrix control
 
 struct PhaseArgs {
-  int prec, t, iters, extra, use_lower;
+  int prec, t, iters, extra, use_lower, order;
   float tol;
 };
+
+// Coefficients (c1, c3) of the third-order step's two SQUARE epilogues.
+constexpr float O3_W_C1 = -5.0f / 3.0f, O3_W_C3 = 1.0f;        // W = X^2 - 5/3 I
+constexpr float O3_Z_C1 = 5.0f / 6.0f, O3_Z_C3 = 3.0f / 8.0f;  // Z = 3/8 W^2 + 5/6 I
 
 // Spectrum-interval scaling of Newton-Schulz (Eq. 6 with a scaled argument): with
 // every |eigenvalue| of X in [l, u], the step x <- p(a x), p(y) = y (3 - y^2) / 2,
@@ -52,7 +67,12 @@ __device__ __forceinline__ double ns_alpha(double l) {
 
 __device__ __forceinline__ double ns_p(double y) { return 0.5 * y * (3.0 - y * y); }
 
-__device__ __forceinline__ void set_coeffs(SubState &s, int use_lower) {
+__device__ __forceinline__ void set_coeffs(SubState &s, int use_lower, int order) {
+  if (order == 3) {
+    s.c1 = O3_W_C1;
+    s.c3 = O3_W_C3;
+    return;
+  }
   const double a = (use_lower && s.lower < 1.0) ? ns_alpha(s.lower) : 1.0;
   s.c1 = (float)(1.5 * a);
   s.c3 = (float)(-0.5 * a * a * a);
@@ -85,11 +105,28 @@ __global__ void ns_check_kernel(const SubDesc *__restrict__ desc, SubState *__re
   } else {
     go = p.t < p.iters;
   }
-  if (!go) s.active = 0;
+  if (!go) {
+    s.active = 0;
+  } else if (p.order == 3) {      // the next product squares W
+    s.cur = (s.cur + 1) % 3;
+    s.c1 = O3_Z_C1;
+    s.c3 = O3_Z_C3;
+  }
+}
+
+// Third-order step: the state moves from W to Z; the residual that the second
+// SQUARE epilogue added (of W W, not X X) is dropped.
+__global__ void ns_shift_kernel(SubState *__restrict__ st, int K, int prec) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (!s.active || s.prec != prec) return;
+  s.cur = (s.cur + 1) % 3;
+  s.racc = 0ull;
 }
 
 __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, int use_lower,
-                                  int fallback) {
+                                  int fallback, int order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -103,13 +140,13 @@ __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, in
     const double ln = pl < pu ? pl : pu;
     s.lower = ln > 1.0 ? 1.0 : ln;
   }
-  set_coeffs(s, use_lower);       // for the next iteration's Z = c1 I + c3 X^2
+  set_coeffs(s, use_lower, order);    // for the next iteration's first SQUARE
 }
 
 // Start a phase: every healthy submatrix iterates; convert the current iterate
 // if the phase changes precision (handled by convert_kernel on the host side).
 __global__ void phase_start_kernel(SubState *__restrict__ st, int K, int use_lower,
-                                   int only_fb) {
+                                   int only_fb, int order) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -119,7 +156,7 @@ __global__ void phase_start_kernel(SubState *__restrict__ st, int K, int use_low
   s.extra_left = -1;
   s.converged = 0;
   s.racc = 0ull;
-  set_coeffs(s, use_lower);
+  set_coeffs(s, use_lower, order);
 }
 
 __global__ void phase_end_kernel(SubState *__restrict__ st, int K) {
@@ -402,13 +439,18 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
   p.extra = ph.extra;
   p.tol = ph.tol;
   p.use_lower = use_lower;
+  p.order = ph.order == 3 ? 3 : 2;
   const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
   for (int t = 0; t <= last; ++t) {
     p.t = t;
     timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
     ns_check_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, p);
+    if (p.order == 3) {
+      timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
+      ns_shift_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
+    }
     timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
-    ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback);
+    ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback, p.order);
   }
   phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
 }
@@ -434,7 +476,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
       convert_commit_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
     }
     const int scaled = (sch.lower != nullptr || sch.lower_log10 != nullptr) ? 1 : 0;
-    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0);
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0, ph.order == 3 ? 3 : 2);
     launch_phase(desc, st, K, ts, ws, ph, scaled, 0, log, flop, s);
   }
   if (sch.fallback_iters > 0) {
@@ -448,7 +490,8 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     fb.iters = sch.fallback_iters;
     fb.tol = 1.0e-3f;
     fb.extra = 2;
-    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, 0, 1);
+    fb.order = 2;
+    phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, 0, 1, 2);
     launch_phase(desc, st, K, ts, ws, fb, 0, 1, nullptr, 0.0, s);
     fb_finish_kernel<<<nblk(K), 256, 0, s>>>(st, K);
   }

@@ -13,14 +13,15 @@ from . import _lib as L
 
 
 def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallback_iters=60,
-                           tol=0.1, cap=30, scale=None, lower=None):
+                           tol=0.1, cap=30, scale=None, lower=None, order=2):
     """Low-precision bulk, then one FP32 Newton-Schulz step on the own-column panel.
 
     By default the bulk runs until ||X^2 - I||_F <= tol (every eigenvalue within
     |1 - x^2| <= 0.1) plus one more iteration; with fixed_iters it runs exactly
-    that many.  Submatrices that miss the tolerance restart in plain FP32.
+    that many.  Submatrices that miss the tolerance restart in plain FP32.  order 3
+    takes the third-order polynomial step in the bulk.
     """
-    phase = (prec, fixed_iters, 0.0, 0) if fixed_iters else (prec, cap, tol, 1)
+    phase = (prec, fixed_iters, 0.0, 0, order) if fixed_iters else (prec, cap, tol, 1, order)
     return L.schedule([phase], fallback_tol=tol, fallback_iters=fallback_iters,
                       panel_steps=panel_steps, scale=scale, lower=lower)
 
@@ -39,9 +40,10 @@ def learned_schedule(panel_steps=1, prec="fp16", fallback_iters=60, tol=0.1):
                                   fallback_iters=fallback_iters, tol=tol, cap=LEARNED_CAP)
 
 
-def plain_fp32_schedule(tol=1e-3, extra=2, cap=100):
-    """Plain FP32 Newton-Schulz to convergence (no panel step, no fallback)."""
-    return L.schedule([("fp32", cap, tol, extra)], fallback_iters=0, panel_steps=0)
+def plain_fp32_schedule(tol=1e-3, extra=2, cap=100, order=2):
+    """Plain FP32 Newton-Schulz (order 2) or third-order (order 3) iteration to
+    convergence (no panel step, no fallback)."""
+    return L.schedule([("fp32", cap, tol, extra, order)], fallback_iters=0, panel_steps=0)
 
 
 def tuned_tile_policy():

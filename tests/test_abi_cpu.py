@@ -30,7 +30,8 @@ def test_header_symbols_exported():
 
 def test_struct_sizes_match_header():
     assert ctypes.sizeof(L.SubInfo) == 64
-    assert ctypes.sizeof(L.Phase) == 16
+    assert ctypes.sizeof(L.Phase) == 20
+    assert L.Schedule.phase.offset == 4 and L.Schedule.scale.offset == 96
     assert L.STATS_DTYPE.itemsize == 48
     assert ctypes.sizeof(L.Pattern) == 8 * 8
 
@@ -132,6 +133,37 @@ def test_sign_rejects_unbound_plan():
     try:
         code = L.lib().nolsm_sign_batched(plan, 0.0, None, None, None)
         assert code == L.EINVAL
+        assert "not bound" in L.nolsm_last_error()
+    finally:
+        L.nolsm_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("case", ["order", "order3_scaled", "prec", "nphase"])
+def test_sign_rejects_bad_schedule(case):
+    """Schedules are checked before anything is enqueued (the plan is not bound and
+    the lower-bound address is never dereferenced)."""
+    inst = get_config("c1")
+    plan = L.nolsm_plan_create(L.HostPattern(inst), np.array([0], dtype=np.int32))
+    try:
+        sch = L.schedule([("fp16", 10, 0.1, 1, 2)])
+        if case == "order":
+            sch.phase[0].order = 4
+        elif case == "order3_scaled":
+            sch.phase[0].order = 3
+            sch.lower = 0x1000
+        elif case == "prec":
+            sch.phase[0].prec = 7
+        else:
+            sch.nphase = 5
+        code = L.lib().nolsm_sign_batched(plan, 0.0, ctypes.byref(sch), None, None)
+        assert code == L.EINVAL
+        msg = L.nolsm_last_error()
+        assert "not bound" not in msg, msg
+        if case == "order3_scaled":
+            assert "unscaled" in msg
+        # a valid order-3 schedule passes the checks and stops at the unbound plan
+        ok = L.schedule([("fp16", 10, 0.1, 1, 3)])
+        assert L.lib().nolsm_sign_batched(plan, 0.0, ctypes.byref(ok), None, None) == L.EINVAL
         assert "not bound" in L.nolsm_last_error()
     finally:
         L.nolsm_plan_destroy(plan)

@@ -163,6 +163,37 @@ def test_parity_mixed_fp16(gpu_ok, name):
     assert dmax < D_TOL and de < E_TOL
 
 
+@pytest.mark.parametrize("name", ["c1", "t_tiles"])
+def test_parity_third_order(gpu_ok, name):
+    """The third-order polynomial step, in plain FP32 and as the FP16 bulk, meets the
+    same bounds as Newton-Schulz and converges in fewer steps (cubic rate)."""
+    inst, D_ref, e_ref, ne_ref, _ = oracle(name)
+    r = Runner(inst)
+    print_case("plain fp32 order 2", name)
+    r.run(sched=plain_fp32_schedule())
+    assert r.check() == L.OK, L.nolsm_last_error()
+    it2 = r.stats_host()["iters_lo"].copy()
+    print_case("plain fp32 order 3", name)
+    r.run(sched=plain_fp32_schedule(order=3))
+    assert r.check() == L.OK, L.nolsm_last_error()
+    dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+    st = r.stats_host()
+    it3 = st["iters_lo"]
+    print_case(name, "order-3 plain dD", dmax, "dE/atom", de, "iters", int(it3.max()), "vs",
+               int(it2.max()))
+    assert dmax < 1e-4 and de < 1e-6
+    assert abs(ne - ne_ref) < 1e-3
+    assert np.all(st["status"] == 0) and np.all(it3 < it2)
+    print_case("mixed fp16 order 3", name)
+    r.run(sched=default_mixed_schedule(order=3))
+    assert r.check() == L.OK, L.nolsm_last_error()
+    dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+    st = r.stats_host()
+    print_case(name, "order-3 mixed dD", dmax, "dE/atom", de, "fallbacks",
+               int(st["fell_back"].sum()))
+    assert dmax < D_TOL and de < E_TOL
+
+
 def test_per_column_traces_match_oracle(gpu_ok):
     inst, D_ref, e_ref, ne_ref, _ = oracle("c1")
     r = Runner(inst)
