@@ -27,9 +27,9 @@ __device__ __forceinline__ void acc_merge(ColAcc &a, const ColAcc &b) {
 }
 
 // Pass 1: grid (npad / 64, K); workgroup x covers columns 64 x .. 64 x + 63, wave w
-// columns 64 x + 16 w .. + 15, lanes stride down a column.  The workgroup's partial
-// (waves combined in order) goes to the submatrix's set-up scratch (free once M is
-// formed).
+// columns 64 x + 16 w .. + 15, lanes stride down a column four rows at a time.  The
+// workgroup's partial (waves combined in order) goes to the submatrix's set-up
+// scratch (free once M is formed).
 __global__ __launch_bounds__(256) void features_part_kernel(const SubDesc *__restrict__ desc,
                                                             char *ws, double mu) {
   const SubDesc d = desc[blockIdx.y];
@@ -43,10 +43,20 @@ __global__ __launch_bounds__(256) void features_part_kernel(const SubDesc *__res
   const int cb = blockIdx.x * 64 + w * 16;
   for (int c = cb; c < cb + 16 && c < d.n; ++c) {
     double R = 0.0, f2 = 0.0, diag = 0.0;
-    for (int r = lane; r < d.n; r += 64) {
-      double v = (double)M[(int64_t)c * d.npad + r];
-      if (r == c) { v -= mu; diag = v; } else R += fabs(v);
-      f2 += v * v;
+    // four consecutive rows per lane (16-byte reads; npad is a multiple of 64)
+    const float *col = M + (int64_t)c * d.npad;
+#pragma unroll 2
+    for (int r4 = 4 * lane; r4 < d.n; r4 += 256) {
+      const float4 m4 = *reinterpret_cast<const float4 *>(col + r4);
+      const float mv[4] = {m4.x, m4.y, m4.z, m4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r4 + e;
+        if (r >= d.n) break;
+        double v = (double)mv[e];
+        if (r == c) { v -= mu; diag = v; } else R += fabs(v);
+        f2 += v * v;
+      }
     }
     R = wave_sum(R);
     f2 = wave_sum(f2);

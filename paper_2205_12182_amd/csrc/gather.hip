@@ -1,10 +1,12 @@
 // Submatrix method, step 1 (paper, Sec. II; Eq. 8 for the non-orthogonal pair):
 // gather the dense principal submatrices T_k(H0), T_k(S) of every planned molecule.
 //
-// One workgroup per (submatrix, member block column b).  It locates every block
-// (J_a, J_b) of the submatrix in block column J_b by binary search, then streams
-// the column-major block column into the dense column-major submatrix: each
-// output column is a contiguous run of n doubles, so writes are coalesced, and
+// One workgroup per (submatrix, member block column b).  The member list (ascending
+// molecule index) goes to LDS with a row -> member map; the stored blocks of block
+// column J_b are read once, coalesced, and each is matched to its member by a
+// binary search in LDS.  The workgroup then streams the column-major block column
+// into the dense column-major submatrix, four consecutive rows per thread: each
+// output column is a contiguous run, so writes are coalesced vector stores, and
 // each stored block is read contiguously.  The padding rows/columns (n..npad) are
 // written as well: zero for H, the identity for S.  Of T_k(S) only the lower
 // triangle (with the diagonal) is written: the factorisation reads nothing else,
@@ -31,8 +33,8 @@ __global__ __launch_bounds__(256) void gather_kernel(
   const int b = blockIdx.x;
   if (b > d.nmem) return;                       // b == nmem: padding columns
   __shared__ int64_t s_t[GATHER_MAXMEM];        // value offset of block (J_a, J_b) or -1
-  __shared__ int32_t s_loc[GATHER_MAXMEM + 1];
-  __shared__ int32_t s_dim[GATHER_MAXMEM];
+  __shared__ int32_t s_loc[GATHER_MAXMEM + 1];  // first row of member a; s_loc[nmem] = n
+  __shared__ int32_t s_mol[GATHER_MAXMEM];      // molecule of member a (ascending)
   __shared__ uint16_t s_rowmem[GATHER_MAXN];    // row -> member
   double *Hk = reinterpret_cast<double *>(ws + d.off_h);
   double *Sk = reinterpret_cast<double *>(ws + d.off_s);
@@ -53,52 +55,80 @@ __global__ __launch_bounds__(256) void gather_kernel(
     return;
   }
 
+  const int nmem = d.nmem;
   const int Jb = mem_mol[d.mem_off + b];
   const int locb = mem_loc[d.mem_off + b];
   const int dJ = blk_dim[Jb];
   const int64_t c0 = colptr[Jb], c1 = colptr[Jb + 1];
-  for (int a = threadIdx.x; a < d.nmem; a += blockDim.x) {
+  for (int a = threadIdx.x; a < nmem; a += blockDim.x) {
     const int Ja = mem_mol[d.mem_off + a];
-    int64_t lo = c0, hi = c1;                   // first row >= Ja
-    while (lo < hi) {
-      const int64_t mid = (lo + hi) >> 1;
-      if (rowblk[mid] < Ja) lo = mid + 1; else hi = mid;
-    }
-    s_t[a] = (lo < c1 && rowblk[lo] == Ja) ? valoff[lo] : -1;     // block values or absent
-    s_loc[a] = mem_loc[d.mem_off + a];
-    s_dim[a] = blk_dim[Ja];
+    const int loc = mem_loc[d.mem_off + a], dim = blk_dim[Ja];
+    s_mol[a] = Ja;
+    s_loc[a] = loc;
+    s_t[a] = -1;                                 // absent unless block column J_b stores it
+    for (int r = 0; r < dim; ++r) s_rowmem[loc + r] = (uint16_t)a;
   }
+  if (threadIdx.x == 0) s_loc[nmem] = n;
   __syncthreads();
-  for (int a = 0; a < d.nmem; ++a)
-    for (int r = threadIdx.x; r < s_dim[a]; r += blockDim.x) s_rowmem[s_loc[a] + r] = (uint16_t)a;
+  for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+    const int J = rowblk[e];
+    int lo = 0, hi = nmem;                       // first member >= J
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_mol[mid] < J) lo = mid + 1; else hi = mid;
+    }
+    if (lo < nmem && s_mol[lo] == J) s_t[lo] = valoff[e];     // rows are distinct
+  }
   __syncthreads();
 
   // column by column (32-bit index arithmetic, no per-element division); rows of
-  // one member are contiguous in both the stored block and the output column
+  // one member are contiguous in both the stored block and the output column.
+  // ld is a multiple of 64, so every four-row group lies inside the column.
+  typedef _Float16 h4 __attribute__((ext_vector_type(4)));
   for (int c = 0; c < dJ; ++c) {
     double *hcol = Hk + (int64_t)(locb + c) * ld;
     _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
     double *scol = Sk + (int64_t)(locb + c) * ld;
     const int col = locb + c;
-    for (int i = threadIdx.x; i < ld; i += blockDim.x) {
-      double h = 0.0, sv = 0.0;
-      if (i < n) {
-        const int a = s_rowmem[i];
-        const int64_t v0 = s_t[a];
-        if (v0 >= 0) {
-          const int64_t src = v0 + (i - s_loc[a]) + c * s_dim[a];
-          h = H_val[src];
-          if (i >= col) sv = S_val[src];
+    for (int i0 = 4 * threadIdx.x; i0 < ld; i0 += 4 * blockDim.x) {
+      double h[4], sv[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = i0 + e;
+        h[e] = 0.0;
+        sv[e] = 0.0;
+        if (i < n) {
+          const int a = s_rowmem[i];
+          const int64_t v0 = s_t[a];
+          if (v0 >= 0) {
+            const int64_t src = v0 + (i - s_loc[a]) + c * (s_loc[a + 1] - s_loc[a]);
+            h[e] = H_val[src];
+            if (i >= col) sv[e] = S_val[src];
+          }
         }
       }
       if (SPLIT_H) {
-        const _Float16 hi = (_Float16)h;                 // one rounding from FP64
-        hrow[i] = hi;
-        hrow[ld + i] = (_Float16)((h - (double)hi) * 2048.0);
+        h4 hi, lo;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          hi[e] = (_Float16)h[e];                        // one rounding from FP64
+          lo[e] = (_Float16)((h[e] - (double)hi[e]) * 2048.0);
+        }
+        *reinterpret_cast<h4 *>(hrow + i0) = hi;
+        *reinterpret_cast<h4 *>(hrow + ld + i0) = lo;
       } else {
-        hcol[i] = h;
+        *reinterpret_cast<double2 *>(hcol + i0) = make_double2(h[0], h[1]);
+        *reinterpret_cast<double2 *>(hcol + i0 + 2) = make_double2(h[2], h[3]);
       }
-      if (i >= col) scol[i] = sv;               // the factorisation reads the lower triangle
+      // the factorisation reads the lower triangle only
+      if (i0 >= col) {
+        *reinterpret_cast<double2 *>(scol + i0) = make_double2(sv[0], sv[1]);
+        *reinterpret_cast<double2 *>(scol + i0 + 2) = make_double2(sv[2], sv[3]);
+      } else if (i0 + 3 >= col) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (i0 + e >= col) scol[i0 + e] = sv[e];
+      }
     }
   }
 }
