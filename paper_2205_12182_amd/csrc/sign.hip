@@ -263,11 +263,10 @@ __device__ void cast_col(const float *M, TI *X, int n, int ld, int c, double mu,
 
 // One wave per column, four consecutive rows per lane (16-byte reads of M).
 template <typename TI>
-__device__ __forceinline__ void cast_col4(const float *__restrict__ M, TI *__restrict__ X, int n,
-                                          int ld, int c, double mu, double inv_b) {
+__device__ __forceinline__ void cast_col4(const float *M, TI *X, int n, int ld, int c, double mu,
+                                          double inv_b) {
   typedef TI v4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
-#pragma unroll 4
   for (int q = lane; q < ld / 4; q += 64) {
     const int r = 4 * q;
     const float4 m = *reinterpret_cast<const float4 *>(M + (int64_t)c * ld + r);
