@@ -194,6 +194,31 @@ def test_parity_third_order(gpu_ok, name):
     assert dmax < D_TOL and de < E_TOL
 
 
+@pytest.mark.parametrize("name", ["c1", "t_tiles"])
+def test_parity_bf16_and_phase_change(gpu_ok, name):
+    """The BF16 bulk, alone and as a first phase converted to an FP16 phase.
+
+    BF16 keeps 8 significand bits against FP16's 11, so its unit roundoff is 8 times
+    larger; rounding errors of the iterates stay in the sign (its derivative weighs
+    them by at least 1), so the BF16 bound is 8 times the FP16 accuracy target.  The
+    two-phase schedule runs the conversion of the iterate between precisions."""
+    inst, D_ref, e_ref, ne_ref, _ = oracle(name)
+    r = Runner(inst)
+    for label, sched in (
+            ("bf16 bulk", default_mixed_schedule(prec="bf16")),
+            ("bf16 -> fp16", L.schedule([("bf16", 3, 0.0, 0), ("fp16", 30, 0.1, 1)],
+                                        fallback_tol=0.1, fallback_iters=60, panel_steps=1))):
+        print_case(label, name)
+        r.run(sched=sched)
+        assert r.check() == L.OK, L.nolsm_last_error()
+        dmax, de, e, ne = errors(inst, r, D_ref, e_ref)
+        st = r.stats_host()
+        print_case(name, label, "dD", dmax, "dE/atom", de, "iters", int(st["iters_lo"].max()),
+                   "fallbacks", int(st["fell_back"].sum()))
+        assert np.all(st["status"] == 0)
+        assert dmax < 8 * D_TOL and de < 8 * E_TOL
+
+
 def test_per_column_traces_match_oracle(gpu_ok):
     inst, D_ref, e_ref, ne_ref, _ = oracle("c1")
     r = Runner(inst)
