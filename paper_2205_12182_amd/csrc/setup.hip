@@ -147,8 +147,19 @@ __device__ __forceinline__ void tri_index(int x, int &ti, int &tj) {   // x -> (
   tj = x - t * (t + 1) / 2;
 }
 
-#define SUB_PTRS                                                               \
-  const SubDesc d = desc[blockIdx.y];                                          \
+// Tile kernels over a (tiles, submatrices) grid take their (tile, submatrix) pair
+// through xcd_remap of the flat workgroup id, so that the tiles of one submatrix run
+// on one XCD and share its panels in that XCD's L2.
+__device__ __forceinline__ void remap_tile_sub(int &tile, int &sub) {
+  const int nx = (int)gridDim.x;
+  const int l = xcd_remap((int)blockIdx.x + nx * (int)blockIdx.y, nx * (int)gridDim.y);
+  tile = l % nx;
+  sub = l / nx;
+}
+
+#define SUB_PTRS SUB_PTRS_AT(blockIdx.y)
+#define SUB_PTRS_AT(k)                                                         \
+  const SubDesc d = desc[k];                                                   \
   const int ld = d.npad;                                                       \
   double *Hb = reinterpret_cast<double *>(ws + d.off_h);                       \
   double *Sb = reinterpret_cast<double *>(ws + d.off_s);                       \
@@ -414,8 +425,10 @@ __device__ __forceinline__ void acc128_foreach(d4 acc[2][4], F f) {
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int m0,
                        int rows) {
-  SUB_PTRS
-  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  int tile, sub;
+  remap_tile_sub(tile, sub);
+  SUB_PTRS_AT(sub)
+  const int ti = tile % rows, tj = tile / rows;
   if (ti < tj || k0 >= ld) return;
   const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
   if (r0 >= ld || c0 >= ld) return;
@@ -490,9 +503,11 @@ constexpr int TW = 256;                 // outer block width of the inverse
 
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
-  SUB_PTRS
+  int tile, sub;
+  remap_tile_sub(tile, sub);
+  SUB_PTRS_AT(sub)
   const int J1 = J0 + TW;
-  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  const int ti = tile % rows, tj = tile / rows;
   const int r0 = J1 + ti * 128, c0 = tj * 128;
   if (r0 >= ld) return;
   double *T = reinterpret_cast<double *>(ws + d.off_lo);
@@ -512,9 +527,11 @@ void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
 
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
-  SUB_PTRS
+  int tile, sub;
+  remap_tile_sub(tile, sub);
+  SUB_PTRS_AT(sub)
   const int J1 = J0 + TW;
-  const int ti = (int)blockIdx.x % rows, tj = (int)blockIdx.x / rows;
+  const int ti = tile % rows, tj = tile / rows;
   const int r0 = J1 + ti * 128, c0 = tj * 128;
   if (r0 >= ld) return;
   const double *T = reinterpret_cast<const double *>(ws + d.off_lo);
