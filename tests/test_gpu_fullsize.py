@@ -1,4 +1,5 @@
-"""The benchmark workload at full size (needs an MI355X).
+"""The benchmark workload at full size, and submatrices near the plan's size limit
+(needs an MI355X).
 
 All 4,096 molecules of the c2 water box (n 1,679-1,863) go through the path in the
 configuration bench.py times (batches of 1,024 submatrices sharing one workspace, the
@@ -17,6 +18,7 @@ from oracle import nolsm_oracle as O
 from paper_2205_12182_amd import learn
 from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, learned_schedule
 from workloads import get_config
+from workloads.water import water_box
 
 pytestmark = pytest.mark.gpu
 
@@ -54,3 +56,44 @@ def test_c2_full_size_sampled_parity(gpu_ok):
           f"(iterations {st['iters_lo'].mean():.2f}, restarts {int(st['fell_back'].sum())})",
           flush=True)
     assert dmax <= D_TOL and abs(de) / atoms <= E_TOL
+
+
+def sampled_errors(inst, D, st, picks, index):
+    """Max |D - D_oracle| over the written columns of molecules `picks` and the
+    summed Tr(D_k H) difference per atom; st[index[k]] is molecule k's record."""
+    dmax, de, atoms = 0.0, 0.0, 0
+    for k in picks:
+        ref = O.submatrix_result(inst, k)
+        got = np.zeros_like(ref["D_cols"])
+        for a, I in enumerate(ref["members"]):
+            t = int(inst.colptr[k]) + a
+            dI, m = int(inst.blk_dim[I]), int(inst.blk_dim[k])
+            got[ref["offs"][a]:ref["offs"][a + 1], :] = \
+                D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
+        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
+        de += float(st["tr_dh"][index[k]]) - ref["tr_dh"]
+        atoms += int(inst.atoms[k])
+    return dmax, abs(de) / atoms
+
+
+def test_near_maximum_submatrices(gpu_ok):
+    """The largest and the smallest submatrix of a 2,048-molecule box with a 13 A
+    cutoff (n 6,831-7,452; the plan accepts npad up to 8,192), ragged against the
+    64-element padding and the 256 x 128 tiles, through the mixed schedule."""
+    inst = water_box(2048, (13, 5, 5), 13.0, seed=3, shift=1.5, name="near-max")
+    dims = inst.submatrix_dims()
+    picks = [int(np.argmax(dims)), int(np.argmin(dims))]
+    print(f"[case] near-maximum submatrices: molecules {picks}, n {dims[picks].tolist()}",
+          flush=True)
+    assert dims.max() > 7000 and dims.max() % 64 != 0
+    r = Runner(inst, mols=picks)
+    r.run(sched=default_mixed_schedule(), energy=False)
+    torch.cuda.synchronize()
+    st = r.stats_host()
+    assert (st["status"] == 0).all()
+    dmax, de = sampled_errors(inst, r.D.cpu().numpy(), st, picks,
+                              {k: i for i, k in enumerate(picks)})
+    print(f"[case] near-maximum vs oracle: dD {dmax:.2e} dE/atom {de:.2e} "
+          f"(iterations {st['iters_lo'].tolist()}, restarts {int(st['fell_back'].sum())})",
+          flush=True)
+    assert dmax <= D_TOL and de <= E_TOL
