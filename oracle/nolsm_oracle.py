@@ -28,6 +28,9 @@ with theta(x) = 1 for x > 0, 0 for x < 0 and 1/2 at x = 0 (sign(0) = 0).
 
 Eq. 6-7 (Newton-Schulz) is provided as `newton_schulz_sign`, used by tests and as
 the source of iteration-count labels; the oracle's density never depends on it.
+`order=3` gives the third-order member of the same polynomial family (Sec. II's
+higher-order schemes); both are pinned by the sign identities, the eigen-
+decomposition, the scalar map and (order 3) its cubic rate.
 
 Readings of points the paper leaves open are listed in the design notes: the
 molecule-column grouping, mu = 0, no spin factor (Tr(DS) counts occupied
