@@ -35,10 +35,11 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-def paper_flops(stats):
-    """2 n^3 per product, two products per iteration (Eq. 6)."""
+def paper_flops(stats, products_per_iter=2):
+    """2 n^3 per product, two products per Newton-Schulz iteration (Eq. 6; every
+    schedule timed here is Newton-Schulz; a third-order phase takes three)."""
     n3 = stats["n"].astype(np.float64) ** 3
-    return float((4.0 * n3 * (stats["iters_lo"] + stats["iters_fb"])).sum())
+    return float((2.0 * products_per_iter * n3 * (stats["iters_lo"] + stats["iters_fb"])).sum())
 
 
 def timed_steps(runner, sched, steps, L, torch, predictor=None):
