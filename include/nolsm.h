@@ -232,7 +232,12 @@ nolsm_status nolsm_features(nolsm_plan *plan, double mu, float *feat, hipStream_
 /* Step 2 (Eq. 8 via Eq. 6-7): FP64 Cholesky and transform, scaling, the batched
  * sign iteration under `sched` (NULL = plain FP32 Newton-Schulz to convergence),
  * the FP32 fallback and the own-column panel refinement, and the FP64 density
- * columns T_k(D)[:, own columns].  stats: device [K] (may be NULL). */
+ * columns T_k(D)[:, own columns].  stats: device [K] (may be NULL).
+ * NOLSM_EINVAL, with nothing enqueued: a null plan, a non-finite mu, a bad
+ * schedule (nphase outside 1..4, a phase with an unknown precision, iters outside
+ * 0..1000, negative extra or tol, an order other than 0, 2 or 3, an order-3 phase
+ * with lower bounds, panel_steps outside 0..2, fallback_iters outside 0..1000),
+ * checked in that order, then an unbound plan. */
 nolsm_status nolsm_sign_batched(nolsm_plan *plan, double mu, const nolsm_schedule *sched /*host*/,
                                 nolsm_stats *stats, hipStream_t stream);
 
