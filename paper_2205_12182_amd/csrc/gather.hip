@@ -1,10 +1,10 @@
 // Submatrix method, step 1 (paper, Sec. II; Eq. 8 for the non-orthogonal pair):
 // gather the dense principal submatrices T_k(H0), T_k(S) of every planned molecule.
 //
-// One workgroup per (submatrix, member block column b).  The member list (ascending
-// molecule index) goes to LDS with a row -> member map; the stored blocks of block
-// column J_b are read once, coalesced, and each is matched to its member by a
-// binary search in LDS.  The workgroup then streams the column-major block column
+// One workgroup per (submatrix, group of four member block columns b).  The member
+// list (ascending molecule index) goes to LDS once with a row -> member map; for
+// each b the stored blocks of block column J_b are read once, coalesced, and each
+// is matched to its member by a binary search in LDS.  The workgroup then streams the column-major block column
 // into the dense column-major submatrix, four consecutive rows per thread: each
 // output column is a contiguous run, so writes are coalesced vector stores, and
 // each stored block is read contiguously.  The padding rows/columns (n..npad) are
@@ -21,6 +21,7 @@ namespace nolsm {
 
 constexpr int GATHER_MAXMEM = 1024;     // members per submatrix held in LDS
 constexpr int GATHER_MAXN = 8192;       // submatrix dimension held in the LDS row map
+constexpr int GATHER_GROUP = 4;         // member block columns per workgroup
 
 template <bool SPLIT_H>
 __global__ __launch_bounds__(256) void gather_kernel(
@@ -30,8 +31,10 @@ __global__ __launch_bounds__(256) void gather_kernel(
     const int64_t *__restrict__ valoff, const double *__restrict__ H_val,
     const double *__restrict__ S_val, char *__restrict__ ws) {
   const SubDesc d = desc[blockIdx.y];
-  const int b = blockIdx.x;
-  if (b > d.nmem) return;                       // b == nmem: padding columns
+  const int nmem = d.nmem;
+  const int b0 = blockIdx.x * GATHER_GROUP;     // member block columns b0 .. b0 + GROUP - 1
+  if (b0 > nmem) return;                        // b == nmem stands for the padding columns
+  const int b1 = b0 + GATHER_GROUP - 1 < nmem ? b0 + GATHER_GROUP - 1 : nmem;
   __shared__ int64_t s_t[GATHER_MAXMEM];        // value offset of block (J_a, J_b) or -1
   __shared__ int32_t s_loc[GATHER_MAXMEM + 1];  // first row of member a; s_loc[nmem] = n
   __shared__ int32_t s_mol[GATHER_MAXMEM];      // molecule of member a (ascending)
@@ -41,93 +44,97 @@ __global__ __launch_bounds__(256) void gather_kernel(
   const int n = d.n, ld = d.npad;
   _Float16 *Hs = reinterpret_cast<_Float16 *>(ws + d.off_lo) + 2 * (int64_t)ld * ld;   // buffer 1
 
-  if (b == d.nmem) {                            // columns n..npad: zero / identity
-    for (int c = n; c < ld; ++c)
-      for (int r = threadIdx.x; r < ld; r += blockDim.x) {
-        if (SPLIT_H) {
-          Hs[(int64_t)c * 2 * ld + r] = (_Float16)0.0f;
-          Hs[(int64_t)c * 2 * ld + ld + r] = (_Float16)0.0f;
-        } else {
-          Hk[(int64_t)c * ld + r] = 0.0;
-        }
-        Sk[(int64_t)c * ld + r] = (r == c) ? 1.0 : 0.0;
-      }
-    return;
-  }
-
-  const int nmem = d.nmem;
-  const int Jb = mem_mol[d.mem_off + b];
-  const int locb = mem_loc[d.mem_off + b];
-  const int dJ = blk_dim[Jb];
-  const int64_t c0 = colptr[Jb], c1 = colptr[Jb + 1];
-  for (int a = threadIdx.x; a < nmem; a += blockDim.x) {
-    const int Ja = mem_mol[d.mem_off + a];
-    const int loc = mem_loc[d.mem_off + a], dim = blk_dim[Ja];
-    s_mol[a] = Ja;
-    s_loc[a] = loc;
-    s_t[a] = -1;                                 // absent unless block column J_b stores it
-    for (int r = 0; r < dim; ++r) s_rowmem[loc + r] = (uint16_t)a;
-  }
-  if (threadIdx.x == 0) s_loc[nmem] = n;
-  __syncthreads();
-  for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
-    const int J = rowblk[e];
-    int lo = 0, hi = nmem;                       // first member >= J
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (s_mol[mid] < J) lo = mid + 1; else hi = mid;
+  if (b0 < nmem) {                              // the member list and row map, once
+    for (int a = threadIdx.x; a < nmem; a += blockDim.x) {
+      const int Ja = mem_mol[d.mem_off + a];
+      const int loc = mem_loc[d.mem_off + a], dim = blk_dim[Ja];
+      s_mol[a] = Ja;
+      s_loc[a] = loc;
+      for (int r = 0; r < dim; ++r) s_rowmem[loc + r] = (uint16_t)a;
     }
-    if (lo < nmem && s_mol[lo] == J) s_t[lo] = valoff[e];     // rows are distinct
+    if (threadIdx.x == 0) s_loc[nmem] = n;
   }
-  __syncthreads();
 
-  // column by column (32-bit index arithmetic, no per-element division); rows of
-  // one member are contiguous in both the stored block and the output column.
-  // ld is a multiple of 64, so every four-row group lies inside the column.
   typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-  for (int c = 0; c < dJ; ++c) {
-    double *hcol = Hk + (int64_t)(locb + c) * ld;
-    _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
-    double *scol = Sk + (int64_t)(locb + c) * ld;
-    const int col = locb + c;
-    for (int i0 = 4 * threadIdx.x; i0 < ld; i0 += 4 * blockDim.x) {
-      double h[4], sv[4];
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int i = i0 + e;
-        h[e] = 0.0;
-        sv[e] = 0.0;
-        if (i < n) {
-          const int a = s_rowmem[i];
-          const int64_t v0 = s_t[a];
-          if (v0 >= 0) {
-            const int64_t src = v0 + (i - s_loc[a]) + c * (s_loc[a + 1] - s_loc[a]);
-            h[e] = H_val[src];
-            if (i >= col) sv[e] = S_val[src];
+  for (int b = b0; b <= b1; ++b) {
+    if (b == nmem) {                            // columns n..npad: zero / identity
+      for (int c = n; c < ld; ++c)
+        for (int r = threadIdx.x; r < ld; r += blockDim.x) {
+          if (SPLIT_H) {
+            Hs[(int64_t)c * 2 * ld + r] = (_Float16)0.0f;
+            Hs[(int64_t)c * 2 * ld + ld + r] = (_Float16)0.0f;
+          } else {
+            Hk[(int64_t)c * ld + r] = 0.0;
           }
+          Sk[(int64_t)c * ld + r] = (r == c) ? 1.0 : 0.0;
         }
+      break;
+    }
+    const int Jb = mem_mol[d.mem_off + b];
+    const int locb = mem_loc[d.mem_off + b];
+    const int dJ = blk_dim[Jb];
+    const int64_t c0 = colptr[Jb], c1 = colptr[Jb + 1];
+    __syncthreads();                             // the previous column set is done with s_t
+    for (int a = threadIdx.x; a < nmem; a += blockDim.x) s_t[a] = -1;   // absent by default
+    __syncthreads();
+    for (int64_t e = c0 + threadIdx.x; e < c1; e += blockDim.x) {
+      const int J = rowblk[e];
+      int lo = 0, hi = nmem;                     // first member >= J
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_mol[mid] < J) lo = mid + 1; else hi = mid;
       }
-      if (SPLIT_H) {
-        h4 hi, lo;
+      if (lo < nmem && s_mol[lo] == J) s_t[lo] = valoff[e];   // rows are distinct
+    }
+    __syncthreads();
+
+    // column by column (32-bit index arithmetic, no per-element division); rows of
+    // one member are contiguous in both the stored block and the output column.
+    // ld is a multiple of 64, so every four-row group lies inside the column.
+    for (int c = 0; c < dJ; ++c) {
+      double *hcol = Hk + (int64_t)(locb + c) * ld;
+      _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
+      double *scol = Sk + (int64_t)(locb + c) * ld;
+      const int col = locb + c;
+      for (int i0 = 4 * threadIdx.x; i0 < ld; i0 += 4 * blockDim.x) {
+        double h[4], sv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          hi[e] = (_Float16)h[e];                        // one rounding from FP64
-          lo[e] = (_Float16)((h[e] - (double)hi[e]) * 2048.0);
+          const int i = i0 + e;
+          h[e] = 0.0;
+          sv[e] = 0.0;
+          if (i < n) {
+            const int a = s_rowmem[i];
+            const int64_t v0 = s_t[a];
+            if (v0 >= 0) {
+              const int64_t src = v0 + (i - s_loc[a]) + c * (s_loc[a + 1] - s_loc[a]);
+              h[e] = H_val[src];
+              if (i >= col) sv[e] = S_val[src];
+            }
+          }
         }
-        *reinterpret_cast<h4 *>(hrow + i0) = hi;
-        *reinterpret_cast<h4 *>(hrow + ld + i0) = lo;
-      } else {
-        *reinterpret_cast<double2 *>(hcol + i0) = make_double2(h[0], h[1]);
-        *reinterpret_cast<double2 *>(hcol + i0 + 2) = make_double2(h[2], h[3]);
-      }
-      // the factorisation reads the lower triangle only
-      if (i0 >= col) {
-        *reinterpret_cast<double2 *>(scol + i0) = make_double2(sv[0], sv[1]);
-        *reinterpret_cast<double2 *>(scol + i0 + 2) = make_double2(sv[2], sv[3]);
-      } else if (i0 + 3 >= col) {
+        if (SPLIT_H) {
+          h4 hi, lo;
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (i0 + e >= col) scol[i0 + e] = sv[e];
+          for (int e = 0; e < 4; ++e) {
+            hi[e] = (_Float16)h[e];                      // one rounding from FP64
+            lo[e] = (_Float16)((h[e] - (double)hi[e]) * 2048.0);
+          }
+          *reinterpret_cast<h4 *>(hrow + i0) = hi;
+          *reinterpret_cast<h4 *>(hrow + ld + i0) = lo;
+        } else {
+          *reinterpret_cast<double2 *>(hcol + i0) = make_double2(h[0], h[1]);
+          *reinterpret_cast<double2 *>(hcol + i0 + 2) = make_double2(h[2], h[3]);
+        }
+        // the factorisation reads the lower triangle only
+        if (i0 >= col) {
+          *reinterpret_cast<double2 *>(scol + i0) = make_double2(sv[0], sv[1]);
+          *reinterpret_cast<double2 *>(scol + i0 + 2) = make_double2(sv[2], sv[3]);
+        } else if (i0 + 3 >= col) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (i0 + e >= col) scol[i0 + e] = sv[e];
+        }
       }
     }
   }
@@ -136,7 +143,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
 void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
                    const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
                    const double *S_val, bool split_h, char *ws, hipStream_t stream) {
-  dim3 grid(maxmem + 1, K);
+  dim3 grid((maxmem + GATHER_GROUP) / GATHER_GROUP, K);   // members 0..maxmem (padding)
   if (split_h)
     gather_kernel<true><<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim,
                                                   pat->colptr, pat->rowblk, pat->valoff, H_val,
