@@ -6,7 +6,7 @@ potential: gather T_k(H0), T_k(S) -> FP64 set-up -> batched sign iteration ->
 panel refinement and density columns -> scatter into D -> Tr(DH), Tr(DS).
 Inputs are resident in HBM before the timed region starts.
 
-The reported value follows the paper's accounting (Sec. IV, "FLOPs in the NOLSM
+The reported value follows the paper's accounting (Sec. V-B, "FLOPs in the NOLSM
 method" and "Node-Performance"): FLOPs are 2 n^3 per n x n x n product of the
 matrix iterations (two products per Newton-Schulz step), O(n^2) work is not
 counted, and the time is the wall time of the whole step.  The roofline entry is

@@ -156,7 +156,7 @@ typedef struct nolsm_plan nolsm_plan;
 nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
                                int32_t K, nolsm_plan **plan /*host out*/);
 
-/* Planning options (GEMM performance depends on the submatrix size, Sec. III-B,
+/* Planning options (GEMM performance depends on the submatrix size, Sec. IV-B,
  * Table II).  big_tile_min_npad: submatrices whose padded dimension is at least
  * this use the 256 x 128 FP16/BF16 tiles (two workgroups per CU), smaller ones
  * 128 x 128 tiles; a negative value selects the library default (768).  The

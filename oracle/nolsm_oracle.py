@@ -26,11 +26,18 @@ symmetric eigenproblem H_k C = S_k C Lambda, C^T S_k C = I:
     T_k(D) = 1/2 C (I - sgn(Lambda - mu)) C^T S_k C C^T = C theta(mu - Lambda) C^T,
 with theta(x) = 1 for x > 0, 0 for x < 0 and 1/2 at x = 0 (sign(0) = 0).
 
-Eq. 6-7 (Newton-Schulz) is provided as `newton_schulz_sign`, used by tests and as
-the source of iteration-count labels; the oracle's density never depends on it.
+Eq. 6-7 (Newton-Schulz) is provided as `newton_schulz_sign` for the tests (which
+pin it and compare it with the eigen route); the oracle's density never depends
+on it, and nothing else uses it.
 `order=3` gives the third-order member of the same polynomial family (Sec. II's
 higher-order schemes); both are pinned by the sign identities, the eigen-
 decomposition, the scalar map and (order 3) its cubic rate.
+
+The chemical potential (Sec. V-A: the runs iterate mu until the system is
+charge neutral) is found by `mu_search`: bisection of the electron count
+Tr(D(mu) S) against the target, with every submatrix's eigen-decomposition
+computed once and reused for every trial mu, since only the occupations
+theta(mu - Lambda) depend on mu.
 
 Readings of points the paper leaves open are listed in the design notes: the
 molecule-column grouping, mu = 0, no spin factor (Tr(DS) counts occupied
@@ -256,3 +263,74 @@ def density_matrix(inst, mu: float | None = None, mols=None):
 def energy_per_atom_error(inst, e_a: float, e_b: float) -> float:
     """|E_a - E_b| / N_atoms (sites count as atoms)."""
     return abs(e_a - e_b) / inst.natoms
+
+
+# ----------------------------------------------------------------- chemical potential
+
+def submatrix_spectra(inst, mols=None) -> list:
+    """Generalized eigen-decomposition H_k C = S_k C Lambda of every submatrix.
+
+    Eq. 8 depends on mu only through the occupations theta(mu - Lambda), so one
+    decomposition per submatrix serves every trial chemical potential.
+    """
+    out = []
+    for k in (range(inst.nmol) if mols is None else mols):
+        Hk, offs = gather(inst, inst.H_val, int(k))
+        Sk, _ = gather(inst, inst.S_val, int(k))
+        lam, C = scipy.linalg.eigh(Hk, Sk)
+        out.append({"k": int(k), "offs": offs, "lam": lam, "C": C})
+    return out
+
+
+def density_matrix_at(inst, spectra: list, mu: float) -> np.ndarray:
+    """Scattered D at chemical potential mu from precomputed submatrix spectra."""
+    D_val = np.zeros_like(inst.H_val)
+    for sp in spectra:
+        Dk = (sp["C"] * theta(mu - sp["lam"])[None, :]) @ sp["C"].T
+        scatter(inst, D_val, sp["k"], Dk, sp["offs"])
+    return D_val
+
+
+def mu_bisection(count, n_target: float, mu_lo: float, mu_hi: float, tol: float = 0.5,
+                 max_iter: int = 40):
+    """Bisection of the chemical potential on the electron count.
+
+    count(mu) returns Tr(D(mu) S).  The bracket keeps count(lo) below
+    n_target - tol and count(hi) above n_target + tol (the caller's bracket is
+    taken as such); every trial is the midpoint, and the search ends at the
+    first trial whose count lies within tol of the target, or after max_iter
+    trials.  Returns (mu, [(mu_t, count_t), ...], converged).
+    """
+    lo, hi = float(mu_lo), float(mu_hi)
+    hist = []
+    mu = 0.5 * (lo + hi)
+    for _ in range(max_iter):
+        mu = 0.5 * (lo + hi)
+        n = float(count(mu))
+        hist.append((mu, n))
+        if n < n_target - tol:
+            lo = mu
+        elif n > n_target + tol:
+            hi = mu
+        else:
+            return mu, hist, True
+    return mu, hist, False
+
+
+def mu_search(inst, n_target: float, mu_lo: float, mu_hi: float, tol: float = 0.5,
+              max_iter: int = 40) -> dict:
+    """Charge-neutral chemical potential of the whole instance (Sec. V-A).
+
+    Returns the final mu, the trial history, the scattered D at that mu and its
+    traces (Tr(D H0), Tr(D S)).
+    """
+    spectra = submatrix_spectra(inst)
+
+    def count(mu):
+        D = density_matrix_at(inst, spectra, mu)
+        return traces(inst, D, inst.H_val, inst.S_val)[1]
+
+    mu, hist, ok = mu_bisection(count, n_target, mu_lo, mu_hi, tol, max_iter)
+    D = density_matrix_at(inst, spectra, mu)
+    e, ne = traces(inst, D, inst.H_val, inst.S_val)
+    return {"mu": mu, "hist": hist, "converged": ok, "D_val": D, "tr_dh": e, "tr_ds": ne}

@@ -2,7 +2,7 @@
 
     python -m paper_2205_12182_amd.autotune --out paper_2205_12182_amd/data/tile_policy.json
 
-GEMM throughput depends on the submatrix size (paper, Sec. III-B and Table II).  For a
+GEMM throughput depends on the submatrix size (paper, Sec. IV-B and Table II).  For a
 sweep of sizes (water boxes of 1,024 molecules with 13+5+5 functions and a range of
 cutoff radii), the FP16 products of a fixed number of Newton-Schulz iterations are
 timed with every submatrix on 128 x 128 tiles and with every submatrix on 256 x 128

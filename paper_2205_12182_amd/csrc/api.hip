@@ -161,7 +161,7 @@ nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pat, const int32_t *mols,
     p->max_npad = std::max(p->max_npad, d.npad);
   }
   // tiles of the symmetric sign-iteration products: upper triangle; small
-  // submatrices use 128 x 128 tiles, the rest 256 x 256.  Executed flops skip the
+  // submatrices use 128 x 128 tiles, the rest 256 x 128 (FP16/BF16) or 128 x 128 (FP32).  Executed flops skip the
   // 32 x 32 blocks that lie entirely in the padding.
   // list 0: small submatrices, 128 x 128 tiles; list 1: large, 256 x 128 tiles (rows x
   // columns; kept when the tile reaches the upper triangle, 2 ti <= tj); list 2: large,

@@ -22,7 +22,7 @@ def test_more_than_one_gpu_exits_with_a_message():
 
 
 def test_paper_flops_counts_2n3_per_product():
-    """Sec. IV-B: 2 n^3 per n x n x n product; Newton-Schulz has two per iteration,
+    """Sec. V-B: 2 n^3 per n x n x n product; Newton-Schulz has two per iteration,
     the third-order step three; restarted (FP32) iterations count as well."""
     st = {"n": np.array([10, 20]), "iters_lo": np.array([3, 1]), "iters_fb": np.array([1, 0])}
     assert bench.paper_flops(st) == 2 * 2 * (1000 * 4 + 8000 * 1)

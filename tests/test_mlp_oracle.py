@@ -54,3 +54,39 @@ def test_loss_decreases_on_learnable_target():
         _, dy = M.mse(y, t)
         p, m, v = M.adam(p, M.backward(p, 1, x, c, dy), m, v, 3e-3, 0.9, 0.999, 1e-8, step)
     assert M.loss(p, 1, x, t) < 0.1 * l0
+
+
+# Kingma and Ba, Algorithm 1: with bias correction the first step moves every
+# parameter by lr * g / (|g| + eps), whatever the scale of g, and a constant
+# gradient keeps the corrected moments at g and g^2, so every step has that size.
+def check_adam_first_step_and_constant_gradient(adam):
+    lr, b1, b2, eps = 0.01, 0.9, 0.999, 1e-8
+    g = np.array([3.0, -0.02, 150.0, -7.5])
+    p0 = np.array([0.5, -1.0, 2.0, 0.0])
+    p1, m, v = adam(p0, g, np.zeros(4), np.zeros(4), lr, b1, b2, eps, 1)
+    assert np.allclose(p1 - p0, -lr * g / (np.abs(g) + eps), rtol=1e-12, atol=0)
+    p = p1
+    for step in range(2, 6):
+        q, m, v = adam(p, g, m, v, lr, b1, b2, eps, step)
+        assert np.allclose(q - p, -lr * g / (np.abs(g) + eps), rtol=1e-9, atol=0)
+        p = q
+
+
+def test_adam_bias_corrected_steps():
+    check_adam_first_step_and_constant_gradient(M.adam)
+
+
+def test_planted_adam_without_bias_correction():
+    def no_correction(p, g, m, v, lr, b1, b2, eps, step):
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        return p - lr * m / (np.sqrt(v) + eps), m, v
+
+    def shifted_correction(p, g, m, v, lr, b1, b2, eps, step):
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        return p - lr * (m / (1 - b1 ** (step + 1))) / (np.sqrt(v / (1 - b2 ** (step + 1))) + eps), m, v
+
+    for bad in (no_correction, shifted_correction):
+        with pytest.raises(AssertionError):
+            check_adam_first_step_and_constant_gradient(bad)

@@ -427,3 +427,124 @@ def test_planted_third_order_coefficient(monkeypatch):
     monkeypatch.setattr(O, "newton_schulz_sign", bad)
     assert _fails(check_sign_invariants, 0, 3)
     monkeypatch.setattr(O, "newton_schulz_sign", orig)
+
+
+# ------------------------------------------------------------------ per-submatrix driver
+
+def read_block_column(inst, D_val, k, offs):
+    """Block column k of a scattered D, laid out as T_k(D)[:, own columns]."""
+    mem = inst.members(k)
+    m = int(inst.blk_dim[k])
+    out = np.zeros((int(offs[-1]), m))
+    for a, I in enumerate(mem):
+        t = int(inst.colptr[k]) + a
+        dI = int(inst.blk_dim[I])
+        s = int(inst.valoff[t])
+        out[offs[a]:offs[a + 1], :] = D_val[s:s + dI * m].reshape(m, dI).T
+    return out
+
+
+@pytest.mark.parametrize("name,mu", [("c1", None), ("c1", -0.3), ("t_23", None)])
+def test_submatrix_result_matches_scattered_density(name, mu):
+    """submatrix_result (the per-molecule record the GPU tests and the benchmark
+    compare against) holds exactly block column k of density_matrix's D, which the
+    whole-system, closed-form and inertia pins fix; its traces are the column sums."""
+    inst = get_config(name)
+    ks = list(range(0, inst.nmol, max(1, inst.nmol // 6)))
+    D_val, _ = O.density_matrix(inst, mu=mu, mols=ks)
+    for k in ks:
+        r = O.submatrix_result(inst, k, mu=mu)
+        assert np.array_equal(r["members"], inst.members(k))
+        assert r["D_cols"].shape == (r["n"], int(inst.blk_dim[k]))
+        assert np.array_equal(read_block_column(inst, D_val, k, r["offs"]), r["D_cols"])
+        eh, es = O.column_traces(inst, D_val, inst.H_val, inst.S_val, k)
+        assert abs(r["tr_dh"] - eh) <= 1e-12 * max(1.0, abs(eh))
+        assert abs(r["tr_ds"] - es) <= 1e-12 * max(1.0, abs(es))
+
+
+# ------------------------------------------------------------------ chemical potential search
+
+LEVELS = np.array([-1.5, -0.2, -0.01, 0.3, 0.7, 2.0])
+
+
+def check_mu_bisection_hand():
+    """Diagonal system, S = I: Tr(D(mu) S) = #{h_i < mu}.  Target 3, tolerance 0.5,
+    bracket [-4, 3]; the trials worked out by hand:
+      -0.5 (count 1: lo), 1.25 (5: hi), 0.375 (4: hi), -0.0625 (2: lo), 0.15625 (3: done)."""
+    inst = instance_from_dense(np.diag(LEVELS), np.eye(6), [2, 2, 2], np.ones((3, 3)))
+    r = O.mu_search(inst, 3, -4.0, 3.0, tol=0.5)
+    assert r["converged"]
+    assert [m for m, _ in r["hist"]] == [-0.5, 1.25, 0.375, -0.0625, 0.15625]
+    assert [round(n, 12) for _, n in r["hist"]] == [1.0, 5.0, 4.0, 2.0, 3.0]
+    assert abs(r["tr_dh"] - LEVELS[:3].sum()) < 1e-14
+
+
+def check_mu_search_whole_system():
+    """c1 with every submatrix the whole system: the count is the number of
+    generalized eigenvalues below mu (SciPy eigenvalues of the dense pair), and the
+    search ends between the 96th and 97th eigenvalue, with D S D = D there."""
+    inst = get_config("c1_whole")
+    H, S = dense(inst, inst.H_val), dense(inst, inst.S_val)
+    lam = scipy.linalg.eigvalsh(H, S)
+    spectra = O.submatrix_spectra(inst, mols=[0])
+    for mu in (-1.2, -0.9, -0.5, 0.0, 0.4, 0.8):
+        # one submatrix is the whole system: its columns for molecule 0 only, so
+        # evaluate the full D from the whole-system decomposition directly
+        C, lk = spectra[0]["C"], spectra[0]["lam"]
+        Dfull = (C * O.theta(mu - lk)[None, :]) @ C.T
+        assert abs(np.trace(Dfull @ S) - np.sum(lam < mu)) < 1e-9
+    r = O.mu_search(inst, inst.n_elec, -1.0, 3.0)
+    assert len(r["hist"]) >= 2
+    assert r["converged"]
+    assert lam[inst.n_elec - 1] < r["mu"] < lam[inst.n_elec]
+    assert abs(r["tr_ds"] - inst.n_elec) < 1e-9
+    assert abs(r["tr_dh"] - lam[:inst.n_elec].sum()) < 1e-9
+    D = dense(inst, r["D_val"])
+    assert np.abs(D @ S @ D - D).max() < 1e-10
+    # every trial's count is the number of eigenvalues below it
+    for mu, n in r["hist"]:
+        assert abs(n - np.sum(lam < mu)) < 1e-9
+
+
+def test_mu_bisection_hand_sequence():
+    check_mu_bisection_hand()
+
+
+def test_mu_search_whole_system():
+    check_mu_search_whole_system()
+
+
+def test_density_at_reuses_spectra():
+    """The cached-spectrum route equals the fresh per-mu route bit for bit."""
+    inst = get_config("c1")
+    ks = [0, 5, 17, 31]
+    spectra = O.submatrix_spectra(inst, mols=ks)
+    for mu in (-0.9, -0.3, 0.0, 0.3):
+        D1 = O.density_matrix_at(inst, spectra, mu)
+        D2, _ = O.density_matrix(inst, mu=mu, mols=ks)
+        assert np.array_equal(D1, D2)
+
+
+def test_planted_bisection_swapped(monkeypatch):
+    def bad(count, n_target, mu_lo, mu_hi, tol=0.5, max_iter=40):
+        lo, hi, hist = mu_lo, mu_hi, []
+        for _ in range(max_iter):
+            mu = 0.5 * (lo + hi)
+            n = count(mu)
+            hist.append((mu, n))
+            if n < n_target - tol:
+                hi = mu                      # wrong side
+            elif n > n_target + tol:
+                lo = mu
+            else:
+                return mu, hist, True
+        return mu, hist, False
+    monkeypatch.setattr(O, "mu_bisection", bad)
+    assert _fails(check_mu_bisection_hand) and _fails(check_mu_search_whole_system)
+
+
+def test_planted_occupation_ignores_mu(monkeypatch):
+    def bad(inst, spectra, mu):
+        return O.density_matrix(inst, mu=0.0, mols=[s["k"] for s in spectra])[0]
+    monkeypatch.setattr(O, "density_matrix_at", bad)
+    assert _fails(check_mu_bisection_hand)

@@ -93,6 +93,12 @@ class Instance:
     def natoms(self) -> int:
         return int(self.atoms.sum())
 
+    @property
+    def n_elec(self) -> int:
+        """Electrons of the neutral system: one per function with the lower onsite
+        energy, i.e. floor(n_f / 2) per molecule (no spin factor)."""
+        return int((self.blk_dim // 2).sum())
+
     def members(self, k: int) -> np.ndarray:
         """Molecules present in block column k (ascending; includes k)."""
         return self.rowblk[self.colptr[k]:self.colptr[k + 1]]
