@@ -257,6 +257,20 @@ nolsm_status nolsm_energy(const nolsm_pattern *pattern_dev, int32_t nmol, const 
                           const double *H_val, const double *S_val, double *col_traces,
                           double *out2, hipStream_t stream);
 
+/* nolsm_energy for callers that cannot allocate or pass scratch memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation): the
+ * same result, bit for bit, with the per-block-column sums kept in a fixed device
+ * array of the library (2 * NOLSM_ENERGY_NOALLOC_MAXMOL doubles, 2 MiB, one copy
+ * per GPU, held until the process ends).  Allocates nothing.  Every call on one GPU
+ * uses that GPU's array, so calls that overlap in time on one GPU (several streams
+ * or threads) race; the array keeps the last call's sums.
+ * NOLSM_EINVAL for a bad argument or nmol > NOLSM_ENERGY_NOALLOC_MAXMOL;
+ * NOLSM_EHIP if the array's address cannot be obtained or a launch fails. */
+#define NOLSM_ENERGY_NOALLOC_MAXMOL 131072
+nolsm_status nolsm_energy_noalloc(const nolsm_pattern *pattern_dev, int32_t nmol,
+                                  const double *D_val, const double *H_val, const double *S_val,
+                                  double *out2, hipStream_t stream);
+
 /* Learned schedule: a multilayer perceptron NOLSM_NFEAT -> 64 -> 64 -> nout
  * (SiLU hidden activations, linear output, FP32) with hand-written training
  * kernels.  Parameters are one FP32 array, in order W1[64][16], b1[64],

@@ -106,6 +106,7 @@ def lib():
         "nolsm_sign_batched": (i32, [vp, dbl, P(Schedule), vp, vp]),
         "nolsm_scatter_density": (i32, [vp, P(Pattern), vp, vp, vp, vp, vp]),
         "nolsm_energy": (i32, [P(Pattern), i32, vp, vp, vp, vp, vp, vp]),
+        "nolsm_energy_noalloc": (i32, [P(Pattern), i32, vp, vp, vp, vp, vp]),
         "nolsm_check": (i32, [vp, vp]),
         "nolsm_plan_set_timing": (i32, [vp, i32]),
         "nolsm_setup_batched": (i32, [vp, vp]),
@@ -130,7 +131,7 @@ def lib():
 
 EXPORTED = ("nolsm_plan_create", "nolsm_plan_create_ex", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
             "nolsm_plan_table_bytes", "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
-            "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_check",
+            "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_energy_noalloc", "nolsm_check",
             "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings",
             "nolsm_setup_batched", "nolsm_features", "nolsm_mlp_param_count",
             "nolsm_mlp_scratch_floats", "nolsm_mlp_forward", "nolsm_mlp_backward",
@@ -273,6 +274,14 @@ def nolsm_energy(dev_pattern: DevicePattern, D_val, H_val, S_val, col_traces, ou
     _ok(lib().nolsm_energy(ctypes.byref(dev_pattern.struct), dev_pattern.nmol, _ptr(D_val),
                            _ptr(H_val), _ptr(S_val), _ptr(col_traces), _ptr(out2),
                            _stream(stream)))
+
+
+def nolsm_energy_noalloc(dev_pattern: DevicePattern, D_val, H_val, S_val, out2, stream=None):
+    _ok(lib().nolsm_energy_noalloc(ctypes.byref(dev_pattern.struct), dev_pattern.nmol, _ptr(D_val),
+                                   _ptr(H_val), _ptr(S_val), _ptr(out2), _stream(stream)))
+
+
+ENERGY_NOALLOC_MAXMOL = 131072
 
 
 def nolsm_check(plan, stream=None) -> int:

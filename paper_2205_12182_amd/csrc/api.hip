@@ -29,6 +29,7 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
                    const double *S_val, double *col_traces, double *out2, hipStream_t s);
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
                   hipStream_t s);
+hipError_t energy_scratch_ptr(double **out);
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
 void launch_features(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
                      double mu, float *feat, hipStream_t s);
@@ -440,6 +441,22 @@ nolsm_status nolsm_energy(const nolsm_pattern *pat, int32_t nmol, const double *
     return fail(NOLSM_EINVAL, "nolsm_energy: bad argument");
   launch_energy(pat, nmol, D_val, H_val, S_val, col_traces, out2, s);
   return hip_check("nolsm_energy");
+}
+
+nolsm_status nolsm_energy_noalloc(const nolsm_pattern *pat, int32_t nmol, const double *D_val,
+                                  const double *H_val, const double *S_val, double *out2,
+                                  hipStream_t s) {
+  if (!pat || !D_val || !H_val || !S_val || !out2 || nmol < 0 || nmol != pat->nmol)
+    return fail(NOLSM_EINVAL, "nolsm_energy_noalloc: bad argument");
+  if (nmol > NOLSM_ENERGY_NOALLOC_MAXMOL)
+    return fail(NOLSM_EINVAL, "nolsm_energy_noalloc: nmol = %d exceeds the limit %d (use nolsm_energy)",
+                nmol, NOLSM_ENERGY_NOALLOC_MAXMOL);
+  double *col = nullptr;
+  const hipError_t e = energy_scratch_ptr(&col);
+  if (e != hipSuccess)
+    return fail(NOLSM_EHIP, "nolsm_energy_noalloc: scratch address: %s", hipGetErrorString(e));
+  launch_energy(pat, nmol, D_val, H_val, S_val, col, out2, s);
+  return hip_check("nolsm_energy_noalloc");
 }
 
 nolsm_status nolsm_plan_set_timing(nolsm_plan *p, int enable) {

@@ -23,6 +23,8 @@ constexpr int RESID_SHIFT = 40;    // fixed-point scale of the residual accumula
 constexpr float RESID_CLAMP = 1.0e4f;
 constexpr int NPANEL = 8;         // n x m FP32 panel slots per submatrix
 constexpr int MAXM = 32;          // own columns per molecule handled by the panel kernels
+constexpr int ENERGY_NOALLOC_MAXMOL = NOLSM_ENERGY_NOALLOC_MAXMOL;   // nolsm_energy_noalloc limit
+constexpr int MAX_DEVICES = 64;   // devices whose scratch address is cached
 
 enum Prec : int32_t { P_FP32 = 0, P_FP16 = 1, P_BF16 = 2 };
 

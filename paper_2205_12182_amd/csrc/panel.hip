@@ -12,6 +12,8 @@
 //   dcol_kernel        Dcol = 1/2 L^-T (V - W)             (FP64)
 //   scatter_kernel     block column k of D <- Dcol; per-column Tr contributions (FP64)
 //   coltrace / final   Tr(D H), Tr(D S) over the whole pattern, fixed reduction order
+#include <mutex>
+
 #include "common.h"
 
 namespace nolsm {
@@ -467,6 +469,31 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
   coltrace_kernel<<<nmol, 256, 0, s>>>(pat->blk_dim, pat->colptr, pat->rowblk, pat->valoff,
                                        D_val, H_val, S_val, col_traces);
   final_trace_kernel<<<1, 256, 0, s>>>(col_traces, nmol, out2);
+}
+
+// Per-block-column partial traces for callers that cannot allocate (graph capture,
+// serving loops): a fixed array in device memory, one copy per GPU, shared by every
+// such call on that GPU.  coltrace_kernel writes every entry it covers before
+// final_trace_kernel reads it, so nothing needs clearing between calls.
+static __device__ __align__(256) double scratch[2 * ENERGY_NOALLOC_MAXMOL];
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t energy_scratch_ptr(double **out) {
+  static std::mutex mtx;
+  static double *ptrs[MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mtx);
+  if (!ptrs[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    ptrs[dev] = static_cast<double *>(p);
+  }
+  *out = ptrs[dev];
+  return hipSuccess;
 }
 
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
