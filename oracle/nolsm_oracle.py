@@ -334,3 +334,137 @@ def mu_search(inst, n_target: float, mu_lo: float, mu_hi: float, tol: float = 0.
     D = density_matrix_at(inst, spectra, mu)
     e, ne = traces(inst, D, inst.H_val, inst.S_val)
     return {"mu": mu, "hist": hist, "converged": ok, "D_val": D, "tr_dh": e, "tr_ds": ne}
+
+
+# ----------------------------------------------------------------- submatrix combination
+
+def submatrix_rows(pattern, group) -> np.ndarray:
+    """Molecules of the submatrix shared by the columns of `group` (Sec. IV-B: the
+    submatrix of a set of combined columns keeps every row that is non-zero in any
+    of them): the union of the block columns' stored rows, ascending."""
+    rows = np.unique(np.concatenate([members(pattern, int(k)) for k in group]))
+    return rows.astype(np.int64)
+
+
+def rate_at(n: int, table) -> float:
+    """Measured GEMM throughput at dimension n: linear interpolation of the table
+    [(n_i, rate_i)] (ascending n_i), constant beyond its ends."""
+    ns = [float(a) for a, _ in table]
+    rs = [float(b) for _, b in table]
+    x = float(n)
+    if x <= ns[0]:
+        return rs[0]
+    if x >= ns[-1]:
+        return rs[-1]
+    i = 0
+    while ns[i + 1] < x:
+        i += 1
+    t = (x - ns[i]) / (ns[i + 1] - ns[i])
+    d = (rs[i + 1] - rs[i]) * t
+    return rs[i] + d
+
+
+def combined_dimension(n_i: int, n_j: int, n_ij: int) -> int:
+    """Dimension of the submatrix of two combined column sets (Eq. 9):
+    n_i + n_j - n_(i and j), with n_(i and j) the rows the two share."""
+    return n_i + n_j - n_ij
+
+
+def combination_cost(n: int, criterion: int, table=None):
+    """Eq. 9: n^3 (the flop count of the dense products, exact integer).
+    Eq. 10: p(n) n^3 with p(n) the time per flop, 1 / rate_at(n) (reading: the
+    predicted run time of the submatrix's products)."""
+    n3 = int(n) ** 3
+    if criterion == 9:
+        return n3
+    return float(n3) / rate_at(n, table)
+
+
+def combine_groups(pattern, mols, criterion: int = 9, table=None, max_n: int | None = None):
+    """Greedy submatrix combination (Sec. IV-B, Eq. 9 or Eq. 10).
+
+    Start from one group per molecule.  Two groups are candidates when their
+    submatrices overlap (share at least one row molecule).  Combining them gives the
+    submatrix on the union of their rows, of dimension n_i + n_j - n_(i and j); the
+    gain is cost(n_i) + cost(n_j) - cost(n_i + n_j - n_(i and j)), positive exactly
+    when the criterion of Eq. 9 (or Eq. 10) holds.  Repeatedly combine the candidate
+    pair with the largest gain (ties: the pair whose smallest molecules, smaller
+    first, come first in lexicographic order), skipping pairs whose combined
+    dimension would exceed max_n, until no candidate pair has a positive gain.
+
+    Returns the groups as ascending molecule lists, ordered by their first molecule.
+    """
+    dims = np.asarray(pattern.blk_dim, dtype=np.int64)
+    group = {int(k): [int(k)] for k in mols}             # keyed by smallest molecule
+    rows = {k: set(int(j) for j in members(pattern, k)) for k in group}
+
+    def dim(rset):
+        return int(sum(int(dims[j]) for j in rset))
+
+    def gain(a, b):
+        nu = combined_dimension(dim(rows[a]), dim(rows[b]), dim(rows[a] & rows[b]))
+        if max_n is not None and nu > max_n:
+            return None
+        return (combination_cost(dim(rows[a]), criterion, table)
+                + combination_cost(dim(rows[b]), criterion, table)
+                - combination_cost(nu, criterion, table))
+
+    while True:
+        best = None
+        keys = sorted(group)
+        for i, a in enumerate(keys):
+            for b in keys[i + 1:]:
+                if not rows[a] & rows[b]:
+                    continue
+                g = gain(a, b)
+                if g is None or not g > 0:
+                    continue
+                if best is None or g > best[0]:
+                    best = (g, a, b)
+        if best is None:
+            break
+        _, a, b = best
+        group[a] = sorted(group[a] + group.pop(b))
+        rows[a] = rows[a] | rows.pop(b)
+    return [group[a] for a in sorted(group)]
+
+
+def density_matrix_groups(inst, groups, mu: float | None = None):
+    """Scattered D when each group of molecules shares one submatrix (Sec. IV-B):
+    Eq. 8 on the submatrix over the union of the group's rows, and every molecule of
+    the group writes its own block column from it (step 3 of the submatrix method).
+    Returns D and per-group records (molecules, n, per-molecule Tr(D H0) and Tr(D S)
+    column contributions)."""
+    mu = inst.mu if mu is None else mu
+    D_val = np.zeros_like(inst.H_val)
+    recs = []
+    for grp in groups:
+        rows = submatrix_rows(inst, grp)
+        idx = np.concatenate([np.arange(inst.blk_off[j], inst.blk_off[j + 1]) for j in rows])
+        pos = {int(j): a for a, j in enumerate(rows)}
+        loc = np.zeros(len(rows) + 1, dtype=np.int64)
+        loc[1:] = np.cumsum([int(inst.blk_dim[j]) for j in rows])
+        Hk = np.zeros((idx.size, idx.size))
+        Sk = np.zeros((idx.size, idx.size))
+        for b, J in enumerate(rows):
+            for t in range(int(inst.colptr[J]), int(inst.colptr[J + 1])):
+                I = int(inst.rowblk[t])
+                if I not in pos:
+                    continue
+                a = pos[I]
+                Hk[loc[a]:loc[a + 1], loc[b]:loc[b + 1]] = _block(inst, inst.H_val, t)
+                Sk[loc[a]:loc[a + 1], loc[b]:loc[b + 1]] = _block(inst, inst.S_val, t)
+        Dk, lam = density(Hk, Sk, mu)
+        per = []
+        for k in grp:
+            cols = np.arange(loc[pos[k]], loc[pos[k] + 1])
+            dk = int(inst.blk_dim[k])
+            for t in range(int(inst.colptr[k]), int(inst.colptr[k + 1])):
+                I = int(inst.rowblk[t])
+                a = pos[I]
+                s = int(inst.valoff[t])
+                D_val[s:s + int(inst.blk_dim[I]) * dk] = Dk[loc[a]:loc[a + 1], cols].T.reshape(-1)
+            per.append(column_traces(inst, D_val, inst.H_val, inst.S_val, k))
+        recs.append({"mols": list(grp), "n": int(idx.size), "traces": per,
+                     "gap": float(np.min(np.abs(lam - mu)))})
+    return D_val, recs

@@ -548,3 +548,99 @@ def test_planted_occupation_ignores_mu(monkeypatch):
         return O.density_matrix(inst, mu=0.0, mols=[s["k"] for s in spectra])[0]
     monkeypatch.setattr(O, "density_matrix_at", bad)
     assert _fails(check_mu_bisection_hand)
+
+
+# ------------------------------------------------------------------ submatrix combination
+
+def chain_instance(dims):
+    """Molecules 0..len(dims)-1 in a chain: block (I, J) stored for |I - J| <= 1."""
+    nm = len(dims)
+    nf = int(sum(dims))
+    present = np.abs(np.subtract.outer(np.arange(nm), np.arange(nm))) <= 1
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((nf, nf))
+    return instance_from_dense(0.5 * (B + B.T), np.eye(nf), dims, present)
+
+
+def check_combination_hand():
+    """Chain 0-1-2-3 of one-function molecules: submatrix sizes 2, 3, 3, 2.
+    Eq. 9 gains: (0,1) 8 + 27 - 27 = 8, (1,2) 27 + 27 - 64 = -10, (2,3) 8; (0,2) and
+    (1,3) overlap too, but their union is all four rows: 8 + 27 - 64 < 0.  The best
+    is a tie at 8 between (0,1) and (2,3); (0,1) comes first, leaving {0,1} (rows
+    0-2, n 3); then (2,3) gains 8; then {0,1} with {2,3} would need n 4:
+    27 + 27 - 64 < 0.  Result [[0, 1], [2, 3]].
+    Eq. 10 with rates (1, 1) .. (4, 100) (time per flop 1 / rate): c(2) = 8/34,
+    c(3) = 27/67, c(4) = 64/100; (0,1) and (2,3) gain c(2), {0,1} with {2,3} gains
+    2 c(3) - c(4) > 0, so everything ends in one group."""
+    inst = chain_instance([1, 1, 1, 1])
+    assert [len(inst.members(k)) for k in range(4)] == [2, 3, 3, 2]
+    assert O.combine_groups(inst, range(4), 9) == [[0, 1], [2, 3]]
+    table = [(1, 1.0), (4, 100.0)]
+    assert abs(O.rate_at(3, table) - 67.0) < 1e-12
+    assert O.combine_groups(inst, range(4), 10, table) == [[0, 1, 2, 3]]
+    # a size limit of 3 stops Eq. 10 at the first two combinations
+    assert O.combine_groups(inst, range(4), 10, table, max_n=3) == [[0, 1], [2, 3]]
+
+
+def check_combination_local_optimum(name, criterion, table=None):
+    """No pair of final groups whose submatrices overlap satisfies the criterion (the
+    gains recomputed from the group rows by brute force), every molecule is in
+    exactly one group, and the groups' D equals the plain per-molecule D when every
+    group is a single molecule."""
+    inst = get_config(name)
+    groups = O.combine_groups(inst, range(inst.nmol), criterion, table)
+    flat = sorted(k for g in groups for k in g)
+    assert flat == list(range(inst.nmol))
+    rows = [set(O.submatrix_rows(inst, g).tolist()) for g in groups]
+
+    def n_of(r):
+        return int(sum(int(inst.blk_dim[j]) for j in r))
+    for i in range(len(groups)):
+        for j in range(i + 1, len(groups)):
+            if rows[i] & rows[j]:
+                gain = (O.combination_cost(n_of(rows[i]), criterion, table)
+                        + O.combination_cost(n_of(rows[j]), criterion, table)
+                        - O.combination_cost(n_of(rows[i] | rows[j]), criterion, table))
+                assert not gain > 0, (i, j, gain)
+    return inst, groups
+
+
+def test_combination_hand_example():
+    check_combination_hand()
+
+
+def test_combination_local_optimum_and_constant_rate():
+    inst, g9 = check_combination_local_optimum("t_sweep", 9)
+    assert len(g9) < inst.nmol          # the small-cutoff boxes combine
+    # a constant rate makes Eq. 10 the cubic criterion of Eq. 9
+    _, g10 = check_combination_local_optimum("t_sweep", 10, [(1, 5.0), (10000, 5.0)])
+    assert g10 == g9
+
+
+def test_groups_density_special_cases():
+    """Singleton groups give density_matrix's D bit for bit; one group holding every
+    molecule makes each submatrix the whole system, whose exact D (eigenvalues of the
+    dense pair) fills every stored block."""
+    inst = get_config("c1")
+    D1, _ = O.density_matrix(inst)
+    D2, recs = O.density_matrix_groups(inst, [[k] for k in range(inst.nmol)])
+    assert np.array_equal(D1, D2)
+    Dw, recs = O.density_matrix_groups(inst, [list(range(inst.nmol))])
+    H, S = dense(inst, inst.H_val), dense(inst, inst.S_val)
+    lam, C = scipy.linalg.eigh(H, S)
+    Dex = (C[:, lam < 0]) @ C[:, lam < 0].T
+    mask = dense(inst, np.ones_like(inst.H_val)) != 0
+    assert np.abs(dense(inst, Dw)[mask] - Dex[mask]).max() < 1e-10
+    assert recs[0]["n"] == inst.nfunc
+
+
+def test_planted_combination_ignores_overlap(monkeypatch):
+    """Counting n_i + n_j instead of the union never satisfies Eq. 9."""
+    monkeypatch.setattr(O, "combined_dimension", lambda ni, nj, nij: ni + nj)
+    assert _fails(check_combination_hand)
+
+
+def test_planted_combination_criterion_reversed(monkeypatch):
+    real = O.combination_cost
+    monkeypatch.setattr(O, "combination_cost", lambda n, c, t=None: -real(n, c, t))
+    assert _fails(check_combination_hand)

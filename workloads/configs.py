@@ -8,7 +8,9 @@
             (30 functions) at 1.35x water's number density, r_c = 8 A
   c5        65,536 molecules, 23 functions, r_c = 8 A (one GPU's share of a large run)
 
-  t_*       small instances for parity tests: several GEMM tiles and a ragged tail
+  t_*       small instances for parity tests: several GEMM tiles and a ragged tail;
+            t_sweep puts five independent 64-molecule water boxes with cutoffs of
+            3.2-7 A side by side (submatrices of 46-1,012 functions in one batch)
 
 The diagonal shift delta of S is a property of (workload, seed).  For the named
 workloads it is tabulated (computed with workloads/shift_table.py, which runs the
@@ -19,7 +21,7 @@ from __future__ import annotations
 
 import math
 
-from .water import water_box, water_with_slab
+from .water import direct_sum, water_box, water_with_slab
 
 # (workload, seed) -> delta; filled by workloads/shift_table.py
 SHIFTS = {
@@ -48,6 +50,10 @@ CONFIGS = {
     "t_tiles": dict(kind="water", nmol=343, fn=(4, 1, 1), r_cut=8.0),
     "t_23": dict(kind="water", nmol=125, fn=(13, 5, 5), r_cut=6.0),
     "t_slab": dict(kind="slab", n_water=300, n_units=60, r_cut=6.0),
+    # lambda_min(S0) of the parts lies between -0.4 and -0.53: a fixed shift of 0.7 keeps every
+    # lambda_min(S) >= 0.1 without an eigenvalue estimate
+    "t_sweep": dict(kind="sweep", parts=[(64, (13, 5, 5), rc) for rc in (3.2, 4.0, 5.0, 6.0, 7.0)],
+                    shift=0.7),
 }
 
 
@@ -58,5 +64,9 @@ def get_config(name: str, seed: int = 0, shift: float | None = None):
         shift = _shift(name, seed)
     if c["kind"] == "water":
         return water_box(c["nmol"], c["fn"], c["r_cut"], seed=seed, shift=shift, name=name)
+    if c["kind"] == "sweep":
+        sh = c["shift"] if shift is None else shift
+        return direct_sum([water_box(n, fn, rc, seed=seed + i, shift=sh, name=f"{name}.{i}")
+                           for i, (n, fn, rc) in enumerate(c["parts"])], name=name)
     return water_with_slab(c["n_water"], c["n_units"], r_cut=c["r_cut"], seed=seed,
                            shift=shift, name=name)

@@ -428,3 +428,33 @@ def water_with_slab(n_water: int, n_units: int, unit_density_ratio: float = 1.35
                           box, r_cut, seed, mu=mu, shift=shift)
     inst.meta.update({"slab_z0": z0, "slab_thickness": thick})
     return inst
+
+
+def direct_sum(parts: list, name: str = "sum") -> Instance:
+    """Independent instances side by side as one block-diagonal instance (molecules
+    renumbered in order; no block couples two parts).  Used to put submatrices of
+    very different sizes into one batch."""
+    nmol = sum(p.nmol for p in parts)
+    blk_dim = np.concatenate([p.blk_dim for p in parts]).astype(np.int32)
+    blk_off = np.zeros(nmol + 1, dtype=np.int64)
+    blk_off[1:] = np.cumsum(blk_dim)
+    colptr, rowblk, valoff, H, S = [np.zeros(1, dtype=np.int64)], [], [], [], []
+    m0 = nnz0 = val0 = 0
+    for p in parts:
+        colptr.append(p.colptr[1:] + nnz0)
+        rowblk.append(p.rowblk + m0)
+        valoff.append(p.valoff + val0)
+        H.append(p.H_val)
+        S.append(p.S_val)
+        m0 += p.nmol
+        nnz0 += p.nnzb
+        val0 += p.nval
+    return Instance(name=name, nmol=nmol, blk_dim=blk_dim, blk_off=blk_off,
+                    colptr=np.concatenate(colptr), rowblk=np.concatenate(rowblk).astype(np.int32),
+                    valoff=np.concatenate(valoff), H_val=np.concatenate(H),
+                    S_val=np.concatenate(S), mu=parts[0].mu,
+                    atoms=np.concatenate([p.atoms for p in parts]).astype(np.int32),
+                    box=max(p.box for p in parts), r_cut=max(p.r_cut for p in parts),
+                    shift=max(p.shift for p in parts),
+                    centres=np.concatenate([p.centres for p in parts]),
+                    meta={"parts": [(p.name, p.nmol, p.r_cut, p.shift) for p in parts]})
