@@ -138,8 +138,10 @@ typedef struct {
 
 /* Where a submatrix lives inside the workspace (for inspection by tests). */
 typedef struct {
-  int32_t n, npad, mol, m;        /* dimension, leading dimension, molecule, own columns */
-  int32_t own_lo, nmem, pad0, pad1;
+  int32_t n, npad, mol, m;        /* dimension, leading dimension, first own molecule,
+                                     own columns                                         */
+  int32_t own_lo, nmem, ngrp, own_mem;   /* first own column, members, own molecules, the
+                                     first own molecule's place in the member order      */
   int64_t off_h;                  /* bytes: M_k (FP32 npad x npad); H_k (FP64) before it
                                      with FP32 set-up products                          */
   int64_t off_s;                  /* bytes: FP64 npad x npad, S_k then L^-1 (lower)    */
@@ -168,7 +170,13 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
 typedef struct {
   int32_t big_tile_min_npad;
   int32_t setup_products;
-  int32_t reserved[6];            /* must be zero */
+  int32_t persist;                /* 0 (default): every arena in the workspace.  1: the
+                                     set-up results M_k and L^-1 of every submatrix live in
+                                     a buffer of their own (nolsm_plan_persist_bytes, bound
+                                     with nolsm_plan_bind_persist), so they survive while
+                                     other plans use the shared workspace; a chemical-
+                                     potential search then sets each batch up once.     */
+  int32_t reserved[5];            /* must be zero */
 } nolsm_plan_options;
 
 /* nolsm_plan_create with options (host pointer; NULL = defaults).
@@ -176,6 +184,46 @@ typedef struct {
 nolsm_status nolsm_plan_create_ex(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
                                   int32_t K, const nolsm_plan_options *options /*host*/,
                                   nolsm_plan **plan /*host out*/);
+/* Plan a batch of combined submatrices (Sec. IV-B: columns are combined so that one
+ * submatrix serves several of them): submatrix g serves the block columns of the
+ * molecules grp_mols[grp_ptr[g] .. grp_ptr[g+1]-1] (host arrays; grp_ptr[0] = 0).
+ * Its rows are the union of those block columns' stored rows; a group of several
+ * molecules puts them first (ascending) and the other rows after them (ascending),
+ * a single molecule keeps the ascending order of nolsm_plan_create, which is this
+ * call with one molecule per group.  Each molecule may appear once.  Limits per
+ * submatrix: 1,024 member molecules, n <= 8,192 (NOLSM_EINVAL). */
+nolsm_status nolsm_plan_create_groups(const nolsm_pattern *pattern_host, const int32_t *grp_ptr,
+                                      const int32_t *grp_mols, int32_t ngroups,
+                                      const nolsm_plan_options *options /*host, nullable*/,
+                                      nolsm_plan **plan /*host out*/);
+
+/* Performance-aware submatrix combination (Sec. IV-B, Eq. 9 and Eq. 10), host only.
+ * Starting from one group per molecule of mols[0..K-1], repeatedly combine the two
+ * groups with the largest gain cost(n_i) + cost(n_j) - cost(n_i + n_j - n_ij) among
+ * the pairs whose submatrices share a row (n_ij > 0: the functions of the shared
+ * rows), until no pair gains.  cost(n) = n^3 (criterion 9, the flops of the dense
+ * products) or n^3 / rate(n) (criterion 10, their predicted run time), with rate(n)
+ * interpolated linearly in the measured table (rate_n ascending, clamped at its
+ * ends).  Ties go to the pair whose smallest molecules, smaller first, come first.
+ * Pairs whose combined n would exceed max_n (> 0) are not combined.
+ * Output: ngroups_out groups in grp_ptr [K+1] / grp_mols [K] (host, caller
+ * allocated), each ascending, ordered by first molecule.
+ * NOLSM_EINVAL for bad arguments (criterion, table not ascending or not positive,
+ * molecules out of range or repeated). */
+typedef struct {
+  int32_t criterion;        /* 9 or 10 */
+  int32_t max_n;            /* 0 = no limit */
+  int32_t npoints;          /* rows of the rate table (criterion 10), >= 1 */
+  int32_t pad;
+  const double *rate_n;     /* host [npoints] dimensions, strictly ascending */
+  const double *rate;       /* host [npoints] throughput at those dimensions (> 0) */
+} nolsm_combine_options;
+
+nolsm_status nolsm_combine(const nolsm_pattern *pattern_host, const int32_t *mols /*host*/,
+                           int32_t K, const nolsm_combine_options *options /*host*/,
+                           int32_t *grp_ptr /*host out [K+1]*/, int32_t *grp_mols /*host out [K]*/,
+                           int32_t *ngroups_out /*host out*/);
+
 void nolsm_plan_destroy(nolsm_plan *plan);
 
 /* Device workspace bytes the plan needs: a 256-byte header shared by every plan
@@ -198,7 +246,25 @@ size_t nolsm_plan_table_bytes(const nolsm_plan *plan);
 nolsm_status nolsm_plan_bind(nolsm_plan *plan, void *tables, size_t table_bytes, void *workspace,
                              size_t bytes, hipStream_t stream);
 
-/* Layout of submatrix i (0 <= i < K) inside the bound workspace. */
+/* Bytes of the plan's own set-up buffer (256-byte aligned base required): M_k
+ * (FP32) and L^-1 (FP64) of every submatrix; 0 unless the plan was created with
+ * persist = 1. */
+size_t nolsm_plan_persist_bytes(const nolsm_plan *plan);
+
+/* nolsm_plan_bind for a plan created with persist = 1 (NOLSM_EINVAL otherwise, and
+ * nolsm_plan_bind refuses such a plan): `persist` (persist_bytes) holds this plan's
+ * set-up results and must not be shared with another plan; `workspace` may be.
+ * While the plan keeps the same table buffer and persist buffer, rebinding keeps
+ * its set-up (and the Gershgorin bounds of nolsm_features) current, so a later
+ * nolsm_sign_batched needs no new gather or set-up.  Binding with a different
+ * workspace or persist buffer than the last time re-uploads the descriptors and
+ * synchronises `stream` (not capturable); the same pair again does no device work. */
+nolsm_status nolsm_plan_bind_persist(nolsm_plan *plan, void *tables, size_t table_bytes,
+                                     void *workspace, size_t bytes, void *persist,
+                                     size_t persist_bytes, hipStream_t stream);
+
+/* Layout of submatrix i (0 <= i < K) inside the bound workspace (off_h and off_s
+ * inside the persist buffer for a plan created with persist = 1). */
 nolsm_status nolsm_plan_query(const nolsm_plan *plan, int32_t i, nolsm_sub_info *info /*host*/);
 
 /* Step 1 of the submatrix method for H0 and S (Sec. II; Eq. 8 builds both from the
@@ -242,7 +308,8 @@ nolsm_status nolsm_sign_batched(nolsm_plan *plan, double mu, const nolsm_schedul
                                 nolsm_stats *stats, hipStream_t stream);
 
 /* Step 3 (Sec. II): write molecule k's density columns into block column k of D
- * (same pattern and layout as H0, S), and record each column's contribution to
+ * (same pattern and layout as H0, S) -- every molecule of a combined submatrix from
+ * that submatrix -- and record the submatrix's own columns' contribution to
  * Tr(D H0) and Tr(D S) in stats[i].tr_dh / tr_ds.  Only block columns of planned
  * molecules are written. */
 nolsm_status nolsm_scatter_density(nolsm_plan *plan, const nolsm_pattern *pattern_dev,
@@ -319,6 +386,35 @@ typedef struct {
  * cleared by a call with reset != 0 (it starts undefined). */
 nolsm_status nolsm_plan_set_timing(nolsm_plan *plan, int enable);
 nolsm_status nolsm_plan_get_timings(nolsm_plan *plan, nolsm_timings *out /*host*/, int reset);
+
+/* Chemical-potential search (Sec. V-A: the runs iterate mu until the system is
+ * charge neutral).  Host-side bisection of the electron count N(mu) = Tr(D(mu) S)
+ * against n_target: the caller evaluates N at s.mu (nolsm_sign_batched and
+ * nolsm_scatter_density for every batch at that mu, then nolsm_energy) and passes
+ * it to nolsm_mu_search_update, until s.done != 0.  The bracket keeps N(lo) below
+ * n_target - tol and N(hi) above n_target + tol (the initial [mu_lo, mu_hi] is
+ * taken as such); each trial is the bracket's midpoint; the search ends at the
+ * first trial with |N - n_target| <= tol (done = 1, s.mu is that trial) or after
+ * max_iter trials (done = -1, s.mu is the last trial).  Every trial shares the
+ * set-up M_k = L^-1 H_k L^-T, since the argument of sign() is M_k - mu I. */
+typedef struct {
+  double n_target, tol;   /* electron count sought, accepted deviation           */
+  double lo, hi;          /* current bracket                                      */
+  double mu;              /* trial to evaluate next; the result once done != 0    */
+  double last_n;          /* N at the last evaluated trial                        */
+  int32_t iters;          /* trials evaluated                                     */
+  int32_t max_iter;       /* 1..1000                                              */
+  int32_t done;           /* 0 searching, 1 converged, -1 max_iter reached        */
+  int32_t pad;
+} nolsm_mu_search;
+
+/* NOLSM_EINVAL for a null pointer, non-finite values, mu_lo >= mu_hi, tol < 0 or
+ * max_iter outside 1..1000. */
+nolsm_status nolsm_mu_search_init(nolsm_mu_search *s /*host*/, double n_target, double mu_lo,
+                                  double mu_hi, double tol, int32_t max_iter);
+/* Fold N(s->mu) into the bracket and set the next trial.  NOLSM_EINVAL for a null
+ * pointer, a non-finite count or a search that has already ended. */
+nolsm_status nolsm_mu_search_update(nolsm_mu_search *s /*host*/, double n_at_mu);
 
 /* Synchronise `stream`, read the plan's device status words, and return
  * NOLSM_ENOTSPD / NOLSM_ENOCONV if any submatrix failed (else NOLSM_OK). */

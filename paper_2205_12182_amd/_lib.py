@@ -50,14 +50,14 @@ class Schedule(ctypes.Structure):
 class SubInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("npad", ctypes.c_int32), ("mol", ctypes.c_int32),
                 ("m", ctypes.c_int32), ("own_lo", ctypes.c_int32), ("nmem", ctypes.c_int32),
-                ("pad0", ctypes.c_int32), ("pad1", ctypes.c_int32), ("off_h", ctypes.c_int64),
+                ("ngrp", ctypes.c_int32), ("own_mem", ctypes.c_int32), ("off_h", ctypes.c_int64),
                 ("off_s", ctypes.c_int64), ("off_lo", ctypes.c_int64),
                 ("off_dcol", ctypes.c_int64)]
 
 
 class PlanOptions(ctypes.Structure):
     _fields_ = [("big_tile_min_npad", ctypes.c_int32), ("setup_products", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("persist", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 SETUP_SPLIT_FP16, SETUP_FP32 = 0, 1
@@ -71,6 +71,19 @@ class Timings(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CombineOptions(ctypes.Structure):
+    _fields_ = [("criterion", ctypes.c_int32), ("max_n", ctypes.c_int32),
+                ("npoints", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("rate_n", ctypes.c_void_p), ("rate", ctypes.c_void_p)]
+
+
+class MuSearch(ctypes.Structure):
+    _fields_ = [("n_target", ctypes.c_double), ("tol", ctypes.c_double),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("mu", ctypes.c_double),
+                ("last_n", ctypes.c_double), ("iters", ctypes.c_int32),
+                ("max_iter", ctypes.c_int32), ("done", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 # nolsm_stats as a numpy record (48 bytes)
@@ -97,10 +110,16 @@ def lib():
     sigs = {
         "nolsm_plan_create": (i32, [P(Pattern), vp, i32, P(vp)]),
         "nolsm_plan_create_ex": (i32, [P(Pattern), vp, i32, P(PlanOptions), P(vp)]),
+        "nolsm_plan_create_groups": (i32, [P(Pattern), vp, vp, i32, P(PlanOptions), P(vp)]),
+        "nolsm_combine": (i32, [P(Pattern), vp, i32, P(CombineOptions), vp, vp, P(i32)]),
         "nolsm_plan_destroy": (None, [vp]),
         "nolsm_plan_workspace_bytes": (sz, [vp]),
         "nolsm_plan_table_bytes": (sz, [vp]),
         "nolsm_plan_bind": (i32, [vp, vp, sz, vp, sz, vp]),
+        "nolsm_plan_bind_persist": (i32, [vp, vp, sz, vp, sz, vp, sz, vp]),
+        "nolsm_plan_persist_bytes": (sz, [vp]),
+        "nolsm_mu_search_init": (i32, [P(MuSearch), dbl, dbl, dbl, dbl, i32]),
+        "nolsm_mu_search_update": (i32, [P(MuSearch), dbl]),
         "nolsm_plan_query": (i32, [vp, i32, P(SubInfo)]),
         "nolsm_build_submatrices": (i32, [vp, P(Pattern), vp, vp, vp]),
         "nolsm_sign_batched": (i32, [vp, dbl, P(Schedule), vp, vp]),
@@ -129,8 +148,11 @@ def lib():
     return L
 
 
-EXPORTED = ("nolsm_plan_create", "nolsm_plan_create_ex", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
-            "nolsm_plan_table_bytes", "nolsm_plan_bind", "nolsm_plan_query", "nolsm_build_submatrices",
+EXPORTED = ("nolsm_plan_create", "nolsm_plan_create_ex", "nolsm_plan_create_groups",
+            "nolsm_combine", "nolsm_plan_destroy", "nolsm_plan_workspace_bytes",
+            "nolsm_plan_table_bytes", "nolsm_plan_bind", "nolsm_plan_bind_persist",
+            "nolsm_plan_persist_bytes", "nolsm_mu_search_init", "nolsm_mu_search_update",
+            "nolsm_plan_query", "nolsm_build_submatrices",
             "nolsm_sign_batched", "nolsm_scatter_density", "nolsm_energy", "nolsm_energy_noalloc", "nolsm_check",
             "nolsm_last_error", "nolsm_plan_set_timing", "nolsm_plan_get_timings",
             "nolsm_setup_batched", "nolsm_features", "nolsm_mlp_param_count",
@@ -213,21 +235,72 @@ def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=N
 # ----------------------------------------------------------------------------- entry points
 
 def nolsm_plan_create(host_pattern: HostPattern, mols, big_tile_min_npad=None,
-                      setup_products=None) -> ctypes.c_void_p:
-    """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy and
-    setup_products (optional) how M_k is formed (SETUP_SPLIT_FP16 or SETUP_FP32)."""
+                      setup_products=None, persist=False) -> ctypes.c_void_p:
+    """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy,
+    setup_products (optional) how M_k is formed (SETUP_SPLIT_FP16 or SETUP_FP32), and
+    persist keeps the set-up results in a buffer of the plan's own."""
     mols = np.ascontiguousarray(mols, dtype=np.int32)
     out = ctypes.c_void_p()
-    if big_tile_min_npad is None and setup_products is None:
+    if big_tile_min_npad is None and setup_products is None and not persist:
         _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                     int(mols.size), ctypes.byref(out)))
     else:
         opt = PlanOptions()
         opt.big_tile_min_npad = -1 if big_tile_min_npad is None else int(big_tile_min_npad)
         opt.setup_products = SETUP_SPLIT_FP16 if setup_products is None else int(setup_products)
+        opt.persist = 1 if persist else 0
         _ok(lib().nolsm_plan_create_ex(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                        int(mols.size), ctypes.byref(opt), ctypes.byref(out)))
     return out
+
+
+def _options(big_tile_min_npad, setup_products, persist):
+    opt = PlanOptions()
+    opt.big_tile_min_npad = -1 if big_tile_min_npad is None else int(big_tile_min_npad)
+    opt.setup_products = SETUP_SPLIT_FP16 if setup_products is None else int(setup_products)
+    opt.persist = 1 if persist else 0
+    return opt
+
+
+def nolsm_plan_create_groups(host_pattern: HostPattern, groups, big_tile_min_npad=None,
+                             setup_products=None, persist=False) -> ctypes.c_void_p:
+    """Plan one submatrix per group of molecules (lists of molecule indices)."""
+    ptr = np.zeros(len(groups) + 1, dtype=np.int32)
+    ptr[1:] = np.cumsum([len(g) for g in groups])
+    flat = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups])
+                                if groups else np.zeros(0, np.int32), dtype=np.int32)
+    out = ctypes.c_void_p()
+    opt = _options(big_tile_min_npad, setup_products, persist)
+    _ok(lib().nolsm_plan_create_groups(ctypes.byref(host_pattern.struct), ptr.ctypes.data,
+                                       flat.ctypes.data, int(len(groups)), ctypes.byref(opt),
+                                       ctypes.byref(out)))
+    return out
+
+
+def nolsm_combine(host_pattern: HostPattern, mols, criterion=9, table=None, max_n=0):
+    """Groups of molecules from the combination heuristic (Eq. 9, or Eq. 10 with the
+    rate table [(n, rate), ...]); a list of ascending molecule lists."""
+    mols = np.ascontiguousarray(mols, dtype=np.int32)
+    K = int(mols.size)
+    ptr = np.zeros(K + 1, dtype=np.int32)
+    flat = np.zeros(max(K, 1), dtype=np.int32)
+    ng = ctypes.c_int32()
+    opt = CombineOptions()
+    opt.criterion = int(criterion)
+    opt.max_n = int(max_n or 0)
+    keep = None
+    if table is not None:
+        tn = np.ascontiguousarray([float(a) for a, _ in table], dtype=np.float64)
+        tr = np.ascontiguousarray([float(b) for _, b in table], dtype=np.float64)
+        keep = (tn, tr)
+        opt.npoints = int(tn.size)
+        opt.rate_n = tn.ctypes.data
+        opt.rate = tr.ctypes.data
+    _ok(lib().nolsm_combine(ctypes.byref(host_pattern.struct), mols.ctypes.data, K,
+                            ctypes.byref(opt), ptr.ctypes.data, flat.ctypes.data,
+                            ctypes.byref(ng)))
+    del keep
+    return [flat[ptr[g]:ptr[g + 1]].tolist() for g in range(ng.value)]
 
 
 def nolsm_plan_destroy(plan):
@@ -246,6 +319,29 @@ def nolsm_plan_bind(plan, tables, workspace, stream=None):
     _ok(lib().nolsm_plan_bind(plan, _ptr(tables), tables.numel() * tables.element_size(),
                               _ptr(workspace), workspace.numel() * workspace.element_size(),
                               _stream(stream)))
+
+
+def nolsm_plan_persist_bytes(plan) -> int:
+    return int(lib().nolsm_plan_persist_bytes(plan))
+
+
+def nolsm_plan_bind_persist(plan, tables, workspace, persist, stream=None):
+    _ok(lib().nolsm_plan_bind_persist(plan, _ptr(tables), tables.numel() * tables.element_size(),
+                                      _ptr(workspace),
+                                      workspace.numel() * workspace.element_size(),
+                                      _ptr(persist), persist.numel() * persist.element_size(),
+                                      _stream(stream)))
+
+
+def nolsm_mu_search_init(n_target, mu_lo, mu_hi, tol=0.5, max_iter=40) -> MuSearch:
+    m = MuSearch()
+    _ok(lib().nolsm_mu_search_init(ctypes.byref(m), float(n_target), float(mu_lo), float(mu_hi),
+                                   float(tol), int(max_iter)))
+    return m
+
+
+def nolsm_mu_search_update(m: MuSearch, n_at_mu):
+    _ok(lib().nolsm_mu_search_update(ctypes.byref(m), float(n_at_mu)))
 
 
 def nolsm_plan_query(plan, i) -> SubInfo:

@@ -22,16 +22,21 @@ constexpr int ST = 128;            // sign-iteration output tile (ST x ST)
 constexpr int RESID_SHIFT = 40;    // fixed-point scale of the residual accumulator
 constexpr float RESID_CLAMP = 1.0e4f;
 constexpr int NPANEL = 8;         // n x m FP32 panel slots per submatrix
-constexpr int MAXM = 32;          // own columns per molecule handled by the panel kernels
+constexpr int MAXM = 32;          // own columns per panel-kernel workgroup (column chunk)
+constexpr int MAX_OWN = 8192;     // own columns of a submatrix (chunks of MAXM columns)
 constexpr int ENERGY_NOALLOC_MAXMOL = NOLSM_ENERGY_NOALLOC_MAXMOL;   // nolsm_energy_noalloc limit
 constexpr int MAX_DEVICES = 64;   // devices whose scratch address is cached
 
 enum Prec : int32_t { P_FP32 = 0, P_FP16 = 1, P_BF16 = 2 };
 
-// Per-submatrix description (device, read-only after bind).
+// Per-submatrix description (device, read-only after bind).  A submatrix serves the
+// block columns of ngrp molecules (one, or a combined group): members own_mem ..
+// own_mem + ngrp - 1 of its member list, whose functions are its own columns
+// own_lo .. own_lo + m - 1.
 struct SubDesc {
-  int32_t n, npad, mol, m;          // dimension, leading dimension, molecule, own columns
-  int32_t own_lo, nmem, mem_off, pad0;
+  int32_t n, npad, mol, m;          // dimension, leading dimension, first own molecule, own columns
+  int32_t own_lo, nmem, mem_off, ngrp;
+  int32_t own_mem, pad0;
   int64_t off_h;                    // bytes from workspace base: FP64 npad^2 H_k, then FP32 M_k
   int64_t off_s;                    // FP64 npad^2 (S_k -> L -> L^-1)
   int64_t off_lo;                   // 3 x (4 npad^2) bytes: sign-iteration buffers / FP64 scratch

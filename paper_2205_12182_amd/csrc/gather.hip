@@ -2,9 +2,9 @@
 // gather the dense principal submatrices T_k(H0), T_k(S) of every planned molecule.
 //
 // One workgroup per (submatrix, group of four member block columns b).  The member
-// list (ascending molecule index) goes to LDS once with a row -> member map; for
-// each b the stored blocks of block column J_b are read once, coalesced, and each
-// is matched to its member by a binary search in LDS.  The workgroup then streams the column-major block column
+// list goes to LDS once with a row -> member map and the members in ascending
+// molecule order; for each b the stored blocks of block column J_b are read once,
+// coalesced, and each is matched to its member by a binary search in LDS.  The workgroup then streams the column-major block column
 // into the dense column-major submatrix, four consecutive rows per thread: each
 // output column is a contiguous run, so writes are coalesced vector stores, and
 // each stored block is read contiguously.  The padding rows/columns (n..npad) are
@@ -27,7 +27,8 @@ template <bool SPLIT_H>
 __global__ __launch_bounds__(256) void gather_kernel(
     const SubDesc *__restrict__ desc, const int32_t *__restrict__ mem_mol,
     const int32_t *__restrict__ mem_loc, const int32_t *__restrict__ blk_dim,
-    const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowblk,
+    const int32_t *__restrict__ mem_srt, const int64_t *__restrict__ colptr,
+    const int32_t *__restrict__ rowblk,
     const int64_t *__restrict__ valoff, const double *__restrict__ H_val,
     const double *__restrict__ S_val, char *__restrict__ ws) {
   const SubDesc d = desc[blockIdx.y];
@@ -37,7 +38,8 @@ __global__ __launch_bounds__(256) void gather_kernel(
   const int b1 = b0 + GATHER_GROUP - 1 < nmem ? b0 + GATHER_GROUP - 1 : nmem;
   __shared__ int64_t s_t[GATHER_MAXMEM];        // value offset of block (J_a, J_b) or -1
   __shared__ int32_t s_loc[GATHER_MAXMEM + 1];  // first row of member a; s_loc[nmem] = n
-  __shared__ int32_t s_mol[GATHER_MAXMEM];      // molecule of member a (ascending)
+  __shared__ int32_t s_mol[GATHER_MAXMEM];      // molecules in ascending order ...
+  __shared__ int16_t s_pos[GATHER_MAXMEM];      // ... and their member indices
   __shared__ uint16_t s_rowmem[GATHER_MAXN];    // row -> member
   double *Hk = reinterpret_cast<double *>(ws + d.off_h);
   double *Sk = reinterpret_cast<double *>(ws + d.off_s);
@@ -48,7 +50,9 @@ __global__ __launch_bounds__(256) void gather_kernel(
     for (int a = threadIdx.x; a < nmem; a += blockDim.x) {
       const int Ja = mem_mol[d.mem_off + a];
       const int loc = mem_loc[d.mem_off + a], dim = blk_dim[Ja];
-      s_mol[a] = Ja;
+      const int q = mem_srt[d.mem_off + a];        // a-th smallest molecule's member index
+      s_mol[a] = mem_mol[d.mem_off + q];
+      s_pos[a] = (int16_t)q;
       s_loc[a] = loc;
       for (int r = 0; r < dim; ++r) s_rowmem[loc + r] = (uint16_t)a;
     }
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
         const int mid = (lo + hi) >> 1;
         if (s_mol[mid] < J) lo = mid + 1; else hi = mid;
       }
-      if (lo < nmem && s_mol[lo] == J) s_t[lo] = valoff[e];   // rows are distinct
+      if (lo < nmem && s_mol[lo] == J) s_t[s_pos[lo]] = valoff[e];   // rows are distinct
     }
     __syncthreads();
 
@@ -141,16 +145,17 @@ __global__ __launch_bounds__(256) void gather_kernel(
 }
 
 void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mol,
-                   const int32_t *mem_loc, const nolsm_pattern *pat, const double *H_val,
-                   const double *S_val, bool split_h, char *ws, hipStream_t stream) {
+                   const int32_t *mem_loc, const int32_t *mem_srt, const nolsm_pattern *pat,
+                   const double *H_val, const double *S_val, bool split_h, char *ws,
+                   hipStream_t stream) {
   dim3 grid((maxmem + GATHER_GROUP) / GATHER_GROUP, K);   // members 0..maxmem (padding)
   if (split_h)
     gather_kernel<true><<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim,
-                                                  pat->colptr, pat->rowblk, pat->valoff, H_val,
+                                                  mem_srt, pat->colptr, pat->rowblk, pat->valoff, H_val,
                                                   S_val, ws);
   else
     gather_kernel<false><<<grid, 256, 0, stream>>>(desc, mem_mol, mem_loc, pat->blk_dim,
-                                                   pat->colptr, pat->rowblk, pat->valoff, H_val,
+                                                   mem_srt, pat->colptr, pat->rowblk, pat->valoff, H_val,
                                                    S_val, ws);
 }
 

@@ -119,20 +119,24 @@ __global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restric
   const SubDesc d = desc[blockIdx.y];
   const SubState &s = st[blockIdx.y];
   if (s.status != 0 || s.prec == P_FP16 || blockIdx.x * PANEL_ROWS >= (unsigned)d.npad) return;
+  const int c0 = MAXM * blockIdx.z;              // this workgroup's chunk of own columns
+  if (c0 >= d.m) return;
+  const int mc = d.m - c0 < MAXM ? d.m - c0 : MAXM;
   __shared__ float sX[PANEL_K][PANEL_ROWS + 4];
   __shared__ float sP[PANEL_K][MAXM];
-  const float *P = panel_ptr(ws, d, qp);
-  const float *Q = panel_ptr(ws, d, qq);
-  float *O = panel_ptr(ws, d, qo);
+  const int64_t co = (int64_t)c0 * d.npad;
+  const float *P = panel_ptr(ws, d, qp) + co;
+  const float *Q = panel_ptr(ws, d, qq) + co;
+  float *O = panel_ptr(ws, d, qo) + co;
   const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
   if (s.prec == P_FP32)
-    panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, d.m, alpha, beta,
+    panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, mc, alpha, beta,
                           sX, sP);
   else if (s.prec == P_FP16)
-    panel_mul_body<_Float16>(reinterpret_cast<const _Float16 *>(xb), P, Q, O, d.npad, d.m, alpha,
+    panel_mul_body<_Float16>(reinterpret_cast<const _Float16 *>(xb), P, Q, O, d.npad, mc, alpha,
                              beta, sX, sP);
   else
-    panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, d.m, alpha,
+    panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, mc, alpha,
                            beta, sX, sP);
 }
 
@@ -159,7 +163,9 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
   const SubDesc d = desc[blockIdx.y];
   const SubState &s = st[blockIdx.y];
   if (s.status != 0 || s.prec != P_FP16) return;
-  const int ld = d.npad, m = d.m;
+  const int c0 = MAXM * blockIdx.z;              // this workgroup's chunk of own columns
+  if (c0 >= d.m) return;
+  const int ld = d.npad, m = d.m - c0 < MAXM ? d.m - c0 : MAXM;
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63, h = lane >> 5, c = lane & 31;
   const int i0 = blockIdx.x * PM_ROWS + 32 * PM_BLK * w;
   if (i0 >= ld) return;                                   // the whole wave
@@ -167,9 +173,10 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
   nb = nb > PM_BLK ? PM_BLK : nb;
   const _Float16 *X = reinterpret_cast<const _Float16 *>(ws + d.off_lo) +
                       (int64_t)s.cur * 2 * ld * ld;
-  const float *P = panel_ptr(ws, d, qp);
-  const float *Q = panel_ptr(ws, d, qq);
-  float *O = panel_ptr(ws, d, qo);
+  const int64_t co = (int64_t)c0 * ld;
+  const float *P = panel_ptr(ws, d, qp) + co;
+  const float *Q = panel_ptr(ws, d, qq) + co;
+  float *O = panel_ptr(ws, d, qo) + co;
   const bool live = c < m;
   const _Float16 *xr = X + (int64_t)(i0 + c) * ld + 8 * h;
   const float *pc = P + (int64_t)(live ? c : 0) * ld + 8 * h;
@@ -231,13 +238,16 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
                                                    int qv, int qw) {
   const SubDesc d = desc[blockIdx.y];
   if (st[blockIdx.y].status != 0) return;
-  const int ld = d.npad, m = d.m;
+  const int c0 = MAXM * blockIdx.z;              // this workgroup's chunk of own columns
+  if (c0 >= d.m) return;
+  const int ld = d.npad, m = d.m - c0 < MAXM ? d.m - c0 : MAXM;
   const int i0 = blockIdx.x * 64;
   if (i0 >= ld) return;
+  const int64_t co = (int64_t)c0 * ld;
   const double *Li = reinterpret_cast<const double *>(ws + d.off_s);
-  const float *V = panel_ptr(ws, d, qv);
-  const float *W = panel_ptr(ws, d, qw);
-  double *Dc = reinterpret_cast<double *>(ws + d.off_dcol);
+  const float *V = panel_ptr(ws, d, qv) + co;
+  const float *W = panel_ptr(ws, d, qw) + co;
+  double *Dc = reinterpret_cast<double *>(ws + d.off_dcol) + co;
   __shared__ double sL[64][65];     // sL[i][k] = Linv[k0 + k, i0 + i]
   __shared__ double sU[64][33];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -299,31 +309,54 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
   }
 }
 
-// Write block column `mol` of D and sum its contributions to Tr(DH), Tr(DS).
+// Write the block columns of the submatrix's own molecules into D and sum their
+// contributions to Tr(DH), Tr(DS).  For own molecule J, every stored block (I, J)
+// of D takes rows of member I and J's own columns of T_k(D); member I is found by a
+// binary search over the members in ascending molecule order (LDS).
+constexpr int SCATTER_MAXMEM = 1024;
+
 __global__ __launch_bounds__(256) void scatter_kernel(
     const SubDesc *__restrict__ desc, const SubState *__restrict__ st,
     const int32_t *__restrict__ mem_mol, const int32_t *__restrict__ mem_loc,
-    const int32_t *__restrict__ blk_dim, const int64_t *__restrict__ colptr,
+    const int32_t *__restrict__ mem_srt, const int32_t *__restrict__ blk_dim,
+    const int64_t *__restrict__ colptr, const int32_t *__restrict__ rowblk,
     const int64_t *__restrict__ valoff, double *__restrict__ D_val,
     const double *__restrict__ H_val, const double *__restrict__ S_val, const char *ws,
     nolsm_stats *__restrict__ stats) {
   const SubDesc d = desc[blockIdx.x];
   __shared__ double red[4];
+  __shared__ int32_t s_mol[SCATTER_MAXMEM];     // members in ascending molecule order
+  __shared__ int32_t s_loc[SCATTER_MAXMEM];     // their first rows in T_k
   const double *Dc = reinterpret_cast<const double *>(ws + d.off_dcol);
   const bool ok = st[blockIdx.x].status == 0;
+  for (int a = threadIdx.x; a < d.nmem; a += 256) {
+    const int q = mem_srt[d.mem_off + a];
+    s_mol[a] = mem_mol[d.mem_off + q];
+    s_loc[a] = mem_loc[d.mem_off + q];
+  }
+  __syncthreads();
   double eh = 0.0, es = 0.0;
-  const int64_t t0 = colptr[d.mol];
-  for (int a = 0; a < d.nmem; ++a) {
-    const int I = mem_mol[d.mem_off + a];
-    const int loc = mem_loc[d.mem_off + a];
-    const int dI = blk_dim[I];
-    const int64_t base = valoff[t0 + a];
-    for (int e = threadIdx.x; e < dI * d.m; e += 256) {
-      const int c = e / dI, r = e - c * dI;
-      const double v = ok ? Dc[(int64_t)c * d.npad + loc + r] : 0.0;
-      D_val[base + e] = v;
-      eh += v * H_val[base + e];
-      es += v * S_val[base + e];
+  for (int j = 0; j < d.ngrp; ++j) {
+    const int J = mem_mol[d.mem_off + d.own_mem + j];
+    const int col0 = mem_loc[d.mem_off + d.own_mem + j] - d.own_lo;   // J's first own column
+    const int dJ = blk_dim[J];
+    for (int64_t t = colptr[J]; t < colptr[J + 1]; ++t) {
+      const int I = rowblk[t];
+      int lo = 0, hi = d.nmem;                   // first member >= I (I is a member)
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_mol[mid] < I) lo = mid + 1; else hi = mid;
+      }
+      const int loc = s_loc[lo];
+      const int dI = blk_dim[I];
+      const int64_t base = valoff[t];
+      for (int e = threadIdx.x; e < dI * dJ; e += 256) {
+        const int c = e / dI, r = e - c * dI;
+        const double v = ok ? Dc[(int64_t)(col0 + c) * d.npad + loc + r] : 0.0;
+        D_val[base + e] = v;
+        eh += v * H_val[base + e];
+        es += v * S_val[base + e];
+      }
     }
   }
   eh = block_sum256(eh, red);
@@ -419,7 +452,7 @@ __global__ __launch_bounds__(256) void panel_axpby_kernel(const SubDesc *__restr
 struct PanelCtx {
   const SubDesc *desc;
   const SubState *st;
-  int K, max_npad;
+  int K, max_npad, nchunk;
   char *ws;
   hipStream_t s;
   unsigned used;
@@ -430,10 +463,10 @@ struct PanelCtx {
   }
   void release(int q) { used &= ~(1u << q); }
   int apply(int steps, int qin) {
-    const dim3 grid((max_npad + PANEL_ROWS - 1) / PANEL_ROWS, K);
+    const dim3 grid((max_npad + PANEL_ROWS - 1) / PANEL_ROWS, K, nchunk);
     if (steps == 0) {
       const int qo = alloc();
-      panel_mfma_kernel<<<dim3((max_npad + PM_ROWS - 1) / PM_ROWS, K), 256, 0, s>>>(
+      panel_mfma_kernel<<<dim3((max_npad + PM_ROWS - 1) / PM_ROWS, K, nchunk), 256, 0, s>>>(
           desc, st, ws, qin, qin, qo, 1.0f, 0.0f);
       panel_mul_kernel<<<grid, 256, 0, s>>>(desc, st, ws, qin, qin, qo, 1.0f, 0.0f);
       return qo;
@@ -449,19 +482,22 @@ struct PanelCtx {
 };
 
 void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
-                            char *ws, int panel_steps, hipStream_t s) {
-  PanelCtx c{desc, st, K, max_npad, ws, s, 1u};   // slot 0 holds V
+                            int max_m, char *ws, int panel_steps, hipStream_t s) {
+  const int nchunk = (max_m + MAXM - 1) / MAXM;   // own columns in chunks of MAXM
+  PanelCtx c{desc, st, K, max_npad, nchunk, ws, s, 1u};   // slot 0 holds V
   panel_v_kernel<<<dim3(64, K), 256, 0, s>>>(desc, st, ws, 0);
   const int qw = c.apply(panel_steps, 0);
-  dcol_kernel<<<dim3(max_npad / 64, K), 256, 0, s>>>(desc, st, ws, 0, qw);
+  dcol_kernel<<<dim3(max_npad / 64, K, nchunk), 256, 0, s>>>(desc, st, ws, 0, qw);
 }
 
-void launch_scatter(const SubDesc *desc, const SubState *st, int K, const int32_t *mem_mol,
-                    const int32_t *mem_loc, const nolsm_pattern *pat, double *D_val,
-                    const double *H_val, const double *S_val, const char *ws,
-                    nolsm_stats *stats, hipStream_t s) {
-  scatter_kernel<<<K, 256, 0, s>>>(desc, st, mem_mol, mem_loc, pat->blk_dim, pat->colptr,
-                                   pat->valoff, D_val, H_val, S_val, ws, stats);
+void launch_scatter(const SubDesc *desc, const SubState *st, int K, int maxmem,
+                    const int32_t *mem_mol, const int32_t *mem_loc, const int32_t *mem_srt,
+                    const nolsm_pattern *pat, double *D_val, const double *H_val,
+                    const double *S_val, const char *ws, nolsm_stats *stats, hipStream_t s) {
+  (void)maxmem;                  // plans keep at most SCATTER_MAXMEM members per submatrix
+  scatter_kernel<<<K, 256, 0, s>>>(desc, st, mem_mol, mem_loc, mem_srt, pat->blk_dim,
+                                   pat->colptr, pat->rowblk, pat->valoff, D_val, H_val, S_val,
+                                   ws, stats);
 }
 
 void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, const double *H_val,

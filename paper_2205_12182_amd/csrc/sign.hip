@@ -133,6 +133,14 @@ __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, in
   if (!s.active || s.prec != prec) return;
   s.cur = (s.cur + 2) % 3;
   if (fallback) ++s.iters_fb; else ++s.iters_lo;
+  if (s.extra_left == 0) {
+    // a tolerance phase reached its tolerance and this was the last of its extra
+    // iterations: stop now rather than after one more X^2, whose only use would be
+    // the stop decision already taken (the residual on record stays the last one
+    // measured, which met the tolerance)
+    s.active = 0;
+    return;
+  }
   if (use_lower && s.lower < 1.0) {
     // new lower bound: the smaller image of the two interval ends
     const double l = s.lower, a = ns_alpha(l);

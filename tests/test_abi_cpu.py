@@ -88,7 +88,7 @@ def test_plan_options_tile_policy():
     assert sizes[0] == sizes[2] and sizes[1] != sizes[0]
     opt = L.PlanOptions()
     opt.big_tile_min_npad = 0
-    opt.reserved[3] = 1
+    opt.reserved[3] = 1    # reserved has 5 entries
     out = ctypes.c_void_p()
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
@@ -167,3 +167,159 @@ def test_sign_rejects_bad_schedule(case):
         assert "not bound" in L.nolsm_last_error()
     finally:
         L.nolsm_plan_destroy(plan)
+
+
+def test_persist_layout_and_bind_checks():
+    """A persist plan moves M_k and L^-1 (4 + 8 npad^2 bytes per submatrix) out of the
+    workspace into its own buffer; each bind entry point refuses the other kind of
+    plan, and short or misaligned persist buffers, before any device work."""
+    inst = get_config("c1")
+    hp = L.HostPattern(inst)
+    mols = np.arange(inst.nmol, dtype=np.int32)
+    npad = (inst.submatrix_dims() + 63) // 64 * 64
+    n2 = int((npad.astype(np.int64) ** 2).sum())
+    plain = L.nolsm_plan_create(hp, mols)
+    per = L.nolsm_plan_create(hp, mols, persist=True)
+    try:
+        assert L.nolsm_plan_persist_bytes(plain) == 0
+        pb = L.nolsm_plan_persist_bytes(per)
+        assert pb >= 12 * n2
+        assert L.nolsm_plan_workspace_bytes(plain) - L.nolsm_plan_workspace_bytes(per) >= 12 * n2
+        tb, wb = L.nolsm_plan_table_bytes(per), L.nolsm_plan_workspace_bytes(per)
+        ft, fw, fp = ctypes.c_void_p(1 << 20), ctypes.c_void_p(1 << 32), ctypes.c_void_p(1 << 36)
+        lib = L.lib()
+        assert lib.nolsm_plan_bind(per, ft, tb, fw, wb, None) == L.EINVAL
+        assert "nolsm_plan_bind_persist" in L.nolsm_last_error()
+        assert lib.nolsm_plan_bind_persist(plain, ft, tb, fw, wb, fp, pb, None) == L.EINVAL
+        assert lib.nolsm_plan_bind_persist(per, ft, tb, fw, wb, None, pb, None) == L.EINVAL
+        assert lib.nolsm_plan_bind_persist(per, ft, tb, fw, wb, fp, pb - 1, None) == L.EWORKSPACE
+        assert "persist buffer" in L.nolsm_last_error()
+        assert lib.nolsm_plan_bind_persist(per, ft, tb, fw, wb, ctypes.c_void_p((1 << 36) + 8),
+                                           pb, None) == L.EWORKSPACE
+        opt = L.PlanOptions()
+        opt.big_tile_min_npad = -1
+        opt.persist = 2
+        out = ctypes.c_void_p()
+        rc = lib.nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
+                                      ctypes.byref(opt), ctypes.byref(out))
+        assert rc == L.EINVAL and "persist" in L.nolsm_last_error()
+    finally:
+        L.nolsm_plan_destroy(plain)
+        L.nolsm_plan_destroy(per)
+
+
+LEVELS = np.array([-1.5, -0.2, -0.01, 0.3, 0.7, 2.0])
+
+
+def _c_bisection(count, n_target, lo, hi, tol, max_iter):
+    m = L.nolsm_mu_search_init(n_target, lo, hi, tol, max_iter)
+    hist = []
+    while m.done == 0:
+        n = count(m.mu)
+        hist.append((m.mu, n))
+        L.nolsm_mu_search_update(m, n)
+    return m, hist
+
+
+def test_mu_search_state_machine_hand_sequence():
+    """The library's bisection (host code) on N(mu) = #{h_i < mu}: the trials worked
+    out by hand for target 3, tolerance 0.5, bracket [-4, 3]."""
+    m, hist = _c_bisection(lambda mu: float(np.sum(LEVELS < mu)), 3, -4.0, 3.0, 0.5, 40)
+    assert m.done == 1 and m.iters == 5 and m.mu == 0.15625
+    assert [h[0] for h in hist] == [-0.5, 1.25, 0.375, -0.0625, 0.15625]
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_mu_search_state_machine_matches_oracle_bisection(seed):
+    """Same trials as the oracle's bisection on random staircase counts (some with a
+    target between two steps, where the search runs out of iterations)."""
+    from oracle import nolsm_oracle as O
+    rng = np.random.default_rng(seed)
+    lev = np.sort(rng.uniform(-2, 2, 40))
+    w = rng.uniform(0.2, 1.3, 40)
+
+    def count(mu):
+        return float(w[lev < mu].sum())
+    target = float(rng.uniform(2, 30))
+    tol = float(rng.choice([0.5, 0.05, 0.0]))
+    mo, ho, ok = O.mu_bisection(count, target, -2.5, 2.5, tol, 25)
+    m, hc = _c_bisection(count, target, -2.5, 2.5, tol, 25)
+    assert [h[0] for h in hc] == [h[0] for h in ho]
+    assert m.mu == mo and (m.done == 1) == ok and m.iters == len(ho)
+
+
+def test_mu_search_rejects_bad_arguments():
+    lib = L.lib()
+    m = L.MuSearch()
+    assert lib.nolsm_mu_search_init(ctypes.byref(m), 1.0, 1.0, 0.0, 0.5, 10) == L.EINVAL
+    assert lib.nolsm_mu_search_init(ctypes.byref(m), 1.0, -1.0, 1.0, -0.5, 10) == L.EINVAL
+    assert lib.nolsm_mu_search_init(ctypes.byref(m), float("nan"), -1.0, 1.0, 0.5, 10) == L.EINVAL
+    assert lib.nolsm_mu_search_init(ctypes.byref(m), 1.0, -1.0, 1.0, 0.5, 0) == L.EINVAL
+    assert lib.nolsm_mu_search_init(ctypes.byref(m), 1.0, -1.0, 1.0, 0.5, 1) == L.OK
+    assert lib.nolsm_mu_search_update(ctypes.byref(m), float("inf")) == L.EINVAL
+    assert lib.nolsm_mu_search_update(ctypes.byref(m), 1.2) == L.OK and m.done == 1
+    assert lib.nolsm_mu_search_update(ctypes.byref(m), 1.2) == L.EINVAL
+    assert "ended" in L.nolsm_last_error()
+
+
+RATE_TABLE = [(341.0, 150.0), (603.0, 420.0), (1243.0, 900.0), (2404.0, 1500.0), (3190.0, 1700.0)]
+
+
+@pytest.mark.parametrize("name,criterion,table,max_n", [
+    ("t_23", 9, None, 0), ("t_sweep", 9, None, 0), ("t_sweep", 10, RATE_TABLE, 0),
+    ("t_sweep", 10, RATE_TABLE, 1200), ("c1", 10, RATE_TABLE, 0)])
+def test_combine_matches_oracle(name, criterion, table, max_n):
+    """The library's combination (C++, heap of candidate pairs) forms the same groups
+    as the oracle's greedy scan, bit for bit (integer work; Eq. 10's gains are
+    evaluated in the same double arithmetic on both sides)."""
+    from oracle import nolsm_oracle as O
+    inst = get_config(name)
+    hp = L.HostPattern(inst)
+    mols = np.arange(inst.nmol, dtype=np.int32)
+    got = L.nolsm_combine(hp, mols, criterion, table, max_n)
+    want = O.combine_groups(inst, mols, criterion, table, max_n or None)
+    assert got == want
+    if name == "t_sweep":
+        assert len(got) < inst.nmol
+
+
+def test_combine_subset_and_errors():
+    from oracle import nolsm_oracle as O
+    inst = get_config("t_sweep")
+    hp = L.HostPattern(inst)
+    mols = np.arange(0, inst.nmol, 3, dtype=np.int32)
+    assert L.nolsm_combine(hp, mols, 9) == O.combine_groups(inst, mols, 9)
+    with pytest.raises(L.NolsmError):
+        L.nolsm_combine(hp, mols, 11)
+    with pytest.raises(L.NolsmError):
+        L.nolsm_combine(hp, np.array([1, 1], np.int32), 9)
+    with pytest.raises(L.NolsmError):
+        L.nolsm_combine(hp, mols, 10, [(5.0, 1.0), (4.0, 2.0)])     # not ascending
+
+
+def test_plan_groups_layout_and_checks():
+    """A combined submatrix spans the union of its molecules' rows; its own columns
+    are the group's functions, ahead of the other rows."""
+    from oracle import nolsm_oracle as O
+    inst = get_config("t_sweep")
+    hp = L.HostPattern(inst)
+    groups = L.nolsm_combine(hp, np.arange(inst.nmol, dtype=np.int32), 9)
+    big = [g for g in groups if len(g) > 1][:5] + [[k] for k in range(3)]
+    plan = L.nolsm_plan_create_groups(hp, big)
+    try:
+        for i, g in enumerate(big):
+            info = L.nolsm_plan_query(plan, i)
+            rows = O.submatrix_rows(inst, g)
+            assert info.ngrp == len(g) and info.mol == min(g)
+            assert info.n == int(inst.blk_dim[rows].sum()) and info.nmem == rows.size
+            assert info.m == int(inst.blk_dim[g].sum())
+            if len(g) > 1:
+                assert info.own_mem == 0 and info.own_lo == 0
+            else:
+                assert info.own_mem == int(np.searchsorted(rows, g[0]))
+    finally:
+        L.nolsm_plan_destroy(plan)
+    with pytest.raises(L.NolsmError):
+        L.nolsm_plan_create_groups(hp, [[0, 1], [1, 2]])             # molecule 1 twice
+    with pytest.raises(L.NolsmError):
+        L.nolsm_plan_create_groups(hp, [[0], []])                    # empty group
