@@ -2,7 +2,9 @@
 
 The runner owns device copies of H0, S and D, the device pattern, and one plan
 per batch of molecules.  All batches share one workspace (sized for the largest
-batch) and are bound in turn; nothing here computes on the data.
+batch) and are bound in turn; with persist=True each batch also keeps its set-up
+(M_k, L^-1) in a buffer of its own, so that several runs at different chemical
+potentials gather and set up every batch once.  Nothing here computes on the data.
 """
 from __future__ import annotations
 
@@ -59,7 +61,10 @@ def tuned_tile_policy():
 
 class Runner:
     def __init__(self, inst, batch: int | None = None, mols=None, device="cuda",
-                 big_tile_min_npad="tuned", setup_products=None):
+                 big_tile_min_npad="tuned", setup_products=None, persist=False, groups=None):
+        """groups: lists of molecules that share one submatrix each (combined
+        submatrices, e.g. from nolsm_combine); then `batch` counts submatrices and
+        the stats hold one record per group, in the order of `groups`."""
         if not torch.cuda.is_available():
             raise RuntimeError("the NOLSM path runs on the GPU only")
         L.lib()
@@ -70,18 +75,37 @@ class Runner:
         self.D = torch.zeros_like(self.H)
         self.hpat = L.HostPattern(inst)
         self.dpat = L.DevicePattern(inst, device)
-        mols = np.arange(inst.nmol, dtype=np.int32) if mols is None else np.asarray(mols, np.int32)
+        if groups is not None:
+            groups = [list(map(int, g)) for g in groups]
+            self.groups = groups
+            mols = np.asarray([k for g in groups for k in g], dtype=np.int32)
+            units = groups
+        else:
+            mols = (np.arange(inst.nmol, dtype=np.int32) if mols is None
+                    else np.asarray(mols, np.int32))
+            self.groups = None
+            units = mols
         self.mols = mols
-        batch = len(mols) if batch is None else batch
-        self.batches = [mols[i:i + batch] for i in range(0, len(mols), batch)]
+        batch = len(units) if batch is None else batch
+        self.batches = [units[i:i + batch] for i in range(0, len(units), batch)]
         if big_tile_min_npad == "tuned":
             big_tile_min_npad = tuned_tile_policy()
         self.big_tile_min_npad = big_tile_min_npad
         self.setup_products = setup_products
-        self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad, setup_products)
-                      for b in self.batches]
+        self.persist = bool(persist)
+        if self.groups is not None:
+            self.plans = [L.nolsm_plan_create_groups(self.hpat, b, big_tile_min_npad,
+                                                     setup_products, persist=self.persist)
+                          for b in self.batches]
+        else:
+            self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad, setup_products,
+                                              persist=self.persist)
+                          for b in self.batches]
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
         self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        self.persist_bufs = ([torch.empty(max(L.nolsm_plan_persist_bytes(p), 256),
+                                          dtype=torch.uint8, device=device)
+                              for p in self.plans] if self.persist else None)
         self.tables = [torch.empty(L.nolsm_plan_table_bytes(p), dtype=torch.uint8, device=device)
                        for p in self.plans]
         self.stats = [torch.zeros(len(b) * L.STATS_DTYPE.itemsize, dtype=torch.uint8,
@@ -102,19 +126,30 @@ class Runner:
 
     def _bind(self, i):
         if self.bound != i:
-            L.nolsm_plan_bind(self.plans[i], self.tables[i], self.workspace)
+            if self.persist:
+                L.nolsm_plan_bind_persist(self.plans[i], self.tables[i], self.workspace,
+                                          self.persist_bufs[i])
+            else:
+                L.nolsm_plan_bind(self.plans[i], self.tables[i], self.workspace)
             self.bound = i
 
-    def run_batch(self, i, mu, sched, predictor=None, lower_factor=0.5):
+    @property
+    def keeps_setup(self):
+        """Whether every batch's set-up survives the other batches' runs."""
+        return self.persist or len(self.plans) == 1
+
+    def run_batch(self, i, mu, sched, predictor=None, lower_factor=0.5, regather=True):
         """Gather, sign iteration and write-back for batch i.
 
         predictor: a learn.ScheduleMLP; its prediction of log10 l_k from the batch's
         nolsm_features drives the scaled iteration (lower_factor is the safety
-        factor applied to l_k).
+        factor applied to l_k).  regather=False reuses the batch's gather and set-up
+        from its last run (only where they survive: keeps_setup).
         """
         self._bind(i)
         p = self.plans[i]
-        L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
+        if regather or not self.keeps_setup:
+            L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
         if predictor is not None:
             K = len(self.batches[i])
             if self._feat is None or self._feat.shape[0] < K:
@@ -130,12 +165,37 @@ class Runner:
         L.nolsm_sign_batched(p, mu, sched, self.stats[i])
         L.nolsm_scatter_density(p, self.dpat, self.D, self.H, self.S, self.stats[i])
 
-    def run(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5):
+    def run(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5,
+            regather=True):
         mu = self.inst.mu if mu is None else mu
         for i in range(len(self.plans)):
-            self.run_batch(i, mu, sched, predictor, lower_factor)
+            self.run_batch(i, mu, sched, predictor, lower_factor, regather)
         if energy:
             L.nolsm_energy(self.dpat, self.D, self.H, self.S, self.col_traces, self.out2)
+
+    def mu_search(self, n_target, mu_lo, mu_hi, tol=0.5, max_iter=40, sched=None,
+                  predictor=None, lower_factor=0.5, on_trial=None):
+        """Chemical potential with Tr(D S) = n_target (nolsm_mu_search_* bisection).
+
+        Every trial runs the whole instance at the trial mu; the gather and set-up
+        run at the first trial only when every batch keeps its set-up (persist or a
+        single batch).  on_trial(t, mu, N, E) is called after each trial.
+        Returns the search record, the trial history [(mu, Tr(DS), Tr(DH))] and
+        whether it converged; D, out2 and the stats hold the result at the final mu.
+        """
+        m = L.nolsm_mu_search_init(n_target, mu_lo, mu_hi, tol, max_iter)
+        hist = []
+        while m.done == 0:
+            mu = m.mu
+            self.run(mu, sched, True, predictor, lower_factor, regather=not hist)
+            e, ne = self.energy_host()
+            hist.append((mu, ne, e))
+            if on_trial is not None:
+                on_trial(len(hist), mu, ne, e)
+            L.nolsm_mu_search_update(m, ne)
+        if m.mu != hist[-1][0]:      # cannot happen: the result is the last trial
+            raise RuntimeError("mu search ended away from its last trial")
+        return m, hist
 
     def capture(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5):
         """Record one whole step (every batch in turn, then the energy) as a HIP graph.
@@ -159,9 +219,16 @@ class Runner:
         return graph
 
     def check(self):
-        """Status of every batch (after the last run): first failing code or OK."""
-        codes = [L.nolsm_check(p) for p in self.plans[-1:]]
-        return max(codes)
+        """Status of every batch (after the last run): the first failing batch's code
+        (self.last_check_message names the batch and the failure) or OK."""
+        first = L.OK
+        msg = None
+        for i, p in enumerate(self.plans):
+            code = L.nolsm_check(p)
+            if code != L.OK and first == L.OK:
+                first, msg = code, f"batch {i}: {L.nolsm_last_error()}"
+        self.last_check_message = msg
+        return first
 
     def stats_host(self, i=None):
         torch.cuda.synchronize()

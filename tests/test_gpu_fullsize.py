@@ -6,8 +6,9 @@ configuration bench.py times (batches of 1,024 submatrices sharing one workspace
 learned schedule when trained weights are committed).  Every submatrix must finish
 without error and sampled molecules from every batch must match the FP64 oracle to
 the accuracy target: every written density element within 1e-3 and the energy of
-the sampled molecules within 1e-5 Ha/atom.
+every sampled molecule (its Tr(D H) columns over its atoms) within 1e-5 Ha/atom.
 """
+import math
 import os
 
 import numpy as np
@@ -19,10 +20,14 @@ from paper_2205_12182_amd import learn
 from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, learned_schedule
 from workloads import get_config
 from workloads.water import water_box
+from tests.helpers import golden_energies
 
 pytestmark = pytest.mark.gpu
 
 D_TOL, E_TOL = 1e-3, 1e-5
+# A single molecule's columns carry first-order FP16 rounding that the system's
+# energy sums away; the per-molecule figure is reported and bounded at 1e-4.
+SINGLE_E_TOL = 1e-4
 WEIGHTS = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
 
 
@@ -40,28 +45,26 @@ def test_c2_full_size_sampled_parity(gpu_ok):
     assert (st["status"] == 0).all()
     D = r.D.cpu().numpy()
     picks = [0, 700, 1024, 1800, 2048, 2900, 3072, 4095]     # two per batch
-    dmax, de, atoms = 0.0, 0.0, 0
-    for k in picks:
-        ref = O.submatrix_result(inst, k)
-        got = np.zeros_like(ref["D_cols"])
-        for a, I in enumerate(ref["members"]):
-            t = int(inst.colptr[k]) + a
-            dI, m = int(inst.blk_dim[I]), int(inst.blk_dim[k])
-            got[ref["offs"][a]:ref["offs"][a + 1], :] = \
-                D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
-        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
-        de += float(st["tr_dh"][k]) - ref["tr_dh"]
-        atoms += int(inst.atoms[k])
-    print(f"[case] c2 vs oracle: dD {dmax:.2e} dE/atom {abs(de) / atoms:.2e} "
-          f"(iterations {st['iters_lo'].mean():.2f}, restarts {int(st['fell_back'].sum())})",
-          flush=True)
-    assert dmax <= D_TOL and abs(de) / atoms <= E_TOL
+    dmax, de = sampled_errors(inst, D, st, picks, {k: k for k in picks})
+    # the whole system against the oracle's energies of all 4,096 molecules
+    gold = golden_energies("c2", inst)
+    e, ne = r.energy_host()
+    de_sys = abs(e - math.fsum(gold["tr_dh"].tolist())) / inst.natoms
+    dn_sys = abs(ne - math.fsum(gold["tr_ds"].tolist()))
+    de_each = np.abs(st["tr_dh"] - gold["tr_dh"]) / inst.atoms
+    print(f"[case] c2 vs oracle: dD {dmax:.2e} max single-molecule dE/atom {de:.2e} (sampled), "
+          f"system dE/atom {de_sys:.2e}, dN {dn_sys:.2e}, largest molecule dE/atom over all "
+          f"{inst.nmol} {de_each.max():.2e} (iterations {st['iters_lo'].mean():.2f}, restarts "
+          f"{int(st['fell_back'].sum())})", flush=True)
+    assert dmax <= D_TOL and de <= E_TOL
+    assert de_sys <= E_TOL and dn_sys <= 1e-2 and de_each.max() <= SINGLE_E_TOL
 
 
 def sampled_errors(inst, D, st, picks, index):
     """Max |D - D_oracle| over the written columns of molecules `picks` and the
-    summed Tr(D_k H) difference per atom; st[index[k]] is molecule k's record."""
-    dmax, de, atoms = 0.0, 0.0, 0
+    largest single-molecule |Tr(D_k H) difference| / atoms_k (no cancellation
+    between molecules); st[index[k]] is molecule k's record."""
+    dmax, de = 0.0, 0.0
     for k in picks:
         ref = O.submatrix_result(inst, k)
         got = np.zeros_like(ref["D_cols"])
@@ -71,9 +74,8 @@ def sampled_errors(inst, D, st, picks, index):
             got[ref["offs"][a]:ref["offs"][a + 1], :] = \
                 D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
-        de += float(st["tr_dh"][index[k]]) - ref["tr_dh"]
-        atoms += int(inst.atoms[k])
-    return dmax, abs(de) / atoms
+        de = max(de, abs(float(st["tr_dh"][index[k]]) - ref["tr_dh"]) / int(inst.atoms[k]))
+    return dmax, de
 
 
 def test_near_maximum_submatrices(gpu_ok):

@@ -357,3 +357,40 @@ def test_empty_plan(gpu_ok):
         assert bool((D == 7.0).all())                  # nothing written
     finally:
         L.nolsm_plan_destroy(plan)
+
+
+@pytest.mark.parametrize("which", ["H", "S"])
+def test_nan_input_is_reported(gpu_ok, which):
+    """A NaN planted in one stored element (a diagonal block of molecule 3): every
+    submatrix that contains molecule 3 is reported (ENOCONV when the NaN is in H0:
+    the residual test and the FP32 restart both fail; ENOTSPD when it is in S: the
+    Cholesky pivot is not positive), in every batch (Runner.check folds them all),
+    and every other submatrix gives exactly the result of the clean input."""
+    inst = get_config("c1")
+    clean = Runner(inst, batch=12)
+    clean.run(sched=default_mixed_schedule())
+    vals = (inst.H_val if which == "H" else inst.S_val).copy()
+    t = int(inst.colptr[3]) + int(np.searchsorted(inst.members(3), 3))
+    vals[int(inst.valoff[t]) + 1] = np.nan           # element (1, 0) of block (3, 3)
+    bad_inst = get_config("c1")
+    if which == "H":
+        bad_inst.H_val = vals
+    else:
+        bad_inst.S_val = vals
+    r = Runner(bad_inst, batch=12)                    # three batches
+    r.run(sched=default_mixed_schedule())
+    code = r.check()
+    want = L.ENOCONV if which == "H" else L.ENOTSPD
+    print_case(f"nan in {which}: check {code}, {r.last_check_message}")
+    assert code == want
+    st, st0 = r.stats_host(), clean.stats_host()
+    hit = np.array([3 in inst.members(k) for k in range(inst.nmol)])
+    assert np.array_equal(st["status"] == want, hit)
+    assert (st["status"][~hit] == 0).all()
+    # clean submatrices are unaffected: their written block columns match bit for bit
+    D, D0 = r.D.cpu().numpy(), clean.D.cpu().numpy()
+    for k in np.nonzero(~hit)[0]:
+        lo, hi = int(inst.valoff[inst.colptr[k]]), int(inst.valoff[inst.colptr[k + 1] - 1])
+        hi += int(inst.blk_dim[inst.rowblk[inst.colptr[k + 1] - 1]]) * int(inst.blk_dim[k])
+        assert np.array_equal(D[lo:hi], D0[lo:hi]), k
+    assert np.array_equal(st["tr_dh"][~hit], st0["tr_dh"][~hit])
