@@ -176,29 +176,37 @@ def pick_molecules(nmol: int, count: int, seed: int, salt: int = 0x5EED) -> np.n
     return np.sort(rng.choice(nmol, count, replace=False)).astype(np.int32)
 
 
-def collect(inst, mols, tol: float = 1e-3, extra: int = 2):
+def collect(inst, mols, tol: float = 1e-3, extra: int = 2, mus=None):
     """Descriptors and labels for the submatrices of `mols` (one batch on the GPU).
 
     The label is log10 of the smallest starting eigenvalue that the plain FP32
     Newton-Schulz iteration (Gershgorin scale, run to ||X^2 - I||_F <= tol plus
     `extra` steps) would bring to tolerance in the number of steps it took.
-    Returns (features [K, NFEAT] float64, labels [K], plain iterations [K], ok [K]).
+    mus: chemical potentials to collect at (default: the instance's mu); the set-up
+    is shared, and the rows for each mu follow each other.
+    Returns (features [K m, NFEAT] float64, labels, plain iterations, ok, mu per row).
     """
     from .runner import Runner, plain_fp32_schedule
+    mus = [inst.mu] if mus is None else list(mus)
     r = Runner(inst, mols=mols)
     L.nolsm_build_submatrices(r.plans[0], r.dpat, r.H, r.S)
-    feat = features(r, 0, inst.mu).cpu().numpy().astype(np.float64)
-    r.run(sched=plain_fp32_schedule(tol=tol, extra=extra), energy=False)
-    st = r.stats_host()
-    ok = (st["status"] == 0) & (st["fell_back"] == 0)
-    lab = labels_from_plain_run(st["iters_lo"], extra, tol)
+    out = []
+    for mu in mus:
+        feat = features(r, 0, mu).cpu().numpy().astype(np.float64)
+        r.run(mu=mu, sched=plain_fp32_schedule(tol=tol, extra=extra), energy=False,
+              regather=False)
+        st = r.stats_host()
+        ok = (st["status"] == 0) & (st["fell_back"] == 0)
+        lab = labels_from_plain_run(st["iters_lo"], extra, tol)
+        out.append((feat, lab, st["iters_lo"].astype(np.int32), ok, np.full(len(lab), mu)))
     del r
-    return feat, lab, st["iters_lo"].astype(np.int32), ok
+    return tuple(np.concatenate([o[i] for o in out]) for i in range(5))
 
 
-def compare_schedules(inst, mols, model: "ScheduleMLP", lower_factor: float = 0.5):
+def compare_schedules(inst, mols, model: "ScheduleMLP", lower_factor: float = 0.5, mu=None):
     """Plain FP32, default mixed and learned mixed on one batch of `mols`.
 
+    mu: the chemical potential (default: the instance's).
     Returns a dict per schedule: mean low-precision and fallback iterations, sign
     and GEMM time (HIP events), paper-convention sign-phase TFLOP/s, fallbacks, and
     for the mixed forms the largest density difference, the energy difference per
@@ -213,10 +221,11 @@ def compare_schedules(inst, mols, model: "ScheduleMLP", lower_factor: float = 0.
     for name, sched, pred in (("plain_fp32", plain_fp32_schedule(), None),
                               ("mixed_default", default_mixed_schedule(), None),
                               ("mixed_learned", learned_schedule(), model)):
-        r.run(sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)  # warm-up
+        r.run(mu=mu, sched=sched, energy=False, predictor=pred,
+              lower_factor=lower_factor)                                            # warm-up
         L.nolsm_plan_get_timings(p, reset=True)
         L.nolsm_plan_set_timing(p, True)
-        r.run(sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)
+        r.run(mu=mu, sched=sched, energy=False, predictor=pred, lower_factor=lower_factor)
         torch.cuda.synchronize()
         tm = L.nolsm_plan_get_timings(p, reset=True).as_dict()
         L.nolsm_plan_set_timing(p, False)

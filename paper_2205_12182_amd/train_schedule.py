@@ -14,7 +14,9 @@ Further training geometries (--water-seeds): 2,048-molecule water boxes built li
 
 Training data: for `per-seed` seeded molecules of each training geometry, the
 descriptors (nolsm_features) and the plain FP32 iteration count turned into a
-lower-bound label (learn.collect).  The network is trained on the GPU with the
+lower-bound label (learn.collect), at mu = 0 and at `mus-per-seed` further chemical
+potentials drawn per geometry from --mu-range (a chemical-potential search visits
+such values, and the descriptors of M - mu I change with mu).  The network is trained on the GPU with the
 library's forward / backward / Adam kernels.  Evaluation: on `eval-per-seed`
 molecules of each held-out geometry, plain FP32, the default mixed schedule and
 the learned mixed schedule are run on the same submatrices, and iterations, time,
@@ -70,16 +72,23 @@ def _range(s: str):
 
 # ----------------------------------------------------------------- worker tasks
 
-def _collect_task(seed, per_seed, tol, extra, kind="slab"):
+def sample_mus(seed: int, count: int, lo: float, hi: float, salt: int = 0x3A5C) -> list:
+    """mu = 0 and `count` chemical potentials drawn uniformly from [lo, hi] per seed."""
+    rng = np.random.default_rng([salt, seed])
+    return [0.0] + [round(float(x), 4) for x in rng.uniform(lo, hi, count)]
+
+
+def _collect_task(seed, per_seed, tol, extra, kind="slab", mus=(0.0,)):
     from . import learn
     t0 = time.perf_counter()
     inst = build(kind, seed)
     t1 = time.perf_counter()
     mols = learn.pick_molecules(inst.nmol, per_seed, seed)
-    feat, lab, iters, ok = learn.collect(inst, mols, tol=tol, extra=extra)
+    feat, lab, iters, ok, mu = learn.collect(inst, mols, tol=tol, extra=extra, mus=mus)
     dims = inst.submatrix_dims()[mols]
     return {"seed": seed, "kind": kind, "mols": mols, "n": dims, "feat": feat, "label": lab,
-            "iters": iters, "ok": ok, "t_build": t1 - t0, "t_gpu": time.perf_counter() - t1}
+            "iters": iters, "ok": ok, "mu": mu, "t_build": t1 - t0,
+            "t_gpu": time.perf_counter() - t1}
 
 
 def _train_task(x, t, steps, lr, seed):
@@ -93,14 +102,15 @@ def _train_task(x, t, steps, lr, seed):
     return {"params": m.params.cpu().numpy(), "loss": hist, "t_train": dt, "pred": pred}
 
 
-def _eval_task(seed, per_seed, params, lower_factor, kind="slab"):
+def _eval_task(seed, per_seed, params, lower_factor, kind="slab", mu=0.0):
     from . import learn
     inst = build(kind, seed)
     mols = learn.pick_molecules(inst.nmol, per_seed, seed, salt=0xE7A1)
     model = learn.ScheduleMLP(nout=1, params=params)
-    res = learn.compare_schedules(inst, mols, model, lower_factor=lower_factor)
+    res = learn.compare_schedules(inst, mols, model, lower_factor=lower_factor, mu=mu)
     res["seed"] = seed
     res["kind"] = kind
+    res["mu"] = mu
     res["n_mean"] = float(inst.submatrix_dims()[mols].mean())
     return res
 
@@ -123,6 +133,10 @@ def main(argv=None):
     ap.add_argument("--lower-factor", type=float, default=0.5)
     ap.add_argument("--tol", type=float, default=1e-3)
     ap.add_argument("--extra", type=int, default=2)
+    ap.add_argument("--mus-per-seed", type=int, default=2,
+                    help="chemical potentials per training geometry besides mu = 0")
+    ap.add_argument("--mu-range", default="-0.45:0.02",
+                    help="interval lo:hi the extra chemical potentials are drawn from")
     ap.add_argument("--out", required=True, help="weights (.npz); the report goes next to it")
     ap.add_argument("--eval-only", action="store_true",
                     help="skip collection and training: evaluate the weights in --out")
@@ -141,10 +155,13 @@ def main(argv=None):
             tr = {"params": p, "loss": [float("nan"), float("nan")]}
             futs = []
         else:
-            futs = [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra)
+            mlo, mhi = (float(v) for v in args.mu_range.split(":"))
+            futs = [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra, "slab",
+                                sample_mus(s, args.mus_per_seed, mlo, mhi))
                     for s in _range(args.train)]
             if args.water_seeds:
-                futs += [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra, "water")
+                futs += [pool.submit(_collect_task, s, args.per_seed, args.tol, args.extra, "water",
+                                     sample_mus(s + 1000, args.mus_per_seed, mlo, mhi))
                          for s in _range(args.water_seeds)]
         data = []
         for f in cf.as_completed(futs):
@@ -162,15 +179,20 @@ def main(argv=None):
             resid = tr["pred"] - t
             say(f"trained in {tr['t_train']:.1f} s: loss {tr['loss'][0]:.4f} -> "
                 f"{tr['loss'][-1]:.4f}, train rms {np.sqrt(np.mean(resid ** 2)):.3f} (log10)")
-        efuts = [pool.submit(_eval_task, s, args.eval_per_seed, tr["params"], args.lower_factor)
-                 for s in _range(args.eval)]
+        mlo, mhi = (float(v) for v in args.mu_range.split(":"))
+        # every held-out geometry at mu = 0 and at one drawn chemical potential
+        efuts = [pool.submit(_eval_task, s, args.eval_per_seed, tr["params"], args.lower_factor,
+                             "slab", mu)
+                 for s in _range(args.eval)
+                 for mu in sample_mus(s + 5000, 1, mlo, mhi)]
         c2fut = (pool.submit(_eval_task, 0, args.c2_check, tr["params"], args.lower_factor, "c2")
                  if args.c2_check > 0 else None)
         evals = []
         for f in cf.as_completed(efuts):
             r = f.result()
             evals.append(r)
-            say(f"evaluated seed {r['seed']}: iters plain {r['plain_fp32']['iters_lo_mean']:.2f} "
+            say(f"evaluated seed {r['seed']} mu {r['mu']}: "
+                f"iters plain {r['plain_fp32']['iters_lo_mean']:.2f} "
                 f"default {r['mixed_default']['iters_lo_mean']:.2f} "
                 f"learned {r['mixed_learned']['iters_lo_mean']:.2f}  ({len(evals)}/{len(efuts)})")
         c2res = c2fut.result() if c2fut is not None else None
@@ -178,28 +200,37 @@ def main(argv=None):
             say(f"4,096-molecule box: iters plain {c2res['plain_fp32']['iters_lo_mean']:.2f} "
                 f"default {c2res['mixed_default']['iters_lo_mean']:.2f} "
                 f"learned {c2res['mixed_learned']['iters_lo_mean']:.2f}")
-    evals.sort(key=lambda r: r["seed"])
+    evals.sort(key=lambda r: (r["seed"], r["mu"]))
 
-    def agg(name, key, fn=np.mean):
-        v = [e[name][key] for e in evals if e[name].get(key) is not None]
-        return float(fn(v)) if v else None
+    def summarise(sel):
+        def agg(name, key, fn=np.mean):
+            v = [e[name][key] for e in sel if e[name].get(key) is not None]
+            return float(fn(v)) if v else None
 
-    summary = {}
-    for name in ("plain_fp32", "mixed_default", "mixed_learned"):
-        s = {"iters_lo_mean": agg(name, "iters_lo_mean"), "iters_fb_mean": agg(name, "iters_fb_mean"),
-             "fallbacks": int(sum(e[name]["fallbacks"] for e in evals)),
-             "failed": int(sum(e[name]["failed"] for e in evals)),
-             "ms_sign_total": agg(name, "ms_sign", np.sum), "ms_gemm_total": agg(name, "ms_gemm", np.sum),
-             "sign_tflops_mean": agg(name, "sign_tflops")}
-        if name != "plain_fp32":
-            s["max_abs_dD_vs_plain"] = agg(name, "max_abs_dD_vs_plain", np.max)
-            s["max_dE_per_atom_vs_plain"] = agg(name, "dE_per_atom_vs_plain", np.max)
-            s["max_sub_dE_per_atom_vs_plain"] = agg(name, "max_sub_dE_per_atom_vs_plain", np.max)
-        summary[name] = s
-    d, l_ = summary["mixed_default"], summary["mixed_learned"]
-    summary["learned_vs_default"] = {
-        "iteration_ratio": l_["iters_lo_mean"] / d["iters_lo_mean"],
-        "sign_time_ratio": l_["ms_sign_total"] / d["ms_sign_total"]}
+        summary = {}
+        for name in ("plain_fp32", "mixed_default", "mixed_learned"):
+            s = {"iters_lo_mean": agg(name, "iters_lo_mean"),
+                 "iters_fb_mean": agg(name, "iters_fb_mean"),
+                 "fallbacks": int(sum(e[name]["fallbacks"] for e in sel)),
+                 "failed": int(sum(e[name]["failed"] for e in sel)),
+                 "ms_sign_total": agg(name, "ms_sign", np.sum),
+                 "ms_gemm_total": agg(name, "ms_gemm", np.sum),
+                 "sign_tflops_mean": agg(name, "sign_tflops")}
+            if name != "plain_fp32":
+                s["max_abs_dD_vs_plain"] = agg(name, "max_abs_dD_vs_plain", np.max)
+                s["max_dE_per_atom_vs_plain"] = agg(name, "dE_per_atom_vs_plain", np.max)
+                s["max_sub_dE_per_atom_vs_plain"] = agg(name, "max_sub_dE_per_atom_vs_plain",
+                                                        np.max)
+            summary[name] = s
+        d, l_ = summary["mixed_default"], summary["mixed_learned"]
+        summary["learned_vs_default"] = {
+            "iteration_ratio": l_["iters_lo_mean"] / d["iters_lo_mean"],
+            "sign_time_ratio": l_["ms_sign_total"] / d["ms_sign_total"]}
+        return summary
+
+    summary = summarise(evals)
+    summary["at_mu_0"] = summarise([e for e in evals if e["mu"] == 0.0])
+    summary["away_from_mu_0"] = summarise([e for e in evals if e["mu"] != 0.0])
 
     if args.eval_only:
         with np.load(args.out, allow_pickle=False) as z:
@@ -212,6 +243,7 @@ def main(argv=None):
                 "eval_seeds": args.eval, "per_seed": args.per_seed, "samples": int(len(x)),
                 "steps": args.steps, "lr": args.lr, "tol": args.tol, "extra": args.extra,
                 "lower_factor": args.lower_factor, "eval_per_seed": args.eval_per_seed,
+                "mus_per_seed": args.mus_per_seed, "mu_range": args.mu_range,
                 "water_seeds": args.water_seeds, "water_nmol": WATER_NMOL,
                 "water_shift_range": [WATER_SHIFT_LO, WATER_SHIFT_HI],
                 "loss_first_last": [float(tr["loss"][0]), float(tr["loss"][-1])],

@@ -37,7 +37,7 @@ def trained():
         inst = get_config("t_slab", seed=seed, shift=SHIFT)
         mols = learn.pick_molecules(inst.nmol, 160, seed)
         print_case(f"collect t_slab seed {seed}")
-        f, lab, iters, ok = learn.collect(inst, mols)
+        f, lab, iters, ok, _ = learn.collect(inst, mols)
         assert ok.all()
         xs.append(f)
         ts.append(lab)
@@ -49,8 +49,9 @@ def trained():
 
 
 def oracle_errors(inst, r, mols, picks):
-    """Largest |dD| over the written columns of `picks`, and |dE| per atom of those
-    molecules together (the whole-system measure restricted to the sample)."""
+    """Largest |dD| over the written columns of `picks`, and the summed |dE_k| of those
+    molecules over their atoms (the whole-system measure restricted to the sample,
+    without cancellation between molecules)."""
     D = r.D.cpu().numpy()
     st = r.stats_host()
     pos = {int(k): i for i, k in enumerate(mols)}
@@ -64,7 +65,7 @@ def oracle_errors(inst, r, mols, picks):
             got[ref["offs"][a]:ref["offs"][a + 1], :] = \
                 D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
-        de += float(st["tr_dh"][pos[int(k)]]) - ref["tr_dh"]
+        de += abs(float(st["tr_dh"][pos[int(k)]]) - ref["tr_dh"])
         atoms += int(inst.atoms[k])
     return dmax, abs(de) / atoms
 
@@ -114,3 +115,22 @@ def test_committed_weights(gpu_ok):
     dmax, demax = oracle_errors(inst, r, mols, mols)
     print_case(f"learned vs oracle: dD {dmax:.2e} dE/atom {demax:.2e}")
     assert dmax <= D_TOL and demax <= E_TOL
+
+
+def test_committed_weights_away_from_mu_zero(gpu_ok):
+    """Trials of a chemical-potential search (mu inside the gap, away from 0): the
+    network's lower bound still saves iterations and sends no submatrix to the FP32
+    restart, on molecules of the 4,096-molecule benchmark box."""
+    if not os.path.exists(WEIGHTS):
+        pytest.skip("no trained weights committed")
+    m = learn.ScheduleMLP.load(WEIGHTS)
+    inst = get_config("c2")
+    mols = np.arange(0, inst.nmol, 64, dtype=np.int32)
+    for mu in (-0.1, -0.25):
+        res = learn.compare_schedules(inst, mols, m, mu=mu)
+        d, l_ = res["mixed_default"], res["mixed_learned"]
+        print_case(f"c2 mu {mu}: iters default {d['iters_lo_mean']:.2f} learned "
+                   f"{l_['iters_lo_mean']:.2f} restarts {l_['fallbacks']}")
+        assert l_["failed"] == 0 and l_["fallbacks"] == 0
+        assert l_["iters_lo_mean"] <= 0.8 * d["iters_lo_mean"]
+        assert l_["max_abs_dD_vs_plain"] <= D_TOL and l_["dE_per_atom_vs_plain"] <= E_TOL
