@@ -6,6 +6,12 @@ potential: gather T_k(H0), T_k(S) -> FP64 set-up -> batched sign iteration ->
 panel refinement and density columns -> scatter into D -> Tr(DH), Tr(DS).
 Inputs are resident in HBM before the timed region starts.
 
+A chemical-potential iteration (Sec. V-A/V-B: the runs iterate mu until the system
+is charge neutral, and the paper times each such iteration) reuses the gather and
+set-up of every batch (each batch keeps M_k and L^-1 in a buffer of its own), so
+it costs the sign iteration, density columns, scatter and traces only; the line
+also reports that time, measured over trial values of mu inside the gap.
+
 The reported value follows the paper's accounting (Sec. V-B, "FLOPs in the NOLSM
 method" and "Node-Performance"): FLOPs are 2 n^3 per n x n x n product of the
 matrix iterations (two products per Newton-Schulz step), O(n^2) work is not
@@ -33,6 +39,14 @@ FP32_PEAK = 157.3             # TFLOP/s, MI355X FP32
 
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def method_flops(stats, products_per_iter=2):
+    """The algorithmic work of the low-precision sign GEMMs: n^3 per product (every
+    product is symmetric, so its upper triangle, n^2/2 outputs of 2n flops each,
+    determines it), products_per_iter products per iteration of the phases."""
+    n3 = stats["n"].astype(np.float64) ** 3
+    return float((products_per_iter * n3 * stats["iters_lo"]).sum())
 
 
 def paper_flops(stats, products_per_iter=2):
@@ -99,6 +113,92 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub):
         demax = max(demax, de)
     err = {"max_abs_dD": dmax, "max_dE_per_atom": demax, "sampled_submatrices": int(len(ks))}
     return cpu, err
+
+
+def combination_table(inst, L, torch, args, log_fn):
+    """Sec. IV-B, Table II on this GPU: the workload without combination and with the
+    groups of Eq. 9 and Eq. 10 (p(n) = the autotuner's measured rates), each run
+    through the whole path with the default mixed schedule: submatrix count, smallest,
+    largest and mean dimension, FLOPs of one multiplication of every submatrix
+    (2 n^3), the estimated throughput and speedup from p(n), and the measured
+    sign-phase and step times and throughputs."""
+    from paper_2205_12182_amd.autotune import rate_table
+    from paper_2205_12182_amd.runner import Runner, default_mixed_schedule
+    table = rate_table()
+    tn = np.array([a for a, _ in table])
+    tr = np.array([b for _, b in table])
+    hp = L.HostPattern(inst)
+    mols = np.arange(inst.nmol, dtype=np.int32)
+    sched = default_mixed_schedule()
+    rows = {}
+    for crit in ("none", "eq9", "eq10"):
+        groups = ([[int(k)] for k in mols] if crit == "none" else
+                  L.nolsm_combine(hp, mols, 9 if crit == "eq9" else 10,
+                                  table if crit == "eq10" else None, args.combine_max_n))
+        r = Runner(inst, groups=groups, batch=args.combine_batch)
+        ns = np.array([L.nolsm_plan_query(p, i).n for p, b in zip(r.plans, r.batches)
+                       for i in range(len(b))], dtype=np.float64)
+        r.run(sched=sched)
+        torch.cuda.synchronize()
+        wall, tm = timed_steps(r, sched, args.combine_steps, L, torch)
+        st = r.stats_host()
+        e, ne = r.energy_host()
+        flops_mult = float((2.0 * ns ** 3).sum())
+        est_time = float((2.0 * ns ** 3 / np.interp(ns, tn, tr)).sum())
+        sign_s = tm["ms_sign"] / args.combine_steps * 1e-3
+        rows[crit] = {"submatrices": int(ns.size), "n_min": int(ns.min()), "n_max": int(ns.max()),
+                      "n_mean": round(float(ns.mean()), 1),
+                      "pflop_one_multiplication": round(flops_mult / 1e15, 4),
+                      "estimated_tflops": round(flops_mult / est_time, 1),
+                      "estimated_time_rel": est_time,
+                      "ms_per_step": round(wall * 1e3, 2), "sign_ms": round(sign_s * 1e3, 2),
+                      "sign_tflops": round(paper_flops(st) / sign_s / 1e12, 1),
+                      "step_tflops": round(paper_flops(st) / wall / 1e12, 1),
+                      "iters_mean": round(float(st["iters_lo"].mean()), 2),
+                      "fallbacks": int(st["fell_back"].sum()),
+                      "failed": int((st["status"] != 0).sum()),
+                      "energy": e, "electrons": ne}
+        log_fn(f"combination {crit}: {json.dumps(rows[crit])}")
+        del r
+        torch.cuda.empty_cache()
+    base = rows["none"]
+    for crit in ("eq9", "eq10"):
+        rows[crit]["estimated_speedup"] = round(base["estimated_time_rel"] /
+                                                rows[crit]["estimated_time_rel"], 3)
+        rows[crit]["measured_speedup_sign"] = round(base["sign_ms"] / rows[crit]["sign_ms"], 3)
+        rows[crit]["measured_speedup_step"] = round(base["ms_per_step"] / rows[crit]["ms_per_step"], 3)
+    for v in rows.values():
+        v.pop("estimated_time_rel")
+    return {"schedule": "default mixed (fp16 to ||X^2-I||_F<=0.1 +1, unscaled)",
+            "rate_table_n_tflops": [[round(a, 1), round(b, 1)] for a, b in table],
+            "max_n": args.combine_max_n, "rows": rows}
+
+
+def golden_energies(inst, workload):
+    """Per-molecule oracle energies of the whole workload (tests/golden), if they were
+    written for this exact instance; else None."""
+    path = os.path.join(ROOT, "tests", "golden", f"{workload}_energies.npz")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_energies import instance_digest
+    with np.load(path, allow_pickle=False) as z:
+        rec = {k: z[k] for k in z.files}
+    if str(rec["instance_sha256"]) != instance_digest(inst):
+        log(f"{path} was written for another instance: not used")
+        return None
+    return rec
+
+
+def system_errors(inst, runner, st, e_gpu, gold):
+    """|E - E_oracle| / N_atoms over the whole system, and the largest single molecule's
+    |dE_k| / atoms_k, against the oracle's energies of every molecule."""
+    mols = runner.mols
+    de_k = np.abs(st["tr_dh"] - gold["tr_dh"][mols]) / inst.atoms[mols]
+    return {"system_dE_per_atom": abs(e_gpu - math.fsum(gold["tr_dh"].tolist())) / inst.natoms,
+            "max_single_molecule_dE_per_atom": float(de_k.max()),
+            "electrons_oracle": math.fsum(gold["tr_ds"].tolist()),
+            "molecules": int(len(mols))}
 
 
 TRAFFIC_PATH = os.path.join(ROOT, "profiles", "ns_gemm_rect_fp16_c2_traffic.json")
@@ -184,6 +284,15 @@ def copy_calibration(torch, mib):
     log(f"copy calibration: 3 x elementwise copy of {mib} MiB")
 
 
+def workload_text(name, inst, dims):
+    if name.startswith("c3"):
+        kind = (f"{int((inst.blk_dim == 23).sum())} water-like molecules (23 functions) around a "
+                f"slab of {int((inst.blk_dim == 30).sum())} five-site units (30 functions)")
+    else:
+        kind = f"{inst.nmol} water-like molecules, {int(inst.blk_dim[0])} functions each"
+    return f"{name}: {kind}, r_c {inst.r_cut} A, submatrices n {dims.min()}-{dims.max()}"
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -201,6 +310,14 @@ def main():
                     help="submatrices the oracle solves on the host (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="timed replays of the step captured as a HIP graph (0: skip)")
+    ap.add_argument("--mu-trials", type=int, default=3,
+                    help="chemical-potential iterations timed after the first (0: skip)")
+    ap.add_argument("--combination", type=int, default=1,
+                    help="1: also run the workload without and with submatrix combination "
+                         "(Eq. 9, Eq. 10) and report the Table II analogue; 0: skip")
+    ap.add_argument("--combine-max-n", type=int, default=6000)
+    ap.add_argument("--combine-batch", type=int, default=512)
+    ap.add_argument("--combine-steps", type=int, default=2)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, three elementwise copies of MIB MiB (counter scaling)")
     ap.add_argument("--traffic-summary", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
@@ -235,8 +352,9 @@ def main():
     dims = inst.submatrix_dims()
     log(f"workload {args.workload}: {inst.nmol} molecules, n_k {dims.min()}-{dims.max()}, "
         f"built in {time.perf_counter() - t:.1f} s")
-    runner = Runner(inst, batch=args.batch)
-    log(f"{len(runner.plans)} batches, workspace {runner.workspace.numel() / 2**30:.1f} GiB")
+    runner = Runner(inst, batch=args.batch, persist=True)
+    log(f"{len(runner.plans)} batches, workspace {runner.workspace.numel() / 2**30:.1f} GiB, "
+        f"set-up buffers {sum(b.numel() for b in runner.persist_bufs) / 2**30:.1f} GiB")
 
     weights = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
     if args.schedule is None:
@@ -255,7 +373,12 @@ def main():
     log(f"mixed: {wall * 1e3:.1f} ms/step  phases {json.dumps({k: round(v, 1) for k, v in tm.items()})}")
     st = runner.stats_host()
     e_mixed, n_mixed = runner.energy_host()
+    failed = int((st["status"] != 0).sum())
+    check = runner.check()
+    if failed or check != L.OK:
+        log(f"{failed} submatrices failed: {runner.last_check_message}")
     flops = paper_flops(st)
+    alg_flop_step = method_flops(st)
     K = len(st)
     gemm_ms = tm["ms_gemm"] / args.steps
     sign_ms = tm["ms_sign"] / args.steps
@@ -276,10 +399,39 @@ def main():
         log(f"graph replay: {json.dumps(graph)}")
         del g
 
+    mu_iter = None
+    if args.mu_trials > 0:
+        # trial chemical potentials inside the gap at mu = 0, as the last iterations of
+        # a charge-neutrality search visit them; the first trial gathers and sets up
+        mus = [inst.mu - 0.05 * (t + 1) for t in range(args.mu_trials + 1)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        runner.run(mu=mus[0], sched=mixed, predictor=predictor)
+        torch.cuda.synchronize()
+        first = time.perf_counter() - t0
+        ne = [runner.energy_host()[1]]
+        t0 = time.perf_counter()
+        for mu in mus[1:]:
+            runner.run(mu=mu, sched=mixed, predictor=predictor, regather=False)
+        torch.cuda.synchronize()
+        per = (time.perf_counter() - t0) / args.mu_trials
+        ne.append(runner.energy_host()[1])
+        mu_iter = {"ms": round(per * 1e3, 2), "first_ms": round(first * 1e3, 2),
+                   "mus": [round(m, 4) for m in mus], "electrons_first_last": ne,
+                   "n_elec": inst.n_elec, "failed": int((runner.stats_host()["status"] != 0).sum()),
+                   "submatrices_per_s": round(K / per, 2),
+                   "tflops": round(paper_flops(runner.stats_host()) / per / 1e12, 3)}
+        log(f"mu iterations: {json.dumps(mu_iter)}")
+        runner.run(sched=mixed, predictor=predictor)        # back to the step's mu
+        torch.cuda.synchronize()
+
     cpu, err = None, None
     if args.cpu_sample > 0:
         from oracle import nolsm_oracle as O
         cpu, err = oracle_sample(inst, runner, O, args.cpu_sample, flops / K)
+        gold = golden_energies(inst, args.workload)
+        if gold is not None:
+            err.update(system_errors(inst, runner, st, e_mixed, gold))
         log(f"cpu baseline: {json.dumps(cpu)}")
         log(f"error vs oracle: {json.dumps(err)}")
     other = None
@@ -315,9 +467,18 @@ def main():
     if args.calibrate_copy > 0:
         copy_calibration(torch, args.calibrate_copy)
 
-    # executed MFMA flops of the active tiles (device counter) over the time of every
-    # GEMM launch in the timed region (HIP events around each launch)
-    achieved = exec_flop_step / (gemm_ms * 1e-3) / 1e12
+    combo = None
+    if args.combination:
+        del runner
+        torch.cuda.empty_cache()
+        combo = combination_table(inst, L, torch, args, log)
+
+    # the method's work of the sign GEMMs (n^3 per symmetric product of each active
+    # submatrix) over the time of every GEMM launch in the timed region (HIP events
+    # around each launch); the executed MFMA flops of the active tiles (device counter:
+    # whole tiles across the diagonal, padding to 64) are reported beside it
+    achieved = alg_flop_step / (gemm_ms * 1e-3) / 1e12
+    executed = exec_flop_step / (gemm_ms * 1e-3) / 1e12
     n_gemm = tm["n_gemm"] / args.steps
     out = {
         "metric": METRIC,
@@ -332,9 +493,7 @@ def main():
         "vs_baseline": None,
         "dtype": args.prec,
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {inst.nmol} water-like molecules, "
-                               f"{int(inst.blk_dim[0])} functions each, r_c {inst.r_cut} A, "
-                               f"submatrices n {dims.min()}-{dims.max()}",
+        "config": {"workload": workload_text(args.workload, inst, dims),
                    "batch": args.batch,
                    "schedule": (f"{args.prec} Newton-Schulz " +
                                 (f"x{args.iters}" if args.iters else "to ||X^2-I||_F<=0.1 +1") +
@@ -345,16 +504,19 @@ def main():
                                 "FP16 MFMAs with split (hi + 2^-11 lo) FP32-class operands"),
                    "iters_mean": round(float(st["iters_lo"].mean()), 2),
                    "fallbacks": int(st["fell_back"].sum()),
+                   "failed": failed,
                    "parallelism": "none (1 GPU)"},
         "submatrices_per_s": round(K / wall, 2),
         "sign_phase_tflops": round(flops / (sign_ms * 1e-3) / 1e12, 3),
         "phase_ms": {k[3:]: round(v / args.steps, 2) for k, v in tm.items() if k.startswith("ms_")},
-        "energy": e_mixed, "electrons": n_mixed,
+        "energy": e_mixed, "electrons": n_mixed, "n_elec": inst.n_elec,
+        "mu_iteration": mu_iter,
         "error_vs_oracle": err,
         "graph_replay": graph,
         "default_schedule": other,
         "plain_fp32": plain,
         "speedup_vs_plain_fp32": round(plain["ms_per_step"] / (wall * 1e3), 3) if plain else None,
+        "submatrix_combination": combo,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2), "peak": FP16_PEAK,
                      "unit": "TFLOP/s", "frac": round(achieved / FP16_PEAK, 4),
                      "traffic": measured_traffic(args.workload, args.schedule),
@@ -363,11 +525,18 @@ def main():
                      "kernel": "ns_gemm_rect_kernel (symmetric upper-tile FP16 product, 256x128 tiles)",
                      "launches_per_step": n_gemm,
                      "avg_launch_ms": round(gemm_ms / max(n_gemm, 1), 4),
+                     "method_flop_per_step": alg_flop_step,
+                     "executed_achieved": round(executed, 2),
+                     "executed_frac": round(executed / FP16_PEAK, 4),
                      "executed_flop_per_step": exec_flop_step,
-                     "note": "achieved = executed MFMA flops of active tiles / summed launch time"},
+                     "note": "achieved = the method's work (n^3 per symmetric product of each "
+                             "active submatrix) / summed launch time; executed_* counts the MFMA "
+                             "work the tiles ran (device counter)"},
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if failed or check != L.OK:
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -60,6 +60,23 @@ def measure(r_cut: float, batch: int, say) -> dict:
     return rec
 
 
+def rate_table(policy: dict | None = None) -> list:
+    """p(n) of Sec. IV-B from the stored measurements: for each measured size, the
+    sign-GEMM throughput in the paper's accounting (2 n^3 per product and submatrix)
+    with the tile shape the policy picks there, [(n_mean, TFLOP/s), ...] ascending.
+    Eq. 10 combines submatrices on the predicted time n^3 / p(n)."""
+    if policy is None:
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tile_policy.json")
+        with open(path) as fh:
+            policy = json.load(fh)
+    out = []
+    for m in sorted(policy["measurements"], key=lambda r: r["n_mean"]):
+        key = "tile256x128" if m["npad_mean"] >= policy["big_tile_min_npad"] else "tile128"
+        t = m[key]["ms_per_launch"] * 1e-3
+        out.append((float(m["n_mean"]), 2.0 * m["submatrices"] * m["n_mean"] ** 3 / t / 1e12))
+    return out
+
+
 def choose(recs) -> int:
     """Smallest mean padded size from which the large tiles win at every larger size."""
     recs = sorted(recs, key=lambda r: r["npad_mean"])
