@@ -272,6 +272,80 @@ def measured_traffic(workload, schedule):
     return float(rec["per_launch_bytes"])
 
 
+def _short_name(name):
+    """Readable kernel name of a rocprofv3 record (mangled or demangled)."""
+    import re
+    for pat, nice in (("ns_gemm_rect_kernelIDF16_Li0E", "ns_gemm_rect_kernel<_Float16, SQUARE>"),
+                      ("ns_gemm_rect_kernelIDF16_Li1E", "ns_gemm_rect_kernel<_Float16, UPDATE>")):
+        if pat in name:
+            return nice
+    name = re.sub(r"^void ", "", name)
+    return name.split("(")[0]
+
+
+def trace_summary(trace_csv, fetch_csv=None, write_csv=None, calib_mib=1024, top=24):
+    """Markdown summary of a rocprofv3 kernel trace (csv): per-kernel totals, the
+    sign GEMM's duration by iteration (launch index within each batch), and, given
+    FETCH_SIZE / WRITE_SIZE collections (csv, KiB per dispatch, scaled by the same
+    counters on a plain copy of calib_mib MiB), the bytes and rates of the gather
+    and scatter kernels."""
+    import csv
+    rows = sorted(csv.DictReader(open(trace_csv)), key=lambda r: int(r["Start_Timestamp"]))
+    per = {}
+    seq = []
+    for r in rows:
+        k = _short_name(r["Kernel_Name"])
+        d = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6
+        per.setdefault(k, []).append(d)
+        if k.startswith("ns_gemm_rect_kernel"):
+            seq.append((k.endswith("SQUARE>"), d))
+    tot = sum(sum(v) for v in per.values())
+    out = ["| Kernel | Calls | Total ms | Avg us | % |", "|---|---|---|---|---|"]
+    for k, v in sorted(per.items(), key=lambda kv: -sum(kv[1]))[:top]:
+        out.append(f"| {k} | {len(v)} | {sum(v):.1f} | {1e3 * sum(v) / len(v):.1f} | "
+                   f"{100 * sum(v) / tot:.1f} |")
+    sq = [d for is_sq, d in seq if is_sq]
+    up = [d for is_sq, d in seq if not is_sq]
+    per_batch = None
+    for cand in range(30, 0, -1):           # launches per batch: the longest period that fits
+        if len(sq) % cand == 0 and len(up) == len(sq) and min(sq[cand - 1::cand]) < 0.2:
+            per_batch = cand
+            break
+    if per_batch:
+        S = np.array(sq).reshape(-1, per_batch)
+        U = np.array(up).reshape(-1, per_batch)
+        out += ["", f"Sign GEMM launches by iteration (mean over {S.shape[0]} batches):", "",
+                "| Iteration | SQUARE ms | UPDATE ms |", "|---|---|---|"]
+        for t in range(per_batch):
+            out.append(f"| {t} | {S[:, t].mean():.3f} | {U[:, t].mean():.3f} |")
+    if fetch_csv and write_csv:
+        def counters(path):
+            acc = {}
+            for r in csv.DictReader(open(path)):
+                acc.setdefault(_short_name(r["Kernel_Name"]), []).append(float(r["Counter_Value"]))
+            return acc
+        f, w = counters(fetch_csv), counters(write_csv)
+        nbytes = calib_mib * (1 << 20)
+        cp = [k for k in f if "MulFunctor" in k]          # the copy of --calibrate-copy
+        fcopy = max(max(f[k]) for k in cp)
+        wcopy = max(max(w[k]) for k in cp)
+        fs, ws = nbytes / (fcopy * 1024.0), nbytes / (wcopy * 1024.0)
+        out += ["", f"HBM bytes per dispatch (FETCH_SIZE x{fs:.2f}, WRITE_SIZE x{ws:.2f}: the "
+                    f"scales that make the counters read the {calib_mib} MiB of a plain copy):", "",
+                "| Kernel | Read GB | Written GB | Avg ms (trace) | GB/s | Fraction of 8 TB/s |",
+                "|---|---|---|---|---|---|"]
+        for k in sorted(f):
+            if "elementwise" in k:
+                continue
+            rb = np.mean(f[k]) * 1024.0 * fs
+            wb = np.mean(w.get(k, [0.0])) * 1024.0 * ws
+            ms = np.mean(per.get(k, [np.nan]))
+            rate = (rb + wb) / (ms * 1e-3) / 1e9
+            out.append(f"| {k} | {rb / 1e9:.2f} | {wb / 1e9:.2f} | {ms:.3f} | {rate:.0f} | "
+                       f"{rate / 8000.0:.2f} |")
+    print("\n".join(out))
+
+
 def copy_calibration(torch, mib):
     """A plain elementwise copy of known size (read mib MiB, write mib MiB), run three
     times so that hardware byte counters can be scaled against it."""
@@ -325,7 +399,16 @@ def main():
                          "(runs nothing on the GPU); with --calibrate-copy, --workload, "
                          "--schedule and --traffic-command")
     ap.add_argument("--traffic-command", default="", help="command recorded in the profile")
+    ap.add_argument("--trace-summary", nargs="+", metavar="CSV",
+                    help="print a markdown summary of a rocprofv3 kernel trace (csv), and with "
+                         "two more csv files (FETCH_SIZE, WRITE_SIZE collections) the bytes and "
+                         "rates of the kernels they cover (runs nothing on the GPU)")
     args = ap.parse_args()
+    if args.trace_summary:
+        t = args.trace_summary
+        trace_summary(t[0], *(t[1:3] if len(t) >= 3 else (None, None)),
+                      calib_mib=args.calibrate_copy or 1024)
+        return
     if args.traffic_summary:
         traffic_summary(args.traffic_summary[0], args.traffic_summary[1], args.workload,
                         args.schedule or "learned", args.calibrate_copy or 1024,
