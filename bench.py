@@ -56,14 +56,14 @@ def paper_flops(stats, products_per_iter=2):
     return float((2.0 * products_per_iter * n3 * (stats["iters_lo"] + stats["iters_fb"])).sum())
 
 
-def timed_steps(runner, sched, steps, L, torch, predictor=None):
+def timed_steps(runner, sched, steps, L, torch, predictor=None, mu=None):
     for p in runner.plans:
         L.nolsm_plan_get_timings(p, reset=True)
         L.nolsm_plan_set_timing(p, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        runner.run(sched=sched, predictor=predictor)
+        runner.run(mu=mu, sched=sched, predictor=predictor)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
     tot = {}
@@ -75,7 +75,7 @@ def timed_steps(runner, sched, steps, L, torch, predictor=None):
     return wall, tot
 
 
-def oracle_sample(inst, runner, O, sample, flops_per_sub):
+def oracle_sample(inst, runner, O, sample, flops_per_sub, mu=None):
     """The oracle on `sample` evenly spaced molecules (one submatrix each), timed on
     the host cores; the same results give the GPU path's error on that sample."""
     try:
@@ -85,7 +85,7 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub):
         cores = os.cpu_count()
     ks = np.linspace(0, inst.nmol - 1, sample).astype(int)
     t0 = time.perf_counter()
-    refs = [O.submatrix_result(inst, int(k)) for k in ks]
+    refs = [O.submatrix_result(inst, int(k), mu=mu) for k in ks]
     dt = time.perf_counter() - t0
     subs_per_s = len(ks) / dt
     cpu = {"value": round(subs_per_s * flops_per_sub / 1e12, 6), "unit": "TFLOP/s",
@@ -115,7 +115,7 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub):
     return cpu, err
 
 
-def combination_table(inst, L, torch, args, log_fn):
+def combination_table(inst, L, torch, args, log_fn, mu=None):
     """Sec. IV-B, Table II on this GPU: the workload without combination and with the
     groups of Eq. 9 and Eq. 10 (p(n) = the autotuner's measured rates), each run
     through the whole path with the default mixed schedule: submatrix count, smallest,
@@ -138,9 +138,9 @@ def combination_table(inst, L, torch, args, log_fn):
         r = Runner(inst, groups=groups, batch=args.combine_batch)
         ns = np.array([L.nolsm_plan_query(p, i).n for p, b in zip(r.plans, r.batches)
                        for i in range(len(b))], dtype=np.float64)
-        r.run(sched=sched)
+        r.run(mu=mu, sched=sched)
         torch.cuda.synchronize()
-        wall, tm = timed_steps(r, sched, args.combine_steps, L, torch)
+        wall, tm = timed_steps(r, sched, args.combine_steps, L, torch, mu=mu)
         st = r.stats_host()
         e, ne = r.energy_host()
         flops_mult = float((2.0 * ns ** 3).sum())
@@ -169,19 +169,20 @@ def combination_table(inst, L, torch, args, log_fn):
         rows[crit]["measured_speedup_step"] = round(base["ms_per_step"] / rows[crit]["ms_per_step"], 3)
     for v in rows.values():
         v.pop("estimated_time_rel")
-    return {"schedule": "default mixed (fp16 to ||X^2-I||_F<=0.1 +1, unscaled)",
+    return {"schedule": "default mixed (fp16 to ||X^2-I||_F<=0.1 +1, unscaled)", "mu": mu,
             "rate_table_n_tflops": [[round(a, 1), round(b, 1)] for a, b in table],
             "max_n": args.combine_max_n, "rows": rows}
 
 
-def golden_energies(inst, workload):
-    """Per-molecule oracle energies of the whole workload (tests/golden), if they were
-    written for this exact instance; else None."""
-    path = os.path.join(ROOT, "tests", "golden", f"{workload}_energies.npz")
+def golden_energies(inst, workload, mu):
+    """Per-molecule oracle energies of the whole workload at mu (tests/golden), if they
+    were written for this exact instance; else None."""
+    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
+    from make_energies import golden_name, instance_digest
+    path = os.path.join(ROOT, "tests", "golden",
+                        golden_name(workload, None if mu == inst.mu else mu))
     if not os.path.exists(path):
         return None
-    sys.path.insert(0, os.path.join(ROOT, "tests", "golden"))
-    from make_energies import instance_digest
     with np.load(path, allow_pickle=False) as z:
         rec = {k: z[k] for k in z.files}
     if str(rec["instance_sha256"]) != instance_digest(inst):
@@ -384,8 +385,16 @@ def main():
                     help="submatrices the oracle solves on the host (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="timed replays of the step captured as a HIP graph (0: skip)")
+    ap.add_argument("--overlap", action="store_true",
+                    help="gather and set up batch i + 1 on a second stream while batch i "
+                         "iterates (two shared workspaces; measured no faster on c2)")
     ap.add_argument("--mu-trials", type=int, default=3,
                     help="chemical-potential iterations timed after the first (0: skip)")
+    ap.add_argument("--mu-trial-step", type=float, default=-0.03,
+                    help="offset between the timed chemical-potential trials")
+    ap.add_argument("--mu-search", default="", metavar="LO:HI",
+                    help="first search the charge-neutral mu in [LO, HI] (Tr(DS) = N_e within "
+                         "half an electron) and run every step there")
     ap.add_argument("--combination", type=int, default=1,
                     help="1: also run the workload without and with submatrix combination "
                          "(Eq. 9, Eq. 10) and report the Table II analogue; 0: skip")
@@ -435,8 +444,10 @@ def main():
     dims = inst.submatrix_dims()
     log(f"workload {args.workload}: {inst.nmol} molecules, n_k {dims.min()}-{dims.max()}, "
         f"built in {time.perf_counter() - t:.1f} s")
-    runner = Runner(inst, batch=args.batch, persist=True)
-    log(f"{len(runner.plans)} batches, workspace {runner.workspace.numel() / 2**30:.1f} GiB, "
+    runner = Runner(inst, batch=args.batch, persist=True, overlap=args.overlap)
+    overlap_used = runner.overlap
+    log(f"{len(runner.plans)} batches, {len(runner.workspaces)} workspaces of "
+        f"{runner.workspace.numel() / 2**30:.1f} GiB, "
         f"set-up buffers {sum(b.numel() for b in runner.persist_bufs) / 2**30:.1f} GiB")
 
     weights = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
@@ -448,11 +459,31 @@ def main():
         mixed = learned_schedule(prec=args.prec)
     else:
         mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec)
+    step_mu = inst.mu
+    search = None
+    if args.mu_search:
+        lo, hi = (float(v) for v in args.mu_search.split(":"))
+        t_prev = [time.perf_counter()]
+        trials = []
+
+        def on_trial(t, mu, ne, e):
+            now = time.perf_counter()
+            trials.append({"mu": mu, "electrons": ne, "energy": e,
+                           "ms": round((now - t_prev[0]) * 1e3, 1)})
+            log(f"mu trial {t}: {json.dumps(trials[-1])}")
+            t_prev[0] = now
+        torch.cuda.synchronize()
+        t_prev[0] = time.perf_counter()
+        m, _ = runner.mu_search(inst.n_elec, lo, hi, tol=0.5, max_iter=40, sched=mixed,
+                                predictor=predictor, on_trial=on_trial)
+        step_mu = m.mu
+        search = {"bracket": [lo, hi], "n_elec": inst.n_elec, "converged": m.done == 1,
+                  "mu": m.mu, "trials": trials}
     for w in range(args.warmup):
-        runner.run(sched=mixed, predictor=predictor)
+        runner.run(mu=step_mu, sched=mixed, predictor=predictor)
         torch.cuda.synchronize()
         log(f"warmup {w} done")
-    wall, tm = timed_steps(runner, mixed, args.steps, L, torch, predictor)
+    wall, tm = timed_steps(runner, mixed, args.steps, L, torch, predictor, mu=step_mu)
     log(f"mixed: {wall * 1e3:.1f} ms/step  phases {json.dumps({k: round(v, 1) for k, v in tm.items()})}")
     st = runner.stats_host()
     e_mixed, n_mixed = runner.energy_host()
@@ -469,7 +500,7 @@ def main():
 
     graph = None
     if args.graph_steps > 0:
-        g = runner.capture(sched=mixed, predictor=predictor)
+        g = runner.capture(mu=step_mu, sched=mixed, predictor=predictor)
         g.replay()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -486,7 +517,7 @@ def main():
     if args.mu_trials > 0:
         # trial chemical potentials inside the gap at mu = 0, as the last iterations of
         # a charge-neutrality search visit them; the first trial gathers and sets up
-        mus = [inst.mu - 0.05 * (t + 1) for t in range(args.mu_trials + 1)]
+        mus = [step_mu + args.mu_trial_step * (t + 1) for t in range(args.mu_trials + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         runner.run(mu=mus[0], sched=mixed, predictor=predictor)
@@ -505,14 +536,14 @@ def main():
                    "submatrices_per_s": round(K / per, 2),
                    "tflops": round(paper_flops(runner.stats_host()) / per / 1e12, 3)}
         log(f"mu iterations: {json.dumps(mu_iter)}")
-        runner.run(sched=mixed, predictor=predictor)        # back to the step's mu
+        runner.run(mu=step_mu, sched=mixed, predictor=predictor)    # back to the step's mu
         torch.cuda.synchronize()
 
     cpu, err = None, None
     if args.cpu_sample > 0:
         from oracle import nolsm_oracle as O
-        cpu, err = oracle_sample(inst, runner, O, args.cpu_sample, flops / K)
-        gold = golden_energies(inst, args.workload)
+        cpu, err = oracle_sample(inst, runner, O, args.cpu_sample, flops / K, mu=step_mu)
+        gold = golden_energies(inst, args.workload, step_mu)
         if gold is not None:
             err.update(system_errors(inst, runner, st, e_mixed, gold))
         log(f"cpu baseline: {json.dumps(cpu)}")
@@ -520,8 +551,8 @@ def main():
     other = None
     if args.schedule == "learned" and args.plain_steps > 0:
         dflt = default_mixed_schedule(prec=args.prec)
-        runner.run(sched=dflt)
-        wall_d, tm_d = timed_steps(runner, dflt, 1, L, torch)
+        runner.run(mu=step_mu, sched=dflt)
+        wall_d, tm_d = timed_steps(runner, dflt, 1, L, torch, mu=step_mu)
         st_d = runner.stats_host()
         other = {"ms_per_step": round(wall_d * 1e3, 2),
                  "tflops": round(paper_flops(st_d) / wall_d / 1e12, 3),
@@ -533,7 +564,7 @@ def main():
     plain = None
     if args.plain_steps > 0:
         pl = plain_fp32_schedule()
-        wall_p, tm_p = timed_steps(runner, pl, args.plain_steps, L, torch)
+        wall_p, tm_p = timed_steps(runner, pl, args.plain_steps, L, torch, mu=step_mu)
         st_p = runner.stats_host()
         e_plain, _ = runner.energy_host()
         fl_p = paper_flops(st_p)
@@ -554,7 +585,7 @@ def main():
     if args.combination:
         del runner
         torch.cuda.empty_cache()
-        combo = combination_table(inst, L, torch, args, log)
+        combo = combination_table(inst, L, torch, args, log, mu=step_mu)
 
     # the method's work of the sign GEMMs (n^3 per symmetric product of each active
     # submatrix) over the time of every GEMM launch in the timed region (HIP events
@@ -588,11 +619,13 @@ def main():
                    "iters_mean": round(float(st["iters_lo"].mean()), 2),
                    "fallbacks": int(st["fell_back"].sum()),
                    "failed": failed,
-                   "parallelism": "none (1 GPU)"},
+                   "parallelism": "none (1 GPU)",
+                   "overlap": overlap_used},
         "submatrices_per_s": round(K / wall, 2),
         "sign_phase_tflops": round(flops / (sign_ms * 1e-3) / 1e12, 3),
         "phase_ms": {k[3:]: round(v / args.steps, 2) for k, v in tm.items() if k.startswith("ms_")},
-        "energy": e_mixed, "electrons": n_mixed, "n_elec": inst.n_elec,
+        "energy": e_mixed, "electrons": n_mixed, "n_elec": inst.n_elec, "mu": step_mu,
+        "mu_search": search,
         "mu_iteration": mu_iter,
         "error_vs_oracle": err,
         "graph_replay": graph,

@@ -78,9 +78,9 @@ struct TileSet {
   unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
   unsigned *fb_count;               // submatrices selected for the FP32 restart
 };
-// 2 * 32 * 32 * 64 flops: one 32 x 32 output block over 64 k (tile edges and npad
+// 2 * 16 * 16 * 64 flops: one 16 x 16 output block over 64 k (tile edges and npad
 // are multiples of these, so the count is exact)
-constexpr double FLOP_UNIT = 131072.0;
+constexpr double FLOP_UNIT = 32768.0;
 constexpr int BIG_TILE_MIN_NPAD = 768;   // submatrices at least this large use 256 x 128 tiles
 
 // Host-side record of HIP event pairs around launch groups (measurement only).

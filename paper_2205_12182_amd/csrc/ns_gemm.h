@@ -365,7 +365,7 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
   const int i0 = t.ti * TILE, j0 = t.tj * TILE;
   if (threadIdx.x == 0) {
     const int rows = (ld - i0 < TILE ? ld - i0 : TILE), cols = (ld - j0 < TILE ? ld - j0 : TILE);
-    atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
+    atomicAdd(flop_units, (unsigned long long)((rows / 16) * (cols / 16) * (ld / 64)));
   }
   // the ring slots (separate arrays, see above); the epilogue reuses them as the
   // four column quarters of its staging tile
@@ -409,7 +409,7 @@ __global__ __launch_bounds__(256) void ns_gemm_gated_kernel(
     const int i0 = t.ti * 128, j0 = t.tj * 128;
     if (threadIdx.x == 0) {
       const int rows = (ld - i0 < 128 ? ld - i0 : 128), cols = (ld - j0 < 128 ? ld - j0 : 128);
-      atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
+      atomicAdd(flop_units, (unsigned long long)((rows / 16) * (cols / 16) * (ld / 64)));
     }
     if (i0 + 128 <= ld && j0 + 128 <= ld)
       ns_gemm_body<float, EPI, 2, false, 1>(A, B, Out, ld, ld, d.n, i0, j0, S.c1, S.c3, s0, s1,

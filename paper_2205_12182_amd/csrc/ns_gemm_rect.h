@@ -39,7 +39,7 @@ template <> struct Mfma16<__bf16> {
   }
 };
 
-template <typename TI, int EPI, bool PARTIAL>
+template <typename TI, int EPI, bool PARTIAL, bool LOWIDLE>
 __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
                                                   const TI *__restrict__ B, TI *__restrict__ Out,
                                                   int ld, int n, int i0, int j0, float c1,
@@ -56,11 +56,21 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
   const int nk = ld / KStage<TI>::KS;
 
   int nvr = BM, nvc = BN;
+  // PARTIAL tiles are ragged at the matrix edge: blocks past the edge, and blocks
+  // wholly below the diagonal (first row after last column), issue no MFMAs.
+  // LOWIDLE tiles start on the diagonal (i0 == j0), so their second 128 rows lie
+  // wholly below it: the two waves that own them issue no MFMAs, and those rows are
+  // not loaded (the null buffer resource returns zeros without a memory access, so
+  // every stage still issues the same number of loads).
+  int diag_off = 0;                                   // row - column offset of block (0, 0)
+  const bool skip_low = (PARTIAL || LOWIDLE) && i0 >= j0;
+  const bool mfma_wave = !(LOWIDLE && wm >= 128);
   if (PARTIAL) {
     nvr = (ld - i0 - wm) / 16;
     nvc = (ld - j0 - wn) / 16;
     nvr = nvr < 0 ? 0 : (nvr > BM ? BM : nvr);
     nvc = nvc < 0 ? 0 : (nvc > BN ? BN : nvc);
+    diag_off = (i0 + wm) - (j0 + wn);
   }
   const int nrec = ld * ld * (int)sizeof(TI);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
@@ -103,7 +113,8 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
     const int so = live ? 64 * kt : 0;
 #pragma unroll
     for (int q = 0; q < LA; ++q)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, NS_LDS_PTR(slot + (4 * q + w) * 64), 16,
+      __builtin_amdgcn_raw_ptr_buffer_load_lds((skip_low && q >= LA / 2) ? rA0 : ra,
+                                               NS_LDS_PTR(slot + (4 * q + w) * 64), 16,
                                                voA[q], so, 0, 0);
 #pragma unroll
     for (int q = 0; q < LB; ++q)
@@ -116,6 +127,11 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
     __builtin_amdgcn_s_waitcnt(wait_vm_lgkm0(LPS));
     __builtin_amdgcn_s_barrier();
     __builtin_amdgcn_sched_barrier(0);
+    if (LOWIDLE && !mfma_wave) {          // loads only; the same barriers as the others
+      issue(refill, kt + 2);
+      __builtin_amdgcn_sched_barrier(0);
+      return;
+    }
     uint4 af[BM], bf[BN];
 #pragma unroll
     for (int b = 0; b < BM; ++b) af[b] = cur[fa + 64 * b];
@@ -126,7 +142,7 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
     for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
       for (int bn = 0; bn < BN; ++bn)
-        if (!PARTIAL || (bm < nvr && bn < nvc))
+        if (!PARTIAL || (bm < nvr && bn < nvc && diag_off + 16 * (bm - bn) <= 15))
           acc[bm][bn] = Mfma16<TI>::op(af[bm], bf[bn], acc[bm][bn]);
     if (!PARTIAL) {
       __builtin_amdgcn_sched_group_barrier(0x100, NDS, 0);                 // LDS reads
@@ -158,6 +174,60 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
   int ldv = ld;
   asm volatile("" : "+v"(ldv));
   float rs = 0.0f;
+  typedef TI v4 __attribute__((ext_vector_type(4)));
+  if (!PARTIAL && !LOWIDLE && !cross) {
+    // Tiles off the diagonal: the tile's own columns are stored from registers (four
+    // rows per lane); its mirror image goes through LDS.  Each wave stages its
+    // 128 x 64 block in two halves of 64 rows, row-major (64 values + 8 of padding
+    // per row), in the now idle ring (waves 0, 1 in slot 0, waves 2, 3 in slot 1),
+    // and reads back 16-byte runs of a row: a row of the block is a 128-byte run of
+    // one column of the mirror image, so the mirror is written in whole lines.
+    // Only the wave that wrote a half reads it, so wave-local ordering suffices.
+    constexpr int SLD = 72;
+    constexpr int LGKM0 = 0xF | (0x3 << 14) | (0x7 << 4);   // lgkmcnt(0) only
+    __syncthreads();                                        // the ring is free
+    TI *stg = reinterpret_cast<TI *>(w < 2 ? s0 : s1) + (w & 1) * 64 * SLD;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int bm = 4 * h + b;
+#pragma unroll
+        for (int bn = 0; bn < BN; ++bn) {
+          const int gc = j0 + wn + 16 * bn + l16;
+          const int r0 = wm + 16 * bm + 4 * g;
+          v4 ov;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            float v = acc[bm][bn][e];
+            if (EPI == EPI_SQUARE) {
+              rs += v * v;
+              v = c3 * v;
+            }
+            ov[e] = from_f32<TI>(v);
+            stg[(16 * b + 4 * g + e) * SLD + 16 * bn + l16] = ov[e];
+          }
+          *reinterpret_cast<v4 *>(Out + (int64_t)gc * ldv + i0 + r0) = ov;
+        }
+      }
+      __builtin_amdgcn_s_waitcnt(LGKM0);
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int it = 0; it < 8; ++it) {
+        const int e = lane + 64 * it, rr = e >> 3, ch = e & 7;
+        const uint4 v = *reinterpret_cast<const uint4 *>(stg + rr * SLD + 8 * ch);
+        *reinterpret_cast<uint4 *>(Out + (int64_t)(i0 + wm + 64 * h + rr) * ldv + j0 + wn +
+                                   8 * ch) = v;
+      }
+      __builtin_amdgcn_s_waitcnt(LGKM0);
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (EPI == EPI_SQUARE) {
+      const float tot = block_sum256(2.0f * rs, red);
+      if (tid == 0) atomicAdd(racc, resid_fixed(tot));
+    }
+    return;
+  }
 #pragma unroll
   for (int bm = 0; bm < BM; ++bm)
 #pragma unroll
@@ -168,7 +238,6 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
       TI *col = Out + (int64_t)gc * ldv + i0;
       TI *mir = Out + (int64_t)(i0 + r0) * ldv + gc;
       if (!cross) {
-        typedef TI v4 __attribute__((ext_vector_type(4)));
         v4 ov;
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -224,17 +293,36 @@ void ns_gemm_rect_kernel(const Tile *__restrict__ tiles, const SubDesc *__restri
   TI *Out = buf_ptr<TI>(ws, d, (cur + (EPI == EPI_SQUARE ? 1 : 2)) % 3);
   const int i0 = t.ti * RT_M, j0 = t.tj * RT_N;
   if (threadIdx.x == 0) {
-    const int rows = (ld - i0 < RT_M ? ld - i0 : RT_M), cols = (ld - j0 < RT_N ? ld - j0 : RT_N);
-    atomicAdd(flop_units, (unsigned long long)((rows / 32) * (cols / 32) * (ld / 64)));
+    // the 16 x 16 blocks the four waves execute (ns_gemm_rect_body's predicates)
+    const bool full = i0 + RT_M <= ld && j0 + RT_N <= ld;
+    unsigned blocks = 0;
+    for (int w = 0; w < 4; ++w) {
+      const int wm = (w >> 1) * 128, wn = (w & 1) * 64;
+      if (full) {
+        blocks += (i0 == j0 && wm >= 128) ? 0u : 32u;
+        continue;
+      }
+      int nvr = (ld - i0 - wm) / 16, nvc = (ld - j0 - wn) / 16;
+      nvr = nvr < 0 ? 0 : (nvr > 8 ? 8 : nvr);
+      nvc = nvc < 0 ? 0 : (nvc > 4 ? 4 : nvc);
+      const int off = (i0 + wm) - (j0 + wn);
+      for (int bm = 0; bm < nvr; ++bm)
+        for (int bn = 0; bn < nvc; ++bn) blocks += (off + 16 * (bm - bn) <= 15) ? 1u : 0u;
+    }
+    atomicAdd(flop_units, (unsigned long long)blocks * (unsigned long long)(ld / 64));
   }
   __shared__ uint4 s0[RT_SLOT_U4], s1[RT_SLOT_U4], s2[RT_SLOT_U4];
   __shared__ float red[4];
-  if (i0 + RT_M <= ld && j0 + RT_N <= ld)
-    ns_gemm_rect_body<TI, EPI, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, red,
-                                      &S.racc);
+  const bool full = i0 + RT_M <= ld && j0 + RT_N <= ld;
+  if (full && i0 != j0)
+    ns_gemm_rect_body<TI, EPI, false, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2,
+                                             red, &S.racc);
+  else if (full)
+    ns_gemm_rect_body<TI, EPI, false, true>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2,
+                                            red, &S.racc);
   else
-    ns_gemm_rect_body<TI, EPI, true>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2, red,
-                                     &S.racc);
+    ns_gemm_rect_body<TI, EPI, true, false>(A, B, Out, ld, d.n, i0, j0, S.c1, S.c3, s0, s1, s2,
+                                            red, &S.racc);
 }
 
 }  // namespace nolsm

@@ -61,10 +61,14 @@ def tuned_tile_policy():
 
 class Runner:
     def __init__(self, inst, batch: int | None = None, mols=None, device="cuda",
-                 big_tile_min_npad="tuned", setup_products=None, persist=False, groups=None):
+                 big_tile_min_npad="tuned", setup_products=None, persist=False, groups=None,
+                 overlap=False):
         """groups: lists of molecules that share one submatrix each (combined
         submatrices, e.g. from nolsm_combine); then `batch` counts submatrices and
-        the stats hold one record per group, in the order of `groups`."""
+        the stats hold one record per group, in the order of `groups`.
+        overlap (with persist and several batches): two shared workspaces, and each
+        step gathers and sets up batch i + 1 on a second stream while batch i
+        iterates on the current one."""
         if not torch.cuda.is_available():
             raise RuntimeError("the NOLSM path runs on the GPU only")
         L.lib()
@@ -102,7 +106,10 @@ class Runner:
                                               persist=self.persist)
                           for b in self.batches]
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
-        self.workspace = torch.empty(need, dtype=torch.uint8, device=device)
+        self.overlap = bool(overlap) and self.persist and len(self.plans) > 1
+        self.workspaces = [torch.empty(need, dtype=torch.uint8, device=device)
+                           for _ in range(2 if self.overlap else 1)]
+        self.workspace = self.workspaces[0]
         self.persist_bufs = ([torch.empty(max(L.nolsm_plan_persist_bytes(p), 256),
                                           dtype=torch.uint8, device=device)
                               for p in self.plans] if self.persist else None)
@@ -114,8 +121,12 @@ class Runner:
         self.out2 = torch.zeros(2, dtype=torch.float64, device=device)
         self.bound = None
         self._feat = None
+        self._side = None
         if len(self.plans) == 1:
             self._bind(0)
+        if self.overlap:
+            for i in range(len(self.plans)):     # first binds upload the tables (not async)
+                self._bind(i)
 
     def __del__(self):
         try:
@@ -127,7 +138,8 @@ class Runner:
     def _bind(self, i):
         if self.bound != i:
             if self.persist:
-                L.nolsm_plan_bind_persist(self.plans[i], self.tables[i], self.workspace,
+                L.nolsm_plan_bind_persist(self.plans[i], self.tables[i],
+                                          self.workspaces[i % len(self.workspaces)],
                                           self.persist_bufs[i])
             else:
                 L.nolsm_plan_bind(self.plans[i], self.tables[i], self.workspace)
@@ -150,6 +162,10 @@ class Runner:
         p = self.plans[i]
         if regather or not self.keeps_setup:
             L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
+        self._sign_and_scatter(i, mu, sched, predictor, lower_factor)
+
+    def _sign_and_scatter(self, i, mu, sched, predictor, lower_factor):
+        p = self.plans[i]
         if predictor is not None:
             K = len(self.batches[i])
             if self._feat is None or self._feat.shape[0] < K:
@@ -166,12 +182,42 @@ class Runner:
         L.nolsm_scatter_density(p, self.dpat, self.D, self.H, self.S, self.stats[i])
 
     def run(self, mu=None, sched=None, energy=True, predictor=None, lower_factor=0.5,
-            regather=True):
+            regather=True, serial=False):
         mu = self.inst.mu if mu is None else mu
-        for i in range(len(self.plans)):
-            self.run_batch(i, mu, sched, predictor, lower_factor, regather)
+        if self.overlap and regather and not serial:
+            self._run_overlapped(mu, sched, predictor, lower_factor)
+        else:
+            for i in range(len(self.plans)):
+                self.run_batch(i, mu, sched, predictor, lower_factor, regather)
         if energy:
             L.nolsm_energy(self.dpat, self.D, self.H, self.S, self.col_traces, self.out2)
+
+    def _run_overlapped(self, mu, sched, predictor, lower_factor):
+        """Batch i + 1's gather and set-up (second stream) run while batch i iterates
+        (current stream).  Batches i and i + 2 share a workspace, so batch i + 2's
+        gather waits for batch i's write-back.  Every kernel sees the same inputs as
+        in the serial order, so the results are the same bit for bit."""
+        main = torch.cuda.current_stream()
+        if self._side is None:
+            self._side = torch.cuda.Stream(device=self.device)
+        side = self._side
+        side.wait_stream(main)
+        n = len(self.plans)
+        ready = [torch.cuda.Event() for _ in range(n)]
+        done = [torch.cuda.Event() for _ in range(n)]
+        for i in range(n):
+            self._bind(i)
+            p = self.plans[i]
+            with torch.cuda.stream(side):
+                if i >= 2:
+                    side.wait_event(done[i - 2])
+                L.nolsm_build_submatrices(p, self.dpat, self.H, self.S)
+                L.nolsm_setup_batched(p)
+                ready[i].record(side)
+            main.wait_event(ready[i])
+            self._sign_and_scatter(i, mu, sched, predictor, lower_factor)
+            done[i].record(main)
+        main.wait_stream(side)
 
     def mu_search(self, n_target, mu_lo, mu_hi, tol=0.5, max_iter=40, sched=None,
                   predictor=None, lower_factor=0.5, on_trial=None):
@@ -210,12 +256,12 @@ class Runner:
         side = torch.cuda.Stream()
         side.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(side):            # warm-up outside the capture
-            self.run(mu, sched, energy, predictor, lower_factor)
+            self.run(mu, sched, energy, predictor, lower_factor, serial=True)
         torch.cuda.current_stream().wait_stream(side)
         torch.cuda.synchronize()
         graph = torch.cuda.CUDAGraph()
-        with torch.cuda.graph(graph):
-            self.run(mu, sched, energy, predictor, lower_factor)
+        with torch.cuda.graph(graph):            # one stream: the batches in turn
+            self.run(mu, sched, energy, predictor, lower_factor, serial=True)
         return graph
 
     def check(self):
