@@ -99,7 +99,7 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub, mu=None):
     D = runner.D.cpu().numpy()
     st = runner.stats_host()
     pos = {int(k): i for i, k in enumerate(runner.mols)}
-    dmax, demax = 0.0, 0.0
+    dmax, demax, wrong = 0.0, 0.0, 0
     for k, ref in zip(ks, refs):
         got = np.zeros_like(ref["D_cols"])
         for a, I in enumerate(ref["members"]):
@@ -111,7 +111,11 @@ def oracle_sample(inst, runner, O, sample, flops_per_sub, mu=None):
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
         de = abs(float(st["tr_dh"][pos[int(k)]]) - ref["tr_dh"]) / int(inst.atoms[k])
         demax = max(demax, de)
-    err = {"max_abs_dD": dmax, "max_dE_per_atom": demax, "sampled_submatrices": int(len(ks))}
+        # wrong-sign guard: the eigenvalues the iteration sent to -1 against the
+        # oracle's count of eigenvalues below mu
+        wrong += int(st["n_neg"][pos[int(k)]] != ref["n_occ"])
+    err = {"max_abs_dD": dmax, "max_dE_per_atom": demax, "sampled_submatrices": int(len(ks)),
+           "wrong_sign_counts": wrong}
     return cpu, err
 
 

@@ -134,6 +134,11 @@ typedef struct {
   double scale;         /* b_k used */
   double tr_dh;         /* sum over molecule k's columns of D_ij H_ij (scatter) */
   double tr_ds;         /* same with S */
+  float tr_x;           /* Tr(X) of the converged iterate (its eigenvalues are near +-1) */
+  int32_t n_neg;        /* round((n - Tr X) / 2): eigenvalues the iteration sent to -1, i.e.
+                           its count of eigenvalues of S_k^-1 H_k below mu; an independent
+                           count (the inertia of H_k - mu S_k) exposes an eigenvalue that
+                           converged to the wrong sign */
 } nolsm_stats;
 
 /* Where a submatrix lives inside the workspace (for inspection by tests). */

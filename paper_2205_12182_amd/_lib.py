@@ -86,11 +86,12 @@ class MuSearch(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("done", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
-# nolsm_stats as a numpy record (48 bytes)
+# nolsm_stats as a numpy record (56 bytes)
 STATS_DTYPE = np.dtype([("n", "<i4"), ("status", "<i4"), ("iters_lo", "<i4"),
                         ("iters_fb", "<i4"), ("resid", "<f4"), ("fell_back", "<i4"),
-                        ("scale", "<f8"), ("tr_dh", "<f8"), ("tr_ds", "<f8")])
-assert STATS_DTYPE.itemsize == 48
+                        ("scale", "<f8"), ("tr_dh", "<f8"), ("tr_ds", "<f8"),
+                        ("tr_x", "<f4"), ("n_neg", "<i4")])
+assert STATS_DTYPE.itemsize == 56
 
 _lib = None
 

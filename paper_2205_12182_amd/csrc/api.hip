@@ -30,6 +30,7 @@ void launch_energy(const nolsm_pattern *pat, int nmol, const double *D_val, cons
                    const double *S_val, double *col_traces, double *out2, hipStream_t s);
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,
                   hipStream_t s);
+void launch_trace_x(const SubDesc *desc, SubState *st, int K, const char *ws, hipStream_t s);
 hipError_t energy_scratch_ptr(double **out);
 void launch_final_status(SubState *st, int K, int check_conv, hipStream_t s);
 void launch_features(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
@@ -532,6 +533,7 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
               p->gemm_flop, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
+  launch_trace_x(desc, st, p->K, p->ws, s);
   p->log.end(ev, s);
   ev = p->log.begin(T_PANEL, s);
   launch_density_columns(desc, st, p->K, p->max_npad, p->max_m, p->ws, sch.panel_steps, s);

@@ -60,7 +60,8 @@ struct SubState {
   int32_t extra_left;               // iterations still to run after reaching tol (-1: not reached)
   int32_t converged;
   float c1, c3;                     // coefficients of the next update X <- c1 X + c3 X Y
-  float pad_[2];
+  float tr_x;                       // Tr(X) of the final iterate
+  float pad_;
 };
 
 struct Tile { int32_t sub, ti, tj, pad; };

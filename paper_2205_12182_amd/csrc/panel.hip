@@ -428,7 +428,29 @@ __global__ void stats_kernel(const SubDesc *__restrict__ desc, const SubState *_
   r.scale = s.scale;
   r.tr_dh = 0.0;
   r.tr_ds = 0.0;
+  r.tr_x = s.tr_x;
+  r.n_neg = (int32_t)lrintf(0.5f * ((float)r.n - s.tr_x));
   out[i] = r;
+}
+
+// Tr(X) of every submatrix's final iterate, in its storage precision summed in FP32
+// (fixed order: one workgroup per submatrix).
+__global__ __launch_bounds__(256) void trace_x_kernel(const SubDesc *__restrict__ desc,
+                                                      SubState *__restrict__ st,
+                                                      const char *ws) {
+  const SubDesc d = desc[blockIdx.x];
+  SubState &s = st[blockIdx.x];
+  __shared__ float red[4];
+  const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
+  float t = 0.0f;
+  for (int i = threadIdx.x; i < d.n; i += 256) {
+    const int64_t o = (int64_t)i * d.npad + i;
+    if (s.prec == P_FP32) t += reinterpret_cast<const float *>(xb)[o];
+    else if (s.prec == P_FP16) t += (float)reinterpret_cast<const _Float16 *>(xb)[o];
+    else t += (float)reinterpret_cast<const __bf16 *>(xb)[o];
+  }
+  t = block_sum256(t, red);
+  if (threadIdx.x == 0) s.tr_x = s.status == 0 ? t : 0.0f;
 }
 
 // ------------------------------------------------------------------ host side
@@ -530,6 +552,10 @@ hipError_t energy_scratch_ptr(double **out) {
   }
   *out = ptrs[dev];
   return hipSuccess;
+}
+
+void launch_trace_x(const SubDesc *desc, SubState *st, int K, const char *ws, hipStream_t s) {
+  trace_x_kernel<<<K, 256, 0, s>>>(desc, st, ws);
 }
 
 void launch_stats(const SubDesc *desc, const SubState *st, int K, nolsm_stats *out,

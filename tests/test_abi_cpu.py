@@ -32,7 +32,7 @@ def test_struct_sizes_match_header():
     assert ctypes.sizeof(L.SubInfo) == 64
     assert ctypes.sizeof(L.Phase) == 20
     assert L.Schedule.phase.offset == 4 and L.Schedule.scale.offset == 96
-    assert L.STATS_DTYPE.itemsize == 48
+    assert L.STATS_DTYPE.itemsize == 56
     assert ctypes.sizeof(L.Pattern) == 8 * 8
 
 

@@ -75,6 +75,8 @@ def sampled_errors(inst, D, st, picks, index):
                 D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
         de = max(de, abs(float(st["tr_dh"][index[k]]) - ref["tr_dh"]) / int(inst.atoms[k]))
+        # no eigenvalue converged to the wrong sign
+        assert st["n_neg"][index[k]] == ref["n_occ"], (k, st["n_neg"][index[k]], ref["n_occ"])
     return dmax, de
 
 

@@ -162,3 +162,23 @@ def test_mu_search_against_oracle(gpu_ok, name, bracket, persist):
     assert gap > 0.05
     dmax, de, dn = compare(r, inst, D_ref, e_ref, ne_ref, f"{name} mu search result {m.mu}")
     assert dmax <= D_TOL and de <= E_TOL and dn <= 1e-3
+
+
+@pytest.mark.parametrize("name,mu,plain", [("c1", 0.0, False), ("c1", -1.2, True),
+                                           ("t_23", -0.4, False), ("t_23", 0.05, True)])
+def test_sign_counts_match_inertia(gpu_ok, name, mu, plain):
+    """Wrong-sign guard: the count of eigenvalues the iteration sent to -1,
+    round((n - Tr X) / 2), equals for every submatrix the number of generalized
+    eigenvalues of (H_k, S_k) below mu (the oracle's; by Sylvester's law the
+    inertia of H_k - mu S_k), inside the gap and inside the bands."""
+    inst, sp = spectra(name)
+    r = Runner(inst)
+    r.run(mu=mu, sched=plain_fp32_schedule() if plain else default_mixed_schedule())
+    assert r.check() == L.OK, r.last_check_message
+    st = r.stats_host()
+    want = np.array([int(np.sum(s["lam"] < mu)) for s in sp])
+    frac = np.abs(0.5 * (st["n"] - st["tr_x"]) - st["n_neg"])
+    print(f"[case] {name} mu {mu}: counts {st['n_neg'][:4]}..., largest distance of "
+          f"(n - Tr X)/2 from an integer {frac.max():.3f}", flush=True)
+    assert np.array_equal(st["n_neg"], want)
+    assert frac.max() < 0.25

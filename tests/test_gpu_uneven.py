@@ -90,6 +90,7 @@ def per_molecule_errors(inst, D, st, picks, pos):
             got[ref["offs"][a]:ref["offs"][a + 1], :] = \
                 D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
         dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
+        assert st["n_neg"][pos[k]] == ref["n_occ"], k      # no wrong-sign convergence
         dk = abs(float(st["tr_dh"][pos[k]]) - ref["tr_dh"])
         de_abs += dk
         atoms += int(inst.atoms[k])
