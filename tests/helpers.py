@@ -59,14 +59,14 @@ def dense(inst, val):
     return to_dense((inst.blk_dim, inst.blk_off, inst.colptr, inst.rowblk, inst.valoff), val)
 
 
-def golden_energies(name, inst):
+def golden_energies(name, inst, mu=None):
     """The oracle's per-molecule Tr(D H0), Tr(D S) column contributions for the whole
-    named workload (tests/golden/<name>_energies.npz, written by
+    named workload at the instance's mu (or `mu`) (tests/golden/, written by
     tests/golden/make_energies.py), checked against the instance's digest."""
     import os
-    from tests.golden.make_energies import instance_digest
+    from tests.golden.make_energies import golden_name, instance_digest
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                        f"{name}_energies.npz")
+                        golden_name(name, None if mu is None or mu == inst.mu else mu))
     with np.load(path, allow_pickle=False) as z:
         rec = {k: z[k] for k in z.files}
     assert str(rec["instance_sha256"]) == instance_digest(inst), f"{path}: other instance"
