@@ -364,7 +364,10 @@ def copy_calibration(torch, mib):
 
 
 def workload_text(name, inst, dims):
-    if name.startswith("c3"):
+    if name == "c5":
+        kind = (f"{inst.nmol} water-like molecules, {int(inst.blk_dim[0])} functions each "
+                f"(streamed in batches)")
+    elif name.startswith("c3"):
         kind = (f"{int((inst.blk_dim == 23).sum())} water-like molecules (23 functions) around a "
                 f"slab of {int((inst.blk_dim == 30).sum())} five-site units (30 functions)")
     else:
@@ -448,11 +451,12 @@ def main():
     dims = inst.submatrix_dims()
     log(f"workload {args.workload}: {inst.nmol} molecules, n_k {dims.min()}-{dims.max()}, "
         f"built in {time.perf_counter() - t:.1f} s")
-    runner = Runner(inst, batch=args.batch, persist=True, overlap=args.overlap)
+    runner = Runner(inst, batch=args.batch, persist="auto", overlap=args.overlap)
     overlap_used = runner.overlap
     log(f"{len(runner.plans)} batches, {len(runner.workspaces)} workspaces of "
-        f"{runner.workspace.numel() / 2**30:.1f} GiB, "
-        f"set-up buffers {sum(b.numel() for b in runner.persist_bufs) / 2**30:.1f} GiB")
+        f"{runner.workspace.numel() / 2**30:.1f} GiB, set-up buffers "
+        + (f"{sum(b.numel() for b in runner.persist_bufs) / 2**30:.1f} GiB" if runner.persist
+           else "none (they do not fit: a new mu gathers and sets up again)"))
 
     weights = os.path.join(os.path.dirname(learn.__file__), "data", "schedule_mlp.npz")
     if args.schedule is None:
@@ -520,7 +524,8 @@ def main():
     mu_iter = None
     if args.mu_trials > 0:
         # trial chemical potentials inside the gap at mu = 0, as the last iterations of
-        # a charge-neutrality search visit them; the first trial gathers and sets up
+        # a charge-neutrality search visit them; the first trial gathers and sets up, the
+        # others reuse the set-up where every batch keeps it
         mus = [step_mu + args.mu_trial_step * (t + 1) for t in range(args.mu_trials + 1)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -535,6 +540,7 @@ def main():
         per = (time.perf_counter() - t0) / args.mu_trials
         ne.append(runner.energy_host()[1])
         mu_iter = {"ms": round(per * 1e3, 2), "first_ms": round(first * 1e3, 2),
+                   "setup_kept": runner.keeps_setup,
                    "mus": [round(m, 4) for m in mus], "electrons_first_last": ne,
                    "n_elec": inst.n_elec, "failed": int((runner.stats_host()["status"] != 0).sum()),
                    "submatrices_per_s": round(K / per, 2),
@@ -579,7 +585,9 @@ def main():
                  "iters_mean": round(float(st_p["iters_lo"].mean()), 2),
                  "gemm_roofline_frac_fp32": round(tm_p["gemm_flop"] / (tm_p["ms_gemm"] * 1e-3) / 1e12 / FP32_PEAK, 4)
                  if tm_p["ms_gemm"] > 0 else None,
-                 "energy_per_atom_diff_vs_mixed": abs(e_plain - e_mixed) / inst.natoms}
+                 "energy_per_atom_diff_vs_mixed": abs(e_plain - e_mixed) / inst.natoms,
+                 "max_single_molecule_diff_vs_mixed": float(
+                     (np.abs(st_p["tr_dh"] - st["tr_dh"]) / inst.atoms[runner.mols]).max())}
         log(f"plain fp32: {json.dumps(plain)}")
 
     if args.calibrate_copy > 0:

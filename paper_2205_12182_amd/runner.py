@@ -66,6 +66,9 @@ class Runner:
         """groups: lists of molecules that share one submatrix each (combined
         submatrices, e.g. from nolsm_combine); then `batch` counts submatrices and
         the stats hold one record per group, in the order of `groups`.
+        persist: True keeps every batch's gather and set-up in buffers of its own (a new
+        chemical potential then reruns only the sign iteration); "auto" does so where
+        those buffers fit the free device memory.
         overlap (with persist and several batches): two shared workspaces, and each
         step gathers and sets up batch i + 1 on a second stream while batch i
         iterates on the current one."""
@@ -97,15 +100,19 @@ class Runner:
         self.big_tile_min_npad = big_tile_min_npad
         self.setup_products = setup_products
         self.persist = bool(persist)
-        if self.groups is not None:
-            self.plans = [L.nolsm_plan_create_groups(self.hpat, b, big_tile_min_npad,
-                                                     setup_products, persist=self.persist)
-                          for b in self.batches]
-        else:
-            self.plans = [L.nolsm_plan_create(self.hpat, b, big_tile_min_npad, setup_products,
-                                              persist=self.persist)
-                          for b in self.batches]
+        self.plans = self._create_plans()
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
+        if persist == "auto":
+            # keep every batch's set-up only where the set-up buffers fit beside the
+            # workspace in 90% of the free device memory
+            free, _ = torch.cuda.mem_get_info(torch.device(device))
+            keep = sum(L.nolsm_plan_persist_bytes(p) for p in self.plans)
+            if keep + need > 0.9 * free:
+                for p in self.plans:
+                    L.nolsm_plan_destroy(p)
+                self.persist = False
+                self.plans = self._create_plans()
+                need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
         self.overlap = bool(overlap) and self.persist and len(self.plans) > 1
         self.workspaces = [torch.empty(need, dtype=torch.uint8, device=device)
                            for _ in range(2 if self.overlap else 1)]
@@ -127,6 +134,15 @@ class Runner:
         if self.overlap:
             for i in range(len(self.plans)):     # first binds upload the tables (not async)
                 self._bind(i)
+
+    def _create_plans(self):
+        if self.groups is not None:
+            return [L.nolsm_plan_create_groups(self.hpat, b, self.big_tile_min_npad,
+                                               self.setup_products, persist=self.persist)
+                    for b in self.batches]
+        return [L.nolsm_plan_create(self.hpat, b, self.big_tile_min_npad, self.setup_products,
+                                    persist=self.persist)
+                for b in self.batches]
 
     def __del__(self):
         try:

@@ -71,3 +71,24 @@ def golden_energies(name, inst, mu=None):
         rec = {k: z[k] for k in z.files}
     assert str(rec["instance_sha256"]) == instance_digest(inst), f"{path}: other instance"
     return rec
+
+
+def sampled_errors(inst, D, st, picks, index, mu=None):
+    """Max |D - D_oracle| over the written columns of molecules `picks` and the
+    largest single-molecule |Tr(D_k H) difference| / atoms_k (no cancellation
+    between molecules); st[index[k]] is molecule k's record."""
+    from oracle import nolsm_oracle as O
+    dmax, de = 0.0, 0.0
+    for k in picks:
+        ref = O.submatrix_result(inst, k, mu=mu)
+        got = np.zeros_like(ref["D_cols"])
+        for a, I in enumerate(ref["members"]):
+            t = int(inst.colptr[k]) + a
+            dI, m = int(inst.blk_dim[I]), int(inst.blk_dim[k])
+            got[ref["offs"][a]:ref["offs"][a + 1], :] = \
+                D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
+        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
+        de = max(de, abs(float(st["tr_dh"][index[k]]) - ref["tr_dh"]) / int(inst.atoms[k]))
+        # no eigenvalue converged to the wrong sign
+        assert st["n_neg"][index[k]] == ref["n_occ"], (k, st["n_neg"][index[k]], ref["n_occ"])
+    return dmax, de

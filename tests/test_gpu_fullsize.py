@@ -15,12 +15,11 @@ import numpy as np
 import pytest
 import torch
 
-from oracle import nolsm_oracle as O
 from paper_2205_12182_amd import learn
 from paper_2205_12182_amd.runner import Runner, default_mixed_schedule, learned_schedule
 from workloads import get_config
 from workloads.water import water_box
-from tests.helpers import golden_energies
+from tests.helpers import golden_energies, sampled_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -58,26 +57,6 @@ def test_c2_full_size_sampled_parity(gpu_ok):
           f"{int(st['fell_back'].sum())})", flush=True)
     assert dmax <= D_TOL and de <= E_TOL
     assert de_sys <= E_TOL and dn_sys <= 1e-2 and de_each.max() <= SINGLE_E_TOL
-
-
-def sampled_errors(inst, D, st, picks, index):
-    """Max |D - D_oracle| over the written columns of molecules `picks` and the
-    largest single-molecule |Tr(D_k H) difference| / atoms_k (no cancellation
-    between molecules); st[index[k]] is molecule k's record."""
-    dmax, de = 0.0, 0.0
-    for k in picks:
-        ref = O.submatrix_result(inst, k)
-        got = np.zeros_like(ref["D_cols"])
-        for a, I in enumerate(ref["members"]):
-            t = int(inst.colptr[k]) + a
-            dI, m = int(inst.blk_dim[I]), int(inst.blk_dim[k])
-            got[ref["offs"][a]:ref["offs"][a + 1], :] = \
-                D[inst.valoff[t]:inst.valoff[t] + dI * m].reshape(m, dI).T
-        dmax = max(dmax, float(np.abs(got - ref["D_cols"]).max()))
-        de = max(de, abs(float(st["tr_dh"][index[k]]) - ref["tr_dh"]) / int(inst.atoms[k]))
-        # no eigenvalue converged to the wrong sign
-        assert st["n_neg"][index[k]] == ref["n_occ"], (k, st["n_neg"][index[k]], ref["n_occ"])
-    return dmax, de
 
 
 def test_near_maximum_submatrices(gpu_ok):

@@ -14,8 +14,9 @@
 
 The diagonal shift delta of S is a property of (workload, seed).  For the named
 workloads it is tabulated (computed with workloads/shift_table.py, which runs the
-Lanczos estimate of lambda_min(S0) and rounds up to 1e-3) so that every machine
-builds bit-identical inputs without repeating the eigenvalue estimate.
+Lanczos estimate of lambda_min(S0) and rounds up to 1e-3; for c5 with the products
+on the GPU, --device cuda) so that every machine builds bit-identical inputs without
+repeating the eigenvalue estimate.
 """
 from __future__ import annotations
 
@@ -29,6 +30,8 @@ SHIFTS = {
     ("c1_whole", 0): 0.0,     # lambda_min(S0) = 0.284939
     ("c2", 0): 0.696,         # lambda_min(S0) = -0.595187
     ("c3", 0): 1.17,          # lambda_min(S0) = -1.069404
+    ("c5", 0): 0.752,         # lambda_min(S0) = -0.651616 (Lanczos on the GPU, 140 steps,
+                              # residual 6.2e-09)
     ("t_small", 0): 0.0,      # lambda_min(S0) = 0.290016
     ("t_tiles", 0): 0.0,      # lambda_min(S0) = 0.254322
     ("t_23", 0): 0.586,       # lambda_min(S0) = -0.485117

@@ -44,6 +44,7 @@ import concurrent.futures
 import dataclasses
 import math
 import os
+import sys
 
 import numpy as np
 
@@ -259,9 +260,14 @@ def _fill_values(inst_dims, blk_off, rowblk, colblk, valoff, sites, fn_site, ons
 
     # chunks write disjoint slices; NumPy releases the GIL inside the array work
     workers = min(16, os.cpu_count() or 1)
+    # large instances (the 65,536-molecule box takes minutes) report their progress
+    report = H_val.size > (1 << 30)
     if workers > 1 and len(jobs) > 1:
         with concurrent.futures.ThreadPoolExecutor(workers) as ex:
-            list(ex.map(work, jobs))
+            for i, _ in enumerate(ex.map(work, jobs)):
+                if report and (i + 1) % max(1, len(jobs) // 10) == 0:
+                    print(f"[workloads] values: {i + 1}/{len(jobs)} chunks", file=sys.stderr,
+                          flush=True)
     else:
         for j in jobs:
             work(j)
@@ -309,6 +315,75 @@ def lambda_min(blk, S_val: np.ndarray, nfunc: int) -> float:
                         dtype=np.float64)
     w = eigsh(op, k=1, which="SA", tol=1e-6, v0=np.ones(nfunc), return_eigenvectors=False)
     return float(w[0])
+
+
+def lambda_min_lanczos(blk, S_val: np.ndarray, nfunc: int, device: str = "cuda",
+                       tol: float = 1e-8, max_steps: int = 800, check_every: int = 10,
+                       log=None):
+    """Smallest eigenvalue of a symmetric block-sparse matrix by Lanczos with full
+    reorthogonalisation, the products evaluated with PyTorch on `device` (for
+    instances whose host-side matrix-vector product is too slow, such as the
+    65,536-molecule box).  Returns (theta, residual, steps): theta is the smallest
+    Ritz value, an upper bound on lambda_min, and residual = |beta_j s_j| bounds the
+    distance from theta to the nearest eigenvalue."""
+    import torch
+    from scipy.linalg import eigh_tridiagonal
+    blk_dim, blk_off, colptr, rowblk, valoff = blk
+    nmol = blk_dim.shape[0]
+    dev = torch.device(device)
+    colblk = np.repeat(np.arange(nmol), np.diff(colptr))
+    shapes = np.stack([blk_dim[rowblk], blk_dim[colblk]], axis=1)
+    S_dev = torch.from_numpy(S_val).to(dev)
+    groups = []
+    for dI, dJ in np.unique(shapes, axis=0):
+        dI, dJ = int(dI), int(dJ)
+        sel = np.nonzero((shapes[:, 0] == dI) & (shapes[:, 1] == dJ))[0]
+        step = max(1, (1 << 25) // (dI * dJ))
+        for a in range(0, sel.size, step):
+            s = sel[a:a + step]
+            groups.append((dI, dJ,
+                           torch.from_numpy(valoff[s]).to(dev),
+                           torch.from_numpy(blk_off[rowblk[s]]).to(dev),
+                           torch.from_numpy(blk_off[colblk[s]]).to(dev)))
+
+    def matvec(x):
+        y = torch.zeros_like(x)
+        for dI, dJ, vo, ro, co in groups:
+            idx = vo[:, None] + torch.arange(dI * dJ, device=dev)[None, :]
+            B = S_dev[idx].view(-1, dJ, dI)                       # B[t, c, r] = A_{I r, J c}
+            xr = x[ro[:, None] + torch.arange(dI, device=dev)[None, :]]
+            contrib = torch.bmm(B, xr.unsqueeze(-1)).squeeze(-1)  # (A^T x)_J = (A x)_J
+            y.index_add_(0, (co[:, None] + torch.arange(dJ, device=dev)[None, :]).reshape(-1),
+                         contrib.reshape(-1))
+        return y
+
+    Q = torch.empty((max_steps + 1, nfunc), dtype=torch.float64, device=dev)
+    Q[0] = 1.0 / math.sqrt(nfunc)
+    alpha, beta = [], []
+    theta, resid = float("nan"), float("inf")
+    for j in range(max_steps):
+        w = matvec(Q[j])
+        a = float(torch.dot(w, Q[j]))
+        w -= a * Q[j]
+        if j > 0:
+            w -= beta[-1] * Q[j - 1]
+        for _ in range(2):                                      # full reorthogonalisation
+            w -= Q[:j + 1].T @ (Q[:j + 1] @ w)
+        b = float(torch.linalg.vector_norm(w))
+        alpha.append(a)
+        beta.append(b)
+        if (j + 1) % check_every == 0 or b == 0.0 or j + 1 == max_steps:
+            ev, vec = eigh_tridiagonal(np.asarray(alpha), np.asarray(beta[:-1]),
+                                       select="i", select_range=(0, 0))
+            theta, resid = float(ev[0]), abs(b * float(vec[-1, 0]))
+            if log is not None:
+                log(f"Lanczos step {j + 1}: theta {theta:.9f}, residual {resid:.2e}")
+            if resid <= tol * max(1.0, abs(theta)):
+                return theta, resid, j + 1
+        if b == 0.0:
+            break
+        Q[j + 1] = w / b
+    return theta, resid, len(alpha)
 
 
 def shift_for(lmin: float) -> float:
