@@ -392,6 +392,9 @@ def main():
                     help="submatrices the oracle solves on the host (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="timed replays of the step captured as a HIP graph (0: skip)")
+    ap.add_argument("--factor-tiles", choices=("fp32", "fp64"), default="fp32",
+                    help="precision of the tile products of the set-up's Cholesky factorisation "
+                         "and inverse (FP64 storage either way)")
     ap.add_argument("--overlap", action="store_true",
                     help="gather and set up batch i + 1 on a second stream while batch i "
                          "iterates (two shared workspaces; measured no faster on c2)")
@@ -451,7 +454,9 @@ def main():
     dims = inst.submatrix_dims()
     log(f"workload {args.workload}: {inst.nmol} molecules, n_k {dims.min()}-{dims.max()}, "
         f"built in {time.perf_counter() - t:.1f} s")
-    runner = Runner(inst, batch=args.batch, persist="auto", overlap=args.overlap)
+    runner = Runner(inst, batch=args.batch, persist="auto", overlap=args.overlap,
+                    factor_tiles=L.FACTOR_FP64 if args.factor_tiles == "fp64" else
+                    L.FACTOR_FP32_TILES)
     overlap_used = runner.overlap
     log(f"{len(runner.plans)} batches, {len(runner.workspaces)} workspaces of "
         f"{runner.workspace.numel() / 2**30:.1f} GiB, set-up buffers "
@@ -626,7 +631,9 @@ def main():
                                 (", learned lower bound -> scaled iteration (cap 16)"
                                  if args.schedule == "learned" else ", unscaled") +
                                 ", Gershgorin scale, FP32 fallback and panel step, FP64 "
-                                "Cholesky/L^-1/D columns/traces, set-up and panel products on "
+                                "Cholesky/L^-1 storage (tile products on " +
+                                ("FP64" if args.factor_tiles == "fp64" else "FP32") +
+                                " MFMAs), FP64 D columns/traces, set-up and panel products on "
                                 "FP16 MFMAs with split (hi + 2^-11 lo) FP32-class operands"),
                    "iters_mean": round(float(st["iters_lo"].mean()), 2),
                    "fallbacks": int(st["fell_back"].sum()),

@@ -171,7 +171,12 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
  * setup_products: how M_k = L^-1 T_k(H) L^-T is formed from the FP64 factor.
  * 0 (default): FP16 MFMAs on split operands (x = hi + 2^-11 lo, three partial
  * products, FP32 sums; every term within about 3 * 2^-22 of its exact value).
- * 1: FP32 operands on FP32 MFMAs.  Other values: NOLSM_EINVAL. */
+ * 1: FP32 operands on FP32 MFMAs.  Other values: NOLSM_EINVAL.
+ * factor_tiles: the large tile products of the Cholesky factorisation of T_k(S)
+ * (trailing updates) and of L^-1 (outer block products); L and L^-1 are stored in
+ * FP64 either way.  0 (default): FP32 MFMAs on operands rounded to FP32, FP32 sums
+ * (L^-1 S L^-T - I of a few 1e-7, density columns within about 1e-7 of the FP64
+ * factor's).  1: FP64 MFMAs throughout.  Other values: NOLSM_EINVAL. */
 typedef struct {
   int32_t big_tile_min_npad;
   int32_t setup_products;
@@ -181,7 +186,8 @@ typedef struct {
                                      with nolsm_plan_bind_persist), so they survive while
                                      other plans use the shared workspace; a chemical-
                                      potential search then sets each batch up once.     */
-  int32_t reserved[5];            /* must be zero */
+  int32_t factor_tiles;
+  int32_t reserved[4];            /* must be zero */
 } nolsm_plan_options;
 
 /* nolsm_plan_create with options (host pointer; NULL = defaults).

@@ -16,7 +16,7 @@ void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mo
                    const double *H_val, const double *S_val, bool split_h, char *ws,
                    hipStream_t stream);
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  bool fp32_products, char *ws, hipStream_t s);
+                  bool fp32_products, bool factor_fp32, char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                  char *ws, double mu, const nolsm_schedule &sch, bool have_scale,
                  EventLog *log, double flop, hipStream_t s);
@@ -51,6 +51,7 @@ struct nolsm_plan {
   std::vector<Tile> tiles;      // the tile lists of TileSet, back to back
   int32_t list_end[NTILELIST] = {};
   bool setup_fp32 = false;      // set-up products on FP32 MFMAs instead of split FP16
+  bool factor_fp64 = false;     // factorisation and inverse tile products on FP64 MFMAs
   bool persist = false;         // M_k and L^-1 in the plan's own buffer (offsets off_h, off_s
                                 // of desc[] are then relative to that buffer)
   size_t persist_bytes = 0;
@@ -139,9 +140,9 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
                                const int32_t *grp_mols, int32_t K, const nolsm_plan_options *opt,
                                nolsm_plan **out) {
   int big_min = BIG_TILE_MIN_NPAD;
-  bool setup_fp32 = false, persist = false;
+  bool setup_fp32 = false, persist = false, factor_fp64 = false;
   if (opt) {
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
       if (opt->reserved[i] != 0)
         return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: reserved option field %d is not zero", i);
     if (opt->setup_products != 0 && opt->setup_products != 1)
@@ -150,9 +151,13 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
     if (opt->persist != 0 && opt->persist != 1)
       return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: persist must be 0 or 1, got %d",
                   opt->persist);
+    if (opt->factor_tiles != 0 && opt->factor_tiles != 1)
+      return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: factor_tiles must be 0 or 1, got %d",
+                  opt->factor_tiles);
     if (opt->big_tile_min_npad >= 0) big_min = opt->big_tile_min_npad;
     setup_fp32 = opt->setup_products == 1;
     persist = opt->persist == 1;
+    factor_fp64 = opt->factor_tiles == 1;
   }
   if (!pat->blk_dim || !pat->blk_off || !pat->colptr || !pat->rowblk || !pat->valoff)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: pattern arrays must be set (host copies)");
@@ -161,6 +166,7 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
   p->K = K;
   p->nmol = pat->nmol;
   p->setup_fp32 = setup_fp32;
+  p->factor_fp64 = factor_fp64;
   p->persist = persist;
   p->desc.resize(K);
   size_t off = 0;
@@ -522,7 +528,7 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   const TileSet ts = tile_set(p, tiles);
   if (!p->setup_done) {
     ev = p->log.begin(T_SETUP, s);
-    launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, p->ws, s);
+    launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, !p->factor_fp64, p->ws, s);
     p->log.end(ev, s);
     p->setup_done = true;
     p->scale_ready = false;
@@ -548,7 +554,8 @@ nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   const int ev = p->log.begin(T_SETUP, s);
-  launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->setup_fp32, p->ws, s);
+  launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->setup_fp32, !p->factor_fp64,
+               p->ws, s);
   p->log.end(ev, s);
   p->setup_done = true;
   p->scale_ready = false;

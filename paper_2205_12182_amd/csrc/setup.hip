@@ -418,10 +418,128 @@ __device__ __forceinline__ void acc128_foreach(d4 acc[2][4], F f) {
         f(wm + 16 * i + (lane >> 4) + 4 * q, wn + 16 * j + (lane & 15), acc[i][j][q]);
 }
 
+// The same 128 x 128 tile product on FP32 MFMAs (v_mfma_f32_16x16x4_f32, twice the
+// FP64 rate): the FP64 operands are rounded to FP32 as they are staged in LDS and the
+// products are summed in FP32; the caller applies the result to its FP64 matrix.
+// Rounding the factor's trailing updates and the inverse's outer products this way
+// leaves L^-1 S L^-T - I at a few 1e-7 (an FP32 factorisation), which moves the
+// density columns by about 1e-7 and a molecule's energy by about 1e-7 Ha/atom, far
+// below the FP16 rounding of the sign iteration.  The input layout of the FP32
+// instruction is that of the FP64 one; its output puts D(i, j) in lane j + 16 (i / 4),
+// register i % 4.  LDS rows are padded by 16 floats, so the four 16-lane groups of a
+// fragment read (consecutive k) fall on different banks.
+constexpr int LDQF = 128 + 16;
+typedef float Stage128f[KS64 * LDQF];
+
+template <bool TB>
+__device__ __forceinline__ bool tile128_f32(const double *__restrict__ A, int64_t lda,
+                                            const double *__restrict__ B, int64_t ldb, int nA,
+                                            int nB, int k0, int k1, f4x acc[2][4], Stage128f *sA,
+                                            Stage128f *sB, bool lower = false) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
+  const bool idle = wm >= nA || wn >= nB || (lower && wm + 31 < wn);
+  double ra[4], rb[4];
+  auto load = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
+      ra[q] = (m < nA) ? A[(int64_t)(k + kk) * lda + m] : 0.0;
+      if (!TB) {
+        rb[q] = (m < nB) ? B[(int64_t)(k + kk) * ldb + m] : 0.0;
+      } else {
+        const int kt = idx & 15, n = idx >> 4;
+        rb[q] = (n < nB) ? B[(int64_t)n * ldb + k + kt] : 0.0;
+      }
+    }
+  };
+  auto store = [&](int b) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
+      sA[b][kk * LDQF + m] = (float)ra[q];
+      if (!TB)
+        sB[b][kk * LDQF + m] = (float)rb[q];
+      else
+        sB[b][(idx & 15) * LDQF + (idx >> 4)] = (float)rb[q];
+    }
+  };
+  if (k0 >= k1) return idle;
+  load(k0);
+  store(0);
+  __syncthreads();
+  int b = 0;
+  for (int k = k0; k < k1; k += KS64) {
+    const bool more = k + KS64 < k1;
+    if (more) load(k + KS64);
+    if (!idle) {
+#pragma unroll
+      for (int kk = 0; kk < KS64; kk += 4) {
+        const int kr = kk + (lane >> 4);
+        float a[2], bb[4];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) a[t] = sA[b][kr * LDQF + wm + 16 * t + (lane & 15)];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) bb[t] = sB[b][kr * LDQF + wn + 16 * t + (lane & 15)];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], bb[j], acc[i][j], 0, 0, 0);
+      }
+    }
+    if (more) store(b ^ 1);
+    __syncthreads();
+    b ^= 1;
+  }
+  return idle;
+}
+
+template <typename F>
+__device__ __forceinline__ void acc128f_foreach(f4x acc[2][4], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        f(wm + 16 * i + 4 * (lane >> 4) + q, wn + 16 * j + (lane & 15), (double)acc[i][j][q]);
+}
+
+// One 128 x 128 tile product in FP64 or (F32) FP32 MFMAs; f(r, c, value) visits the
+// result unless every wave was idle (then nothing is to be applied).
+template <bool TB, bool F32, typename F>
+__device__ __forceinline__ void tile128(const double *__restrict__ A, int64_t lda,
+                                        const double *__restrict__ B, int64_t ldb, int nA, int nB,
+                                        int k0, int k1, bool lower, F f) {
+  if constexpr (F32) {
+    __shared__ Stage128f sA[2], sB[2];
+    f4x acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
+    if (tile128_f32<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
+    acc128f_foreach(acc, f);
+  } else {
+    __shared__ Stage128 sA[2], sB[2];
+    d4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    if (tile128_f64<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
+    acc128_foreach(acc, f);
+  }
+}
+
 // Trailing update of the outer Cholesky blocks on 128 x 128 tiles:
 //   A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s],  tiles (ti, tj) of 128 with ti >= tj
 // starting at row/column m0 (a multiple of 128).  A 64 x 64 FP64 tile reads
 // 6.5 flop per byte of its panels; the 128 x 128 tile doubles that.
+template <bool F32>
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int m0,
                        int rows) {
@@ -432,21 +550,13 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
   if (ti < tj || k0 >= ld) return;
   const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
   if (r0 >= ld || c0 >= ld) return;
-  __shared__ Stage128 sA[2], sB[2];
-  d4 acc[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  if (tile128_f64<false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, acc, sA, sB,
-                         ti == tj))
-    return;                                       // nothing to subtract
-  acc128_foreach(acc, [&](int r, int c, double v) {
-    if (r0 + r < ld && c0 + c < ld) {
-      double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
-      *p = *p - v;
-    }
-  });
+  tile128<false, F32>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj,
+                      [&](int r, int c, double v) {
+                        if (r0 + r < ld && c0 + c < ld) {
+                          double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
+                          *p = *p - v;
+                        }
+                      });
 }
 
 // ------------------------------------------------------------------ L^-1 in place
@@ -501,6 +611,7 @@ __global__ __launch_bounds__(256) void trtri_update_kernel(const SubDesc *__rest
 // (blockIdx.x = row tile + rows * column tile, two column tiles).
 constexpr int TW = 256;                 // outer block width of the inverse
 
+template <bool F32>
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
   int tile, sub;
@@ -511,20 +622,15 @@ void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   const int r0 = J1 + ti * 128, c0 = tj * 128;
   if (r0 >= ld) return;
   double *T = reinterpret_cast<double *>(ws + d.off_lo);
-  __shared__ Stage128 sA[2], sB[2];
-  d4 acc[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
   // T[r0 + r, c0 + c] = sum_s L[r0 + r, J0 + s] X_JJ[s, c0 + c];  X_JJ[s, c] = 0 for s < c
-  tile128_f64<true>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
-                    ld - r0, 128, c0, TW, acc, sA, sB);
-  acc128_foreach(acc, [&](int r, int c, double v) {
-    if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = v;
-  });
+  // (an all-idle tile has no rows below ld: nothing to store)
+  tile128<true, F32>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
+                     ld - r0, 128, c0, TW, false, [&](int r, int c, double v) {
+                       if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = v;
+                     });
 }
 
+template <bool F32>
 __global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
 void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, int rows) {
   int tile, sub;
@@ -536,17 +642,10 @@ void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   if (r0 >= ld) return;
   const double *T = reinterpret_cast<const double *>(ws + d.off_lo);
   const int kend = (r0 + 128 < ld ? r0 + 128 : ld) - J1;       // X[i, k] = 0 for k > i
-  __shared__ Stage128 sA[2], sB[2];
-  d4 acc[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  tile128_f64<false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, acc, sA,
-                     sB);
-  acc128_foreach(acc, [&](int r, int c, double v) {
-    if (r0 + r < ld) Sb[(int64_t)(J0 + c0 + c) * ld + r0 + r] = -v;
-  });
+  tile128<false, F32>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, false,
+                      [&](int r, int c, double v) {
+                        if (r0 + r < ld) Sb[(int64_t)(J0 + c0 + c) * ld + r0 + r] = -v;
+                      });
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restrict__ desc,
@@ -648,8 +747,9 @@ void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s) {
 
 // ------------------------------------------------------------------ host launcher
 
-void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  bool fp32_products, char *ws, hipStream_t s) {
+template <bool F32>
+static void launch_factor(const SubDesc *desc, SubState *st, int K, int max_npad, char *ws,
+                          hipStream_t s) {
   const int nbmax = max_npad / NB;
   launch_reset_status(st, K, 0, s);
   // Blocked Cholesky with two levels: inside an outer block of OB columns each
@@ -674,8 +774,8 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     if (Jend < nbmax) {
       // Jend * 64 is a multiple of 256 here, so the 128-wide tiles start aligned
       const int m0 = Jend * NB, rows = (max_npad - m0 + 127) / 128;
-      chol_trail_kernel<<<dim3(rows * rows, K), T128_THREADS, 0, s>>>(desc, ws, J * NB, Jend * NB, m0,
-                                                             rows);
+      chol_trail_kernel<F32><<<dim3(rows * rows, K), T128_THREADS, 0, s>>>(desc, ws, J * NB,
+                                                                        Jend * NB, m0, rows);
     }
   }
   // L^-1 in place, outer blocks of TW columns right to left: the 64-wide steps
@@ -696,10 +796,19 @@ void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     }
     if (J1 < max_npad) {
       const int rows = (max_npad - J1 + 127) / 128;
-      trtri_outer_t_kernel<<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
-      trtri_outer_x_kernel<<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
+      trtri_outer_t_kernel<F32><<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
+      trtri_outer_x_kernel<F32><<<dim3(2 * rows, K), T128_THREADS, 0, s>>>(desc, ws, J0, rows);
     }
   }
+}
+
+// factor_fp32: the 128 x 128 tile products of the factorisation and the inverse on
+// FP32 MFMAs (tile128_f32); otherwise FP64 throughout.
+void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
+                  bool fp32_products, bool factor_fp32, char *ws, hipStream_t s) {
+  const int nbmax = max_npad / NB;
+  if (factor_fp32) launch_factor<true>(desc, st, K, max_npad, ws, s);
+  else launch_factor<false>(desc, st, K, max_npad, ws, s);
   // M = L^-1 H L^-T as two products: U = H L^-T, then M = L^-1 U
   if (!fp32_products) {
     prep_split_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);

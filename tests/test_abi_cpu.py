@@ -88,7 +88,7 @@ def test_plan_options_tile_policy():
     assert sizes[0] == sizes[2] and sizes[1] != sizes[0]
     opt = L.PlanOptions()
     opt.big_tile_min_npad = 0
-    opt.reserved[3] = 1    # reserved has 5 entries
+    opt.reserved[3] = 1    # reserved has 4 entries
     out = ctypes.c_void_p()
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
@@ -98,9 +98,15 @@ def test_plan_options_tile_policy():
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
     assert rc == L.EINVAL and "setup_products" in L.nolsm_last_error()
+    opt.setup_products = 0
+    opt.factor_tiles = 2
+    rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
+                                      ctypes.byref(opt), ctypes.byref(out))
+    assert rc == L.EINVAL and "factor_tiles" in L.nolsm_last_error()
     for sp in (L.SETUP_SPLIT_FP16, L.SETUP_FP32):
-        plan = L.nolsm_plan_create(hp, mols, setup_products=sp)
-        L.nolsm_plan_destroy(plan)
+        for ft in (L.FACTOR_FP32_TILES, L.FACTOR_FP64):
+            plan = L.nolsm_plan_create(hp, mols, setup_products=sp, factor_tiles=ft)
+            L.nolsm_plan_destroy(plan)
 
 
 def test_plan_rejects_bad_molecule():
