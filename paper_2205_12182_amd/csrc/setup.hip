@@ -429,7 +429,8 @@ __device__ __forceinline__ void acc128_foreach(d4 acc[2][4], F f) {
 // register i % 4.  LDS rows are padded by 16 floats, so the four 16-lane groups of a
 // fragment read (consecutive k) fall on different banks.
 constexpr int LDQF = 128 + 16;
-typedef float Stage128f[KS64 * LDQF];
+constexpr int KSF = 16;             // k per LDS stage of the FP32 tiles (32 measured no faster)
+typedef float Stage128f[KSF * LDQF];
 
 template <bool TB>
 __device__ __forceinline__ bool tile128_f32(const double *__restrict__ A, int64_t lda,
@@ -439,29 +440,30 @@ __device__ __forceinline__ bool tile128_f32(const double *__restrict__ A, int64_
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
   const bool idle = wm >= nA || wn >= nB || (lower && wm + 31 < wn);
-  double ra[4], rb[4];
+  constexpr int NQ = KSF * 128 / T128_THREADS;     // elements per thread per operand and stage
+  double ra[NQ], rb[NQ];
   auto load = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
-      ra[q] = (m < nA) ? A[(int64_t)(k + kk) * lda + m] : 0.0;
+      ra[q] = (m < nA && k + kk < k1) ? A[(int64_t)(k + kk) * lda + m] : 0.0;
       if (!TB) {
-        rb[q] = (m < nB) ? B[(int64_t)(k + kk) * ldb + m] : 0.0;
+        rb[q] = (m < nB && k + kk < k1) ? B[(int64_t)(k + kk) * ldb + m] : 0.0;
       } else {
-        const int kt = idx & 15, n = idx >> 4;
-        rb[q] = (n < nB) ? B[(int64_t)n * ldb + k + kt] : 0.0;
+        const int kt = idx & (KSF - 1), n = idx / KSF;
+        rb[q] = (n < nB && k + kt < k1) ? B[(int64_t)n * ldb + k + kt] : 0.0;
       }
     }
   };
   auto store = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < NQ; ++q) {
       const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
       sA[b][kk * LDQF + m] = (float)ra[q];
       if (!TB)
         sB[b][kk * LDQF + m] = (float)rb[q];
       else
-        sB[b][(idx & 15) * LDQF + (idx >> 4)] = (float)rb[q];
+        sB[b][(idx & (KSF - 1)) * LDQF + idx / KSF] = (float)rb[q];
     }
   };
   if (k0 >= k1) return idle;
@@ -469,12 +471,12 @@ __device__ __forceinline__ bool tile128_f32(const double *__restrict__ A, int64_
   store(0);
   __syncthreads();
   int b = 0;
-  for (int k = k0; k < k1; k += KS64) {
-    const bool more = k + KS64 < k1;
-    if (more) load(k + KS64);
+  for (int k = k0; k < k1; k += KSF) {
+    const bool more = k + KSF < k1;
+    if (more) load(k + KSF);
     if (!idle) {
 #pragma unroll
-      for (int kk = 0; kk < KS64; kk += 4) {
+      for (int kk = 0; kk < KSF; kk += 4) {
         const int kr = kk + (lane >> 4);
         float a[2], bb[4];
 #pragma unroll
