@@ -68,6 +68,12 @@ typedef struct {
   const int64_t *valoff;
 } nolsm_pattern;
 
+/* Form of the sign argument (Eq. 8; see nolsm_plan_options.form). */
+typedef enum {
+  NOLSM_FORM_SYM = 0,      /* M_k - mu I = L^-1 (H_k - mu S_k) L^-T, symmetric          */
+  NOLSM_FORM_LITERAL = 1   /* A_k = S_k^-1 H_k - mu I, as Eq. 8 prints it            */
+} nolsm_form;
+
 /* Arithmetic of a sign-iteration phase. */
 typedef enum {
   NOLSM_PREC_FP32 = 0,   /* FP32 operands, FP32 MFMA accumulate               */
@@ -78,9 +84,10 @@ typedef enum {
 /* Iteration schedule for nolsm_sign_batched.
  *
  * The argument of sign() is formed in the congruent symmetric form
- *   M_k = L^-1 (H_k - mu S_k) L^-T,  S_k = L L^T (FP64 Cholesky),
+ *   M_k = L^-1 (H_k - mu S_k) L^-T,  S_k = L L^T (Cholesky, FP64 storage),
  * which has the spectrum of S_k^-1 H_k - mu I (Eq. 8) and gives the same density
- * in exact arithmetic: T_k(D) = 1/2 L^-T (I - sign(M_k)) L^-1.
+ * in exact arithmetic: T_k(D) = 1/2 L^-T (I - sign(M_k)) L^-1 (plans of the literal
+ * form iterate on S_k^-1 H_k - mu I itself, see nolsm_plan_options.form).
  * X_0 = M_k / b_k with b_k >= rho(M_k) (Gershgorin bound unless `scale` is given).
  *
  * Phases run in order.  A phase with tol > 0 stops a submatrix once
@@ -172,6 +179,15 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
  * 0 (default): FP16 MFMAs on split operands (x = hi + 2^-11 lo, three partial
  * products, FP32 sums; every term within about 3 * 2^-22 of its exact value).
  * 1: FP32 operands on FP32 MFMAs.  Other values: NOLSM_EINVAL.
+ * form: NOLSM_FORM_SYM (0, default) iterates on the congruent symmetric matrix
+ * M_k - mu I = L^-1 (T_k(H0) - mu T_k(S)) L^-T and writes T_k(D) = 1/2 L^-T (I - X) L^-1
+ * (the same T_k(D) as Eq. 8 in exact arithmetic; half of every product is formed);
+ * NOLSM_FORM_LITERAL (1) evaluates Eq. 8 as printed: A_k = T_k(S)^-1 T_k(H0) - mu I
+ * (S^-1 H formed in FP64), the sign iteration on the non-symmetric A_k with general
+ * products (every tile), T_k(D) = 1/2 (I - sign(A_k)) T_k(S)^-1.  The literal form
+ * runs every phase of a schedule in one precision and Newton-Schulz steps only
+ * (nolsm_sign_batched returns NOLSM_EINVAL otherwise); it serves to check the
+ * identity of the two forms and is not tuned for speed.
  * factor_tiles: the large tile products of the Cholesky factorisation of T_k(S)
  * (trailing updates) and of L^-1 (outer block products); L and L^-1 are stored in
  * FP64 either way.  0 (default): FP32 MFMAs on operands rounded to FP32, FP32 sums
@@ -187,7 +203,8 @@ typedef struct {
                                      other plans use the shared workspace; a chemical-
                                      potential search then sets each batch up once.     */
   int32_t factor_tiles;
-  int32_t reserved[4];            /* must be zero */
+  int32_t form;                   /* nolsm_form */
+  int32_t reserved[3];            /* must be zero */
 } nolsm_plan_options;
 
 /* nolsm_plan_create with options (host pointer; NULL = defaults).

@@ -58,11 +58,12 @@ class SubInfo(ctypes.Structure):
 class PlanOptions(ctypes.Structure):
     _fields_ = [("big_tile_min_npad", ctypes.c_int32), ("setup_products", ctypes.c_int32),
                 ("persist", ctypes.c_int32), ("factor_tiles", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 4)]
+                ("form", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
 
 
 SETUP_SPLIT_FP16, SETUP_FP32 = 0, 1
 FACTOR_FP32_TILES, FACTOR_FP64 = 0, 1
+FORM_SYM, FORM_LITERAL = 0, 1
 
 
 class Timings(ctypes.Structure):
@@ -238,44 +239,46 @@ def schedule(phases, fallback_tol=0.05, fallback_iters=0, panel_steps=1, scale=N
 # ----------------------------------------------------------------------------- entry points
 
 def nolsm_plan_create(host_pattern: HostPattern, mols, big_tile_min_npad=None,
-                      setup_products=None, persist=False, factor_tiles=None) -> ctypes.c_void_p:
+                      setup_products=None, persist=False, factor_tiles=None,
+                      form=None) -> ctypes.c_void_p:
     """Plan for `mols`; big_tile_min_npad (optional) sets the tile policy,
     setup_products (optional) how M_k is formed (SETUP_SPLIT_FP16 or SETUP_FP32),
     persist keeps the set-up results in a buffer of the plan's own, and factor_tiles
     (optional) the precision of the factorisation's tile products (FACTOR_FP32_TILES
-    or FACTOR_FP64)."""
+    or FACTOR_FP64), form (optional) FORM_SYM or FORM_LITERAL."""
     mols = np.ascontiguousarray(mols, dtype=np.int32)
     out = ctypes.c_void_p()
     if (big_tile_min_npad is None and setup_products is None and not persist
-            and factor_tiles is None):
+            and factor_tiles is None and form is None):
         _ok(lib().nolsm_plan_create(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                     int(mols.size), ctypes.byref(out)))
     else:
-        opt = _options(big_tile_min_npad, setup_products, persist, factor_tiles)
+        opt = _options(big_tile_min_npad, setup_products, persist, factor_tiles, form)
         _ok(lib().nolsm_plan_create_ex(ctypes.byref(host_pattern.struct), mols.ctypes.data,
                                        int(mols.size), ctypes.byref(opt), ctypes.byref(out)))
     return out
 
 
-def _options(big_tile_min_npad, setup_products, persist, factor_tiles=None):
+def _options(big_tile_min_npad, setup_products, persist, factor_tiles=None, form=None):
     opt = PlanOptions()
     opt.big_tile_min_npad = -1 if big_tile_min_npad is None else int(big_tile_min_npad)
     opt.setup_products = SETUP_SPLIT_FP16 if setup_products is None else int(setup_products)
     opt.persist = 1 if persist else 0
     opt.factor_tiles = FACTOR_FP32_TILES if factor_tiles is None else int(factor_tiles)
+    opt.form = FORM_SYM if form is None else int(form)
     return opt
 
 
 def nolsm_plan_create_groups(host_pattern: HostPattern, groups, big_tile_min_npad=None,
                              setup_products=None, persist=False,
-                             factor_tiles=None) -> ctypes.c_void_p:
+                             factor_tiles=None, form=None) -> ctypes.c_void_p:
     """Plan one submatrix per group of molecules (lists of molecule indices)."""
     ptr = np.zeros(len(groups) + 1, dtype=np.int32)
     ptr[1:] = np.cumsum([len(g) for g in groups])
     flat = np.ascontiguousarray(np.concatenate([np.asarray(g, np.int32) for g in groups])
                                 if groups else np.zeros(0, np.int32), dtype=np.int32)
     out = ctypes.c_void_p()
-    opt = _options(big_tile_min_npad, setup_products, persist, factor_tiles)
+    opt = _options(big_tile_min_npad, setup_products, persist, factor_tiles, form)
     _ok(lib().nolsm_plan_create_groups(ctypes.byref(host_pattern.struct), ptr.ctypes.data,
                                        flat.ctypes.data, int(len(groups)), ctypes.byref(opt),
                                        ctypes.byref(out)))

@@ -16,12 +16,12 @@ void launch_gather(const SubDesc *desc, int K, int maxmem, const int32_t *mem_mo
                    const double *H_val, const double *S_val, bool split_h, char *ws,
                    hipStream_t stream);
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  bool fp32_products, bool factor_fp32, char *ws, hipStream_t s);
+                  bool fp32_products, bool factor_fp32, bool literal, char *ws, hipStream_t s);
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                  char *ws, double mu, const nolsm_schedule &sch, bool have_scale,
-                 EventLog *log, double flop, hipStream_t s);
+                 EventLog *log, double flop, bool literal, hipStream_t s);
 void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
-                            int max_m, char *ws, int panel_steps, hipStream_t s);
+                            int max_m, char *ws, int panel_steps, bool literal, hipStream_t s);
 void launch_scatter(const SubDesc *desc, const SubState *st, int K, int maxmem,
                     const int32_t *mem_mol, const int32_t *mem_loc, const int32_t *mem_srt,
                     const nolsm_pattern *pat, double *D_val, const double *H_val,
@@ -52,6 +52,7 @@ struct nolsm_plan {
   int32_t list_end[NTILELIST] = {};
   bool setup_fp32 = false;      // set-up products on FP32 MFMAs instead of split FP16
   bool factor_fp64 = false;     // factorisation and inverse tile products on FP64 MFMAs
+  bool literal = false;         // the literal form of Eq. 8 (NOLSM_FORM_LITERAL)
   bool persist = false;         // M_k and L^-1 in the plan's own buffer (offsets off_h, off_s
                                 // of desc[] are then relative to that buffer)
   size_t persist_bytes = 0;
@@ -140,9 +141,9 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
                                const int32_t *grp_mols, int32_t K, const nolsm_plan_options *opt,
                                nolsm_plan **out) {
   int big_min = BIG_TILE_MIN_NPAD;
-  bool setup_fp32 = false, persist = false, factor_fp64 = false;
+  bool setup_fp32 = false, persist = false, factor_fp64 = false, literal = false;
   if (opt) {
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 3; ++i)
       if (opt->reserved[i] != 0)
         return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: reserved option field %d is not zero", i);
     if (opt->setup_products != 0 && opt->setup_products != 1)
@@ -154,10 +155,13 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
     if (opt->factor_tiles != 0 && opt->factor_tiles != 1)
       return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: factor_tiles must be 0 or 1, got %d",
                   opt->factor_tiles);
+    if (opt->form != NOLSM_FORM_SYM && opt->form != NOLSM_FORM_LITERAL)
+      return fail(NOLSM_EINVAL, "nolsm_plan_create_ex: form must be 0 or 1, got %d", opt->form);
     if (opt->big_tile_min_npad >= 0) big_min = opt->big_tile_min_npad;
     setup_fp32 = opt->setup_products == 1;
     persist = opt->persist == 1;
     factor_fp64 = opt->factor_tiles == 1;
+    literal = opt->form == NOLSM_FORM_LITERAL;
   }
   if (!pat->blk_dim || !pat->blk_off || !pat->colptr || !pat->rowblk || !pat->valoff)
     return fail(NOLSM_EINVAL, "nolsm_plan_create: pattern arrays must be set (host copies)");
@@ -167,6 +171,7 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
   p->nmol = pat->nmol;
   p->setup_fp32 = setup_fp32;
   p->factor_fp64 = factor_fp64;
+  p->literal = literal;
   p->persist = persist;
   p->desc.resize(K);
   size_t off = 0;
@@ -307,7 +312,7 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
   for (int i = 0; i < K; ++i) {
     SubDesc &d = p->desc[i];
     const size_t np = (size_t)d.npad;
-    const size_t hbytes = (setup_fp32 ? 8 : 4) * np * np;
+    const size_t hbytes = ((setup_fp32 || literal) ? 8 : 4) * np * np;   // FP64 H first
     size_t &o = persist ? poff : off;
     d.off_h = (int64_t)o;
     o = align256(o + hbytes);
@@ -476,7 +481,7 @@ nolsm_status nolsm_build_submatrices(nolsm_plan *p, const nolsm_pattern *pat, co
   PLAN_PTRS
   const int ev = p->log.begin(T_GATHER, s);
   launch_gather(desc, p->K, p->maxmem, mem_mol, mem_loc, mem_srt, pat, H_val, S_val,
-                !p->setup_fp32, p->ws, s);
+                !(p->setup_fp32 || p->literal), p->ws, s);
   p->log.end(ev, s);
   p->setup_done = false;
   p->scale_ready = false;
@@ -522,13 +527,24 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
     sch.fallback_iters = 0;
   }
   if (!p->bound) return fail(NOLSM_EINVAL, "nolsm_sign_batched: plan not bound");
+  if (p->literal) {
+    for (int q = 0; q < sch.nphase; ++q) {
+      if (sch.phase[q].order == 3)
+        return fail(NOLSM_EINVAL, "nolsm_sign_batched: the literal form runs Newton-Schulz "
+                                  "steps only (phase %d has order 3)", q);
+      if (sch.phase[q].prec != sch.phase[0].prec)
+        return fail(NOLSM_EINVAL, "nolsm_sign_batched: the literal form runs every phase in one "
+                                  "precision (phase %d differs)", q);
+    }
+  }
   if (p->K == 0) return NOLSM_OK;
   PLAN_PTRS
   int ev;
   const TileSet ts = tile_set(p, tiles);
   if (!p->setup_done) {
     ev = p->log.begin(T_SETUP, s);
-    launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, !p->factor_fp64, p->ws, s);
+    launch_setup(desc, st, p->K, p->max_npad, ts, p->setup_fp32, !p->factor_fp64, p->literal,
+                 p->ws, s);
     p->log.end(ev, s);
     p->setup_done = true;
     p->scale_ready = false;
@@ -536,13 +552,14 @@ nolsm_status nolsm_sign_batched(nolsm_plan *p, double mu, const nolsm_schedule *
   ev = p->log.begin(T_SIGN, s);
   const bool have_scale = p->scale_ready && p->scale_mu == mu;
   launch_sign(desc, st, p->K, p->max_npad, ts, p->ws, mu, sch, have_scale, &p->log,
-              p->gemm_flop, s);
+              p->gemm_flop, p->literal, s);
   const nolsm_phase &lastph = sch.phase[sch.nphase - 1];
   launch_final_status(st, p->K, (lastph.tol > 0.0f && sch.fallback_iters == 0) ? 1 : 0, s);
   launch_trace_x(desc, st, p->K, p->ws, s);
   p->log.end(ev, s);
   ev = p->log.begin(T_PANEL, s);
-  launch_density_columns(desc, st, p->K, p->max_npad, p->max_m, p->ws, sch.panel_steps, s);
+  launch_density_columns(desc, st, p->K, p->max_npad, p->max_m, p->ws, sch.panel_steps,
+                         p->literal, s);
   p->log.end(ev, s);
   if (stats) launch_stats(desc, st, p->K, stats, s);
   return hip_check("nolsm_sign_batched");
@@ -555,7 +572,7 @@ nolsm_status nolsm_setup_batched(nolsm_plan *p, hipStream_t s) {
   PLAN_PTRS
   const int ev = p->log.begin(T_SETUP, s);
   launch_setup(desc, st, p->K, p->max_npad, tile_set(p, tiles), p->setup_fp32, !p->factor_fp64,
-               p->ws, s);
+               p->literal, p->ws, s);
   p->log.end(ev, s);
   p->setup_done = true;
   p->scale_ready = false;

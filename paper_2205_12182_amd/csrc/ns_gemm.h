@@ -34,8 +34,11 @@ typedef float f4x __attribute__((ext_vector_type(4)));
 
 // SQUARE: Z = c1 I + c3 X X (+ residual); UPDATE: X' = X Z; PLAIN_SYM: the plain
 // product of a symmetric result (upper tiles, mirrored); PLAIN_FULL: the plain
-// product, every tile, nothing mirrored.
-enum { EPI_SQUARE = 0, EPI_UPDATE = 1, EPI_PLAIN_SYM = 2, EPI_PLAIN_FULL = 3 };
+// product, every tile, nothing mirrored; FULL_SQUARE: SQUARE's epilogue on every
+// tile of a general (non-symmetric) product, nothing mirrored, the residual summed
+// over every element once.
+enum { EPI_SQUARE = 0, EPI_UPDATE = 1, EPI_PLAIN_SYM = 2, EPI_PLAIN_FULL = 3,
+       EPI_FULL_SQUARE = 4 };
 
 constexpr int NSLOT = 4;           // LDS ring slots (stages in flight: NSLOT - 1)
 // Word 3 of a raw (stride 0) buffer resource on CDNA: 32-bit data format, no
@@ -267,7 +270,7 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
   auto quarter = [&](int qi) -> TI * {
     return reinterpret_cast<TI *>(qi == 0 ? s0 : qi == 1 ? s1 : qi == 2 ? s2 : s3);
   };
-  constexpr bool MIRROR = EPI != EPI_PLAIN_FULL;
+  constexpr bool MIRROR = EPI != EPI_PLAIN_FULL && EPI != EPI_FULL_SQUARE;
   const bool diag_tile = MIRROR && (i0 == j0);
   // keep the row stride in a vector register so that the per-row store offsets
   // are formed with vector arithmetic instead of occupying scalar registers
@@ -287,7 +290,19 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
       for (int g = 0; g < 4; ++g) {
         const int r0 = wm + 32 * bm + 8 * g + 4 * h;
         TI o[4];
-        if (!diag_tile) {          // every element has r < c (global)
+        if (EPI == EPI_FULL_SQUARE) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int gr = i0 + r0 + e;
+            const bool diag = gr == gc;
+            float v = acc[bm][bn][4 * g + e];
+            if (gr < n && gc < n) {
+              const float df = v - (diag ? 1.0f : 0.0f);
+              rs += df * df;
+            }
+            o[e] = from_f32<TI>(c3 * v + (diag && gc < n ? c1 : 0.0f));
+          }
+        } else if (!diag_tile) {          // every element has r < c (global)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             float v = acc[bm][bn][4 * g + e];
@@ -341,6 +356,10 @@ __device__ __forceinline__ void ns_gemm_body(const TI *__restrict__ A, const TI 
     // off-diagonal tiles count each element twice (it stands for (r, c) and (c, r));
     // their padding rows and columns are zero and contribute nothing
     const float tot = block_sum256(diag_tile ? rs : 2.0f * rs, red);
+    if (tid == 0) atomicAdd(racc, resid_fixed(tot));
+  }
+  if (EPI == EPI_FULL_SQUARE) {
+    const float tot = block_sum256(rs, red);
     if (tid == 0) atomicAdd(racc, resid_fixed(tot));
   }
 }

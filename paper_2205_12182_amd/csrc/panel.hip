@@ -503,13 +503,21 @@ struct PanelCtx {
   }
 };
 
+void launch_lit_panel_v(const SubDesc *desc, const SubState *st, int K, char *ws, int qv,
+                        hipStream_t s);
+void launch_lit_dcol(const SubDesc *desc, const SubState *st, int K, char *ws, int qv, int qw,
+                     hipStream_t s);
+
+// literal: V = S^-1[:, own] and T_k(D)[:, own] = 1/2 (V - W) (literal.hip)
 void launch_density_columns(const SubDesc *desc, const SubState *st, int K, int max_npad,
-                            int max_m, char *ws, int panel_steps, hipStream_t s) {
+                            int max_m, char *ws, int panel_steps, bool literal, hipStream_t s) {
   const int nchunk = (max_m + MAXM - 1) / MAXM;   // own columns in chunks of MAXM
   PanelCtx c{desc, st, K, max_npad, nchunk, ws, s, 1u};   // slot 0 holds V
-  panel_v_kernel<<<dim3(64, K), 256, 0, s>>>(desc, st, ws, 0);
+  if (literal) launch_lit_panel_v(desc, st, K, ws, 0, s);
+  else panel_v_kernel<<<dim3(64, K), 256, 0, s>>>(desc, st, ws, 0);
   const int qw = c.apply(panel_steps, 0);
-  dcol_kernel<<<dim3(max_npad / 64, K, nchunk), 256, 0, s>>>(desc, st, ws, 0, qw);
+  if (literal) launch_lit_dcol(desc, st, K, ws, 0, qw, s);
+  else dcol_kernel<<<dim3(max_npad / 64, K, nchunk), 256, 0, s>>>(desc, st, ws, 0, qw);
 }
 
 void launch_scatter(const SubDesc *desc, const SubState *st, int K, int maxmem,

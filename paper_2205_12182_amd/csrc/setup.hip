@@ -806,11 +806,19 @@ static void launch_factor(const SubDesc *desc, SubState *st, int K, int max_npad
 
 // factor_fp32: the 128 x 128 tile products of the factorisation and the inverse on
 // FP32 MFMAs (tile128_f32); otherwise FP64 throughout.
+void launch_lit_setup(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+                      hipStream_t s);
+
+// literal: A0 = S^-1 H in place of M (literal.hip; H is gathered in FP64)
 void launch_setup(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
-                  bool fp32_products, bool factor_fp32, char *ws, hipStream_t s) {
+                  bool fp32_products, bool factor_fp32, bool literal, char *ws, hipStream_t s) {
   const int nbmax = max_npad / NB;
   if (factor_fp32) launch_factor<true>(desc, st, K, max_npad, ws, s);
   else launch_factor<false>(desc, st, K, max_npad, ws, s);
+  if (literal) {
+    launch_lit_setup(desc, st, K, max_npad, ws, s);
+    return;
+  }
   // M = L^-1 H L^-T as two products: U = H L^-T, then M = L^-1 U
   if (!fp32_products) {
     prep_split_kernel<<<dim3(nbmax * nbmax, K), 256, 0, s>>>(desc, ws);

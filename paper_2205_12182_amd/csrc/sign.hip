@@ -125,13 +125,14 @@ __global__ void ns_shift_kernel(SubState *__restrict__ st, int K, int prec) {
   s.racc = 0ull;
 }
 
+// rotate = 0 (the literal form, literal.hip): the buffers keep fixed roles.
 __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, int use_lower,
-                                  int fallback, int order) {
+                                  int fallback, int order, int rotate) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
   if (!s.active || s.prec != prec) return;
-  s.cur = (s.cur + 2) % 3;
+  if (rotate) s.cur = (s.cur + 2) % 3;
   if (fallback) ++s.iters_fb; else ++s.iters_lo;
   if (s.extra_left == 0) {
     // a tolerance phase reached its tolerance and this was the last of its extra
@@ -370,6 +371,11 @@ __global__ void clear_scale_kernel(SubState *__restrict__ st, int K) {
 static inline int nblk(int K) { return (K + 255) / 256; }
 
 void launch_reset_status(SubState *st, int K, int keep_spd, hipStream_t s);
+void launch_lit_transpose(const SubDesc *desc, const SubState *st, int K, int max_npad, char *ws,
+                          int mode, int prec, const unsigned *cnt, hipStream_t s);
+void launch_lit_gemm(int square, const Tile *tiles, int ntiles, const SubDesc *desc, SubState *st,
+                     char *ws, int prec, unsigned long long *flop_units, hipStream_t s);
+void launch_lit_finish(SubState *st, int K, hipStream_t s);
 
 template <typename TI, int EPI>
 static void launch_ns_gemm_t(const TileSet &ts, const SubDesc *desc, SubState *st, char *ws,
@@ -424,8 +430,17 @@ static void gated_gemm(int epi, const TileSet &ts, const SubDesc *desc, SubState
 
 static void timed_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc,
                        SubState *st, char *ws, EventLog *log, double flop, int fallback,
-                       hipStream_t s) {
+                       bool literal, hipStream_t s) {
   (void)flop;
+  if (literal) {        // every tile of every submatrix (tile list 3), no gating
+    const int e = (log && !fallback) ? log->begin(T_GEMM, s) : -1;
+    launch_lit_gemm(epi == EPI_SQUARE, ts.t[3], ts.n[3], desc, st, ws, prec, ts.flop_units, s);
+    if (e >= 0) {
+      log->end(e, s);
+      ++log->n_gemm;
+    }
+    return;
+  }
   if (fallback) {
     gated_gemm(epi, ts, desc, st, ws, s);
     return;
@@ -438,9 +453,9 @@ static void timed_gemm(int epi, int prec, const TileSet &ts, const SubDesc *desc
   }
 }
 
-void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
+void launch_phase(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                   char *ws, const nolsm_phase &ph, int use_lower, int fallback, EventLog *log,
-                  double flop, hipStream_t s) {
+                  double flop, bool literal, hipStream_t s) {
   PhaseArgs p;
   p.prec = ph.prec;
   p.iters = ph.iters;
@@ -451,14 +466,18 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
   const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
   for (int t = 0; t <= last; ++t) {
     p.t = t;
-    timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
+    timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, literal, s);
     ns_check_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, p);
     if (p.order == 3) {
-      timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
+      timed_gemm(EPI_SQUARE, ph.prec, ts, desc, st, ws, log, flop, fallback, literal, s);
       ns_shift_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec);
     }
-    timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, fallback, s);
-    ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback, p.order);
+    timed_gemm(EPI_UPDATE, ph.prec, ts, desc, st, ws, log, flop, fallback, literal, s);
+    // the literal form keeps X^T beside X; transposed before the advance, which may
+    // end a submatrix's iteration
+    if (literal) launch_lit_transpose(desc, st, K, max_npad, ws, 1, ph.prec, nullptr, s);
+    ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback, p.order,
+                                              literal ? 0 : 1);
   }
   phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
 }
@@ -466,9 +485,10 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, const TileSet &ts,
 // flop: executed MFMA flops of one GEMM launch over every tile of the plan.
 // have_scale: the Gershgorin bounds for this mu are already in the state (written with
 // the descriptors of the learned schedule), so the pass over M_k is skipped.
+// literal: the literal form (literal.hip; one precision for every phase, order 2).
 void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const TileSet &ts,
                  char *ws, double mu, const nolsm_schedule &sch, bool have_scale,
-                 EventLog *log, double flop, hipStream_t s) {
+                 EventLog *log, double flop, bool literal, hipStream_t s) {
   launch_reset_status(st, K, 1, s);
   if (!have_scale) {
     clear_scale_kernel<<<nblk(K), 256, 0, s>>>(st, K);
@@ -477,6 +497,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
   scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, sch.scale, sch.lower, sch.lower_log10,
                                             sch.lower_factor, sch.phase[0].prec, 0);
   cast_kernel<<<dim3((max_npad + CAST_COLS - 1) / CAST_COLS, K), 256, 0, s>>>(desc, st, ws, mu);
+  if (literal) launch_lit_transpose(desc, st, K, max_npad, ws, 0, 0, nullptr, s);
   for (int q = 0; q < sch.nphase; ++q) {
     const nolsm_phase &ph = sch.phase[q];
     if (q > 0 && ph.prec != sch.phase[q - 1].prec) {
@@ -485,7 +506,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     }
     const int scaled = (sch.lower != nullptr || sch.lower_log10 != nullptr) ? 1 : 0;
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0, ph.order == 3 ? 3 : 2);
-    launch_phase(desc, st, K, ts, ws, ph, scaled, 0, log, flop, s);
+    launch_phase(desc, st, K, max_npad, ts, ws, ph, scaled, 0, log, flop, literal, s);
   }
   if (sch.fallback_iters > 0) {
     clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count);
@@ -493,6 +514,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, nullptr, 0.0f,
                                               P_FP32, 1);
     cast_fb_kernel<<<K, 256, 0, s>>>(desc, st, ws, mu, ts.fb_count);
+    if (literal) launch_lit_transpose(desc, st, K, max_npad, ws, 2, 0, ts.fb_count, s);
     nolsm_phase fb;
     fb.prec = P_FP32;
     fb.iters = sch.fallback_iters;
@@ -500,9 +522,10 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     fb.extra = 2;
     fb.order = 2;
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, 0, 1, 2);
-    launch_phase(desc, st, K, ts, ws, fb, 0, 1, nullptr, 0.0, s);
+    launch_phase(desc, st, K, max_npad, ts, ws, fb, 0, 1, nullptr, 0.0, literal, s);
     fb_finish_kernel<<<nblk(K), 256, 0, s>>>(st, K);
   }
+  if (literal) launch_lit_finish(st, K, s);      // the panel kernels read X^T
 }
 
 }  // namespace nolsm

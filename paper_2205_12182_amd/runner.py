@@ -62,7 +62,7 @@ def tuned_tile_policy():
 class Runner:
     def __init__(self, inst, batch: int | None = None, mols=None, device="cuda",
                  big_tile_min_npad="tuned", setup_products=None, persist=False, groups=None,
-                 overlap=False, factor_tiles=None):
+                 overlap=False, factor_tiles=None, form=None):
         """groups: lists of molecules that share one submatrix each (combined
         submatrices, e.g. from nolsm_combine); then `batch` counts submatrices and
         the stats hold one record per group, in the order of `groups`.
@@ -100,6 +100,7 @@ class Runner:
         self.big_tile_min_npad = big_tile_min_npad
         self.setup_products = setup_products
         self.factor_tiles = factor_tiles
+        self.form = form
         self.persist = bool(persist)
         self.plans = self._create_plans()
         need = max(L.nolsm_plan_workspace_bytes(p) for p in self.plans)
@@ -140,10 +141,11 @@ class Runner:
         if self.groups is not None:
             return [L.nolsm_plan_create_groups(self.hpat, b, self.big_tile_min_npad,
                                                self.setup_products, persist=self.persist,
-                                               factor_tiles=self.factor_tiles)
+                                               factor_tiles=self.factor_tiles, form=self.form)
                     for b in self.batches]
         return [L.nolsm_plan_create(self.hpat, b, self.big_tile_min_npad, self.setup_products,
-                                    persist=self.persist, factor_tiles=self.factor_tiles)
+                                    persist=self.persist, factor_tiles=self.factor_tiles,
+                                    form=self.form)
                 for b in self.batches]
 
     def __del__(self):

@@ -88,12 +88,12 @@ def test_plan_options_tile_policy():
     assert sizes[0] == sizes[2] and sizes[1] != sizes[0]
     opt = L.PlanOptions()
     opt.big_tile_min_npad = 0
-    opt.reserved[3] = 1    # reserved has 4 entries
+    opt.reserved[2] = 1    # reserved has 3 entries
     out = ctypes.c_void_p()
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
     assert rc == L.EINVAL and "reserved" in L.nolsm_last_error()
-    opt.reserved[3] = 0
+    opt.reserved[2] = 0
     opt.setup_products = 2
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
@@ -103,6 +103,19 @@ def test_plan_options_tile_policy():
     rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
                                       ctypes.byref(opt), ctypes.byref(out))
     assert rc == L.EINVAL and "factor_tiles" in L.nolsm_last_error()
+    opt.factor_tiles = 0
+    opt.form = 2
+    rc = L.lib().nolsm_plan_create_ex(ctypes.byref(hp.struct), mols.ctypes.data, int(mols.size),
+                                      ctypes.byref(opt), ctypes.byref(out))
+    assert rc == L.EINVAL and "form" in L.nolsm_last_error()
+    # the literal form keeps T_k(H0) in FP64 (8 npad^2 bytes) where the split set-up
+    # products keep only the FP32 M_k
+    ws = {}
+    for form in (L.FORM_SYM, L.FORM_LITERAL):
+        plan = L.nolsm_plan_create(hp, mols, form=form)
+        ws[form] = L.nolsm_plan_workspace_bytes(plan)
+        L.nolsm_plan_destroy(plan)
+    assert ws[L.FORM_LITERAL] > ws[L.FORM_SYM]
     for sp in (L.SETUP_SPLIT_FP16, L.SETUP_FP32):
         for ft in (L.FACTOR_FP32_TILES, L.FACTOR_FP64):
             plan = L.nolsm_plan_create(hp, mols, setup_products=sp, factor_tiles=ft)
