@@ -9,7 +9,9 @@ timed with every submatrix on 128 x 128 tiles and with every submatrix on 256 x 
 tiles (HIP events around each launch; executed MFMA flops from the device counter).
 The policy is the smallest padded dimension from which the 256 x 128 kernel is faster
 at every measured size above it; the table of rates (this GPU's p(n)) is stored with
-it.  Runner applies the stored policy to every plan it creates.
+it.  Runner applies the stored policy to every plan it creates, provided it was
+measured on the same GPU architecture (the file records the gfx target, the HIP and
+PyTorch versions and a digest of the GEMM kernel sources it was measured with).
 """
 from __future__ import annotations
 
@@ -22,6 +24,8 @@ import time
 import numpy as np
 
 RADII = (4.5, 5.0, 5.5, 6.0, 6.5, 7.0, 7.5, 8.0, 9.0, 10.0)
+POLICY_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tile_policy.json")
+GEMM_SOURCES = ("ns_gemm.h", "ns_gemm_rect.h", "sign.hip")
 NMOL, SHIFT, ITERS = 1024, 1.5, 4
 NEVER = 1 << 20
 
@@ -60,14 +64,46 @@ def measure(r_cut: float, batch: int, say) -> dict:
     return rec
 
 
+def gemm_sources_digest() -> str:
+    """sha256 over the sign-GEMM kernel sources (first 16 hex digits)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in GEMM_SOURCES:
+        with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc", name),
+                  "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def target_key() -> dict:
+    """What a policy is measured on: gfx target, HIP and PyTorch versions, kernels."""
+    import torch
+    return {"gfx_arch": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+            "hip_version": str(torch.version.hip), "torch_version": torch.__version__,
+            "kernel_sha256": gemm_sources_digest()}
+
+
+def policy_applies(policy: dict, gfx_arch: str) -> tuple:
+    """(usable, note): a policy applies on the architecture it was measured on; one
+    without a recorded target is taken as it is.  A changed kernel digest is noted
+    (the crossover may have moved) but does not void the policy."""
+    key = policy.get("target")
+    if not key:
+        return True, ""
+    if key.get("gfx_arch") != gfx_arch:
+        return False, f"measured on {key.get('gfx_arch')}, this GPU is {gfx_arch}"
+    if key.get("kernel_sha256") != gemm_sources_digest():
+        return True, "the GEMM kernel sources changed since the measurement"
+    return True, ""
+
+
 def rate_table(policy: dict | None = None) -> list:
     """p(n) of Sec. IV-B from the stored measurements: for each measured size, the
     sign-GEMM throughput in the paper's accounting (2 n^3 per product and submatrix)
     with the tile shape the policy picks there, [(n_mean, TFLOP/s), ...] ascending.
     Eq. 10 combines submatrices on the predicted time n^3 / p(n)."""
     if policy is None:
-        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tile_policy.json")
-        with open(path) as fh:
+        with open(POLICY_PATH) as fh:
             policy = json.load(fh)
     out = []
     for m in sorted(policy["measurements"], key=lambda r: r["n_mean"]):
@@ -102,7 +138,7 @@ def main(argv=None):
     recs = [measure(rc, args.batch, say) for rc in RADII]
     big_min = choose(recs)
     out = {"big_tile_min_npad": big_min, "iterations": ITERS, "batch": args.batch,
-           "measurements": recs, "wall_s": time.perf_counter() - t0}
+           "target": target_key(), "measurements": recs, "wall_s": time.perf_counter() - t0}
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     with open(args.out, "w") as fh:
         json.dump(out, fh, indent=1)

@@ -49,14 +49,26 @@ def plain_fp32_schedule(tol=1e-3, extra=2, cap=100, order=2):
 
 
 def tuned_tile_policy():
-    """big_tile_min_npad from the autotuner's table (data/tile_policy.json), or None."""
+    """big_tile_min_npad from the autotuner's table (data/tile_policy.json), or None
+    (the library default) when there is no table or it was measured on another GPU
+    architecture."""
     import json
     import os
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "tile_policy.json")
-    if not os.path.exists(path):
+    import warnings
+    from .autotune import POLICY_PATH, policy_applies
+    if not os.path.exists(POLICY_PATH):
         return None
-    with open(path) as fh:
-        return int(json.load(fh)["big_tile_min_npad"])
+    with open(POLICY_PATH) as fh:
+        policy = json.load(fh)
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    ok, note = policy_applies(policy, arch)
+    if note and note not in _policy_notes:
+        _policy_notes.add(note)
+        warnings.warn(f"tile policy: {note}", stacklevel=2)
+    return int(policy["big_tile_min_npad"]) if ok else None
+
+
+_policy_notes = set()
 
 
 class Runner:
