@@ -392,6 +392,10 @@ def main():
                     help="submatrices the oracle solves on the host (0: skip)")
     ap.add_argument("--graph-steps", type=int, default=2,
                     help="timed replays of the step captured as a HIP graph (0: skip)")
+    ap.add_argument("--extra", type=int, default=1,
+                    help="low-precision iterations after the tolerance is reached")
+    ap.add_argument("--panel-steps", type=int, default=1,
+                    help="FP32 Newton-Schulz steps on the own-column panel")
     ap.add_argument("--factor-tiles", choices=("fp32", "fp64"), default="fp32",
                     help="precision of the tile products of the set-up's Cholesky factorisation "
                          "and inverse (FP64 storage either way)")
@@ -469,9 +473,10 @@ def main():
     predictor = None
     if args.schedule == "learned":
         predictor = learn.ScheduleMLP.load(weights)
-        mixed = learned_schedule(prec=args.prec)
+        mixed = learned_schedule(prec=args.prec, extra=args.extra, panel_steps=args.panel_steps)
     else:
-        mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec)
+        mixed = default_mixed_schedule(fixed_iters=args.iters or None, prec=args.prec,
+                                       extra=args.extra, panel_steps=args.panel_steps)
     step_mu = inst.mu
     search = None
     if args.mu_search:
@@ -627,10 +632,10 @@ def main():
         "config": {"workload": workload_text(args.workload, inst, dims),
                    "batch": args.batch,
                    "schedule": (f"{args.prec} Newton-Schulz " +
-                                (f"x{args.iters}" if args.iters else "to ||X^2-I||_F<=0.1 +1") +
+                                (f"x{args.iters}" if args.iters else f"to ||X^2-I||_F<=0.1 +{args.extra}") +
                                 (", learned lower bound -> scaled iteration (cap 16)"
                                  if args.schedule == "learned" else ", unscaled") +
-                                ", Gershgorin scale, FP32 fallback and panel step, FP64 "
+                                f", Gershgorin scale, FP32 fallback, {args.panel_steps} FP32 panel step(s), FP64 "
                                 "Cholesky/L^-1 storage (tile products on " +
                                 ("FP64" if args.factor_tiles == "fp64" else "FP32") +
                                 " MFMAs), FP64 D columns/traces, set-up and panel products on "

@@ -15,7 +15,7 @@ from . import _lib as L
 
 
 def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallback_iters=60,
-                           tol=0.1, cap=30, scale=None, lower=None, order=2):
+                           tol=0.1, cap=30, scale=None, lower=None, order=2, extra=1):
     """Low-precision bulk, then one FP32 Newton-Schulz step on the own-column panel.
 
     By default the bulk runs until ||X^2 - I||_F <= tol (every eigenvalue within
@@ -23,7 +23,7 @@ def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallbac
     that many.  Submatrices that miss the tolerance restart in plain FP32.  order 3
     takes the third-order polynomial step in the bulk.
     """
-    phase = (prec, fixed_iters, 0.0, 0, order) if fixed_iters else (prec, cap, tol, 1, order)
+    phase = (prec, fixed_iters, 0.0, 0, order) if fixed_iters else (prec, cap, tol, extra, order)
     return L.schedule([phase], fallback_tol=tol, fallback_iters=fallback_iters,
                       panel_steps=panel_steps, scale=scale, lower=lower)
 
@@ -36,10 +36,11 @@ def default_mixed_schedule(fixed_iters=None, panel_steps=1, prec="fp16", fallbac
 LEARNED_CAP = 16
 
 
-def learned_schedule(panel_steps=1, prec="fp16", fallback_iters=60, tol=0.1):
+def learned_schedule(panel_steps=1, prec="fp16", fallback_iters=60, tol=0.1, extra=1):
     """The mixed schedule used with a learned lower bound (Runner.run(predictor=...))."""
     return default_mixed_schedule(panel_steps=panel_steps, prec=prec,
-                                  fallback_iters=fallback_iters, tol=tol, cap=LEARNED_CAP)
+                                  fallback_iters=fallback_iters, tol=tol, cap=LEARNED_CAP,
+                                  extra=extra)
 
 
 def plain_fp32_schedule(tol=1e-3, extra=2, cap=100, order=2):
