@@ -7,8 +7,8 @@ sweep of sizes (water boxes of 1,024 molecules with 13+5+5 functions and a range
 cutoff radii), the FP16 products of a fixed number of Newton-Schulz iterations are
 timed with every submatrix on 128 x 128 tiles and with every submatrix on 256 x 128
 tiles (HIP events around each launch; executed MFMA flops from the device counter).
-The policy is the smallest padded dimension from which the 256 x 128 kernel is faster
-at every measured size above it; the table of rates (this GPU's p(n)) is stored with
+The policy is the smallest padded dimension from which the 256 x 128 kernel takes less
+time per launch at every measured size above it; the table of rates (this GPU's p(n)) is stored with
 it.  Runner applies the stored policy to every plan it creates, provided it was
 measured on the same GPU architecture (the file records the gfx target, the HIP and
 PyTorch versions and a digest of the GEMM kernel sources it was measured with).
@@ -114,11 +114,14 @@ def rate_table(policy: dict | None = None) -> list:
 
 
 def choose(recs) -> int:
-    """Smallest mean padded size from which the large tiles win at every larger size."""
+    """Smallest mean padded size from which the large tiles take less time per launch
+    at every larger size.  Both kernels form the same products; their executed-flop
+    rates are not comparable, since the large tiles skip the blocks of diagonal tiles
+    that lie wholly below the diagonal and the 128 x 128 tiles do not."""
     recs = sorted(recs, key=lambda r: r["npad_mean"])
     big_min = NEVER
     for r in reversed(recs):
-        if r["tile256x128"]["tflops_executed"] > r["tile128"]["tflops_executed"]:
+        if r["tile256x128"]["ms_per_launch"] < r["tile128"]["ms_per_launch"]:
             big_min = int(r["npad_mean"] // 64 * 64)
         else:
             break

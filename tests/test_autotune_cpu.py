@@ -5,30 +5,29 @@ import json
 from paper_2205_12182_amd import autotune as A
 
 
-def rec(npad, t128, t256, n=None, k=512, ms=1.0):
+def rec(npad, ms128, ms256, n=None, k=512):
     return {"npad_mean": npad, "n_mean": npad - 30 if n is None else n, "submatrices": k,
-            "tile128": {"tflops_executed": t128, "ms_per_launch": ms},
-            "tile256x128": {"tflops_executed": t256, "ms_per_launch": ms / 2}}
+            "tile128": {"ms_per_launch": ms128}, "tile256x128": {"ms_per_launch": ms256}}
 
 
 def test_choose_crossover():
-    # the large tiles win from 448 up: the policy starts there (rounded down to 64)
-    recs = [rec(378, 280, 276), rec(460, 334, 356), rec(535, 373, 400), rec(900, 700, 800)]
+    # the large tiles are faster from 460 up: the policy starts there (rounded down to 64)
+    recs = [rec(378, 0.14, 0.17), rec(460, 0.20, 0.19), rec(535, 0.26, 0.25), rec(900, 0.9, 0.8)]
     assert A.choose(recs) == 448
     # a win below a loss does not count: only the wins above the last loss
-    recs = [rec(378, 280, 300), rec(460, 360, 356), rec(535, 373, 400), rec(900, 700, 800)]
+    recs = [rec(378, 0.14, 0.13), rec(460, 0.19, 0.20), rec(535, 0.26, 0.25), rec(900, 0.9, 0.8)]
     assert A.choose(recs) == 512
     # never faster: the "never" threshold
-    assert A.choose([rec(378, 280, 200), rec(900, 900, 800)]) == A.NEVER
+    assert A.choose([rec(378, 0.14, 0.17), rec(900, 0.8, 0.9)]) == A.NEVER
     # order of the records does not matter
-    recs = [rec(900, 700, 800), rec(378, 280, 276), rec(535, 373, 400), rec(460, 334, 356)]
+    recs = [rec(900, 0.9, 0.8), rec(378, 0.14, 0.17), rec(535, 0.26, 0.25), rec(460, 0.20, 0.19)]
     assert A.choose(recs) == 448
 
 
 def test_rate_table_follows_policy_and_paper_accounting():
     """p(n) = 2 n^3 per product and submatrix over the launch time of the tile
     shape the policy uses at that size, ascending in n."""
-    recs = [rec(900, 700, 800, n=870, k=256, ms=2.0), rec(378, 280, 276, n=341, k=512, ms=0.2)]
+    recs = [rec(900, 2.0, 1.0, n=870, k=256), rec(378, 0.2, 0.25, n=341, k=512)]
     pol = {"big_tile_min_npad": 448, "measurements": recs}
     table = A.rate_table(pol)
     assert [n for n, _ in table] == [341.0, 870.0]
