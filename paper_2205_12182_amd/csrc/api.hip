@@ -256,6 +256,8 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
                      std::to_string(d.mol) + ") exceeds limits (own columns " +
                      std::to_string(d.m) + " <= " + std::to_string(MAX_OWN) + ", members " +
                      std::to_string(d.nmem) + " <= 1024, n " + std::to_string(d.n) + " <= 8192)");
+    // the 256 x 128 tiles (tile list 1) iterate on the k-blocked layout
+    d.kb = (!literal && d.npad >= big_min) ? 1 : 0;
     p->maxmem = std::max(p->maxmem, d.nmem);
     p->max_npad = std::max(p->max_npad, d.npad);
     p->max_m = std::max(p->max_m, d.m);

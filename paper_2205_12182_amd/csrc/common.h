@@ -36,7 +36,7 @@ enum Prec : int32_t { P_FP32 = 0, P_FP16 = 1, P_BF16 = 2 };
 struct SubDesc {
   int32_t n, npad, mol, m;          // dimension, leading dimension, first own molecule, own columns
   int32_t own_lo, nmem, mem_off, ngrp;
-  int32_t own_mem, pad0;
+  int32_t own_mem, kb;              // kb: the FP16/BF16 iterate is k-blocked (kb_index)
   int64_t off_h;                    // bytes from workspace base: FP64 npad^2 H_k, then FP32 M_k
   int64_t off_s;                    // FP64 npad^2 (S_k -> L -> L^-1)
   int64_t off_lo;                   // 3 x (4 npad^2) bytes: sign-iteration buffers / FP64 scratch
@@ -65,6 +65,18 @@ struct SubState {
 };
 
 struct Tile { int32_t sub, ti, tj, pad; };
+
+// k-blocked layout of the sign iterate of submatrices on the 256 x 128 tiles (FP16 and
+// BF16): element (row r, column c) at ((r / 32) npad + c) 32 + r % 32, so a 32-row
+// chunk of a column is one 64-byte run and the chunks of consecutive columns are
+// adjacent.  The products read both factors as column panels 32 k deep, so a stage of
+// 256 columns is one contiguous 16 KiB block (instead of 256 runs of 64 bytes one
+// column apart).  Every other kernel sees the column-major layout: the iterate is
+// formed k-blocked (cast, precision changes) and turned column-major after the
+// low-precision phases.
+__host__ __device__ __forceinline__ int64_t kb_index(int r, int c, int ld) {
+  return ((int64_t)(r >> 5) * ld + c) * 32 + (r & 31);
+}
 
 // Tile lists: upper-triangle tiles of the symmetric products, t[0] the small
 // submatrices in 128 x 128 tiles, t[1] the large ones in 256 x 128 tiles (FP16 and

@@ -11,12 +11,15 @@
 // MFMAs.  (The 16 x 16 x 32 MFMA covers a whole 32-k stage per instruction and
 // issues faster than 32 x 32 x 16: measured 3% more throughput for this kernel.)
 //
-// Stages are loaded straight into LDS (buffer loads with the LDS destination),
-// two stages ahead; rows are 64 bytes with the conflict-free chunk permutation.
+// The iterate is k-blocked (kb_index, common.h): a stage of 256 (or 128) columns is
+// one contiguous block, loaded straight into LDS (buffer loads with the LDS
+// destination), two stages ahead; rows are 64 bytes with the chunk permutation.
+// (Measured against the column-major layout, whose stage rows are 64-byte runs one
+// column apart: 7-10% less time per product.)
 // Lane (g, l) of a fragment read takes chunk g (k = 8 g .. 8 g + 7) of row l of a
 // 16-row block, for A and B alike.  The epilogue stores from registers: 8-byte
-// stores of four consecutive rows of a column for the tile itself and 2-byte
-// stores for its mirror image.
+// stores of four consecutive rows of a column for the tile itself and, on tiles
+// that meet the diagonal or the ragged edge, 2-byte stores for its mirror image.
 #pragma once
 #include "ns_gemm.h"
 
@@ -73,6 +76,10 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
     diag_off = (i0 + wm) - (j0 + wn);
   }
   const int nrec = ld * ld * (int)sizeof(TI);
+  // k-blocked offsets: row r of a panel (column r of the iterate) starts at 64 r within
+  // a stage's block, stage kt at 64 ld kt; rows past ld (the ragged edge) get an
+  // offset past the buffer, which reads as zero
+  constexpr unsigned KB_OOB = 0x80000000u;
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(A), (short)0, nrec, BUFFER_RSRC_WORD3);
   const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
@@ -86,13 +93,13 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
   for (int q = 0; q < LA; ++q) {
     const int row = 16 * (4 * q + w) + (lane >> 2);
     const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
-    voA[q] = (unsigned)((i0 + row) * ld) * (unsigned)sizeof(TI) + 16u * ch;
+    voA[q] = i0 + row < ld ? (unsigned)(i0 + row) * 64u + 16u * ch : KB_OOB;
   }
 #pragma unroll
   for (int q = 0; q < LB; ++q) {
     const int row = 16 * (4 * q + w) + (lane >> 2);
     const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
-    voB[q] = (unsigned)((j0 + row) * ld) * (unsigned)sizeof(TI) + 16u * ch;
+    voB[q] = j0 + row < ld ? (unsigned)(j0 + row) * 64u + 16u * ch : KB_OOB;
   }
   // lane (g, l16) reads chunk g of row l16 of each 16-row block (rows 16 b + l16 have
   // the same permutation for every b since 16 b does not change (r ^ (r >> 2)) & 3)
@@ -110,7 +117,7 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
   auto issue = [&](uint4 *slot, int kt) {
     const bool live = kt < nk;
     const __amdgpu_buffer_rsrc_t ra = live ? rA : rA0, rb = live ? rB : rB0;
-    const int so = live ? 64 * kt : 0;
+    const int so = live ? 64 * ld * kt : 0;
 #pragma unroll
     for (int q = 0; q < LA; ++q)
       __builtin_amdgcn_raw_ptr_buffer_load_lds((skip_low && q >= LA / 2) ? rA0 : ra,
@@ -207,7 +214,7 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
             ov[e] = from_f32<TI>(v);
             stg[(16 * b + 4 * g + e) * SLD + 16 * bn + l16] = ov[e];
           }
-          *reinterpret_cast<v4 *>(Out + (int64_t)gc * ldv + i0 + r0) = ov;
+          *reinterpret_cast<v4 *>(Out + kb_index(i0 + r0, gc, ldv)) = ov;
         }
       }
       __builtin_amdgcn_s_waitcnt(LGKM0);
@@ -216,8 +223,8 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
       for (int it = 0; it < 8; ++it) {
         const int e = lane + 64 * it, rr = e >> 3, ch = e & 7;
         const uint4 v = *reinterpret_cast<const uint4 *>(stg + rr * SLD + 8 * ch);
-        *reinterpret_cast<uint4 *>(Out + (int64_t)(i0 + wm + 64 * h + rr) * ldv + j0 + wn +
-                                   8 * ch) = v;
+        *reinterpret_cast<uint4 *>(Out + kb_index(j0 + wn + 8 * ch, i0 + wm + 64 * h + rr,
+                                                  ldv)) = v;
       }
       __builtin_amdgcn_s_waitcnt(LGKM0);
       __builtin_amdgcn_wave_barrier();
@@ -235,8 +242,9 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
       if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
       const int c = wn + 16 * bn + l16, gc = j0 + c;
       const int r0 = wm + 16 * bm + 4 * g;
-      TI *col = Out + (int64_t)gc * ldv + i0;
-      TI *mir = Out + (int64_t)(i0 + r0) * ldv + gc;
+      // element (i0 + r0 + e, gc) and its mirror (gc, i0 + r0 + e)
+      TI *col = Out + kb_index(i0 + r0, gc, ldv);
+      TI *mir = Out + kb_index(gc, i0 + r0, ldv);
       if (!cross) {
         v4 ov;
 #pragma unroll
@@ -247,9 +255,9 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
             v = c3 * v;
           }
           ov[e] = from_f32<TI>(v);
-          mir[(int64_t)e * ldv] = ov[e];
+          mir[32 * e] = ov[e];
         }
-        *reinterpret_cast<v4 *>(col + r0) = ov;
+        *reinterpret_cast<v4 *>(col) = ov;
       } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -264,8 +272,8 @@ __device__ __forceinline__ void ns_gemm_rect_body(const TI *__restrict__ A,
             v = c3 * v + (diag ? c1 : 0.0f);
           }
           const TI o = from_f32<TI>(v);
-          if (gr <= gc) col[r0 + e] = o;
-          if (gr < gc) mir[(int64_t)e * ldv] = o;
+          if (gr <= gc) col[e] = o;
+          if (gr < gc) mir[32 * e] = o;
         }
       }
     }

@@ -175,10 +175,14 @@ __global__ void phase_end_kernel(SubState *__restrict__ st, int K) {
 }
 
 // Convert the current iterate to precision `to` (one column per workgroup).
+// Layouts: the iterate of a k-blocked submatrix (d.kb) is k-blocked in FP16 and BF16
+// (the 256 x 128 tiles) and column major in FP32 (128 x 128 tiles).
 template <typename TF, typename TT>
-__device__ void convert_col(const TF *src, TT *dst, int ld, int c) {
-  for (int r = threadIdx.x; r < ld; r += blockDim.x)
-    dst[(int64_t)c * ld + r] = from_f32<TT>(to_f32<TF>(src[(int64_t)c * ld + r]));
+__device__ void convert_col(const TF *src, TT *dst, int ld, int c, bool kb_src, bool kb_dst) {
+  for (int r = threadIdx.x; r < ld; r += blockDim.x) {
+    const int64_t cm = (int64_t)c * ld + r;
+    dst[kb_dst ? kb_index(r, c, ld) : cm] = from_f32<TT>(to_f32<TF>(src[kb_src ? kb_index(r, c, ld) : cm]));
+  }
 }
 
 __global__ __launch_bounds__(256) void convert_kernel(const SubDesc *__restrict__ desc,
@@ -189,7 +193,9 @@ __global__ __launch_bounds__(256) void convert_kernel(const SubDesc *__restrict_
   const int c = blockIdx.x;
   if (c >= d.npad || s.status != 0 || s.prec == to) return;
   const int q = s.cur, qn = (s.cur + 1) % 3;
-#define CV(TF, TT) convert_col<TF, TT>(buf_ptr<TF>(ws, d, q), buf_ptr<TT>(ws, d, qn), d.npad, c)
+  const bool ks = d.kb && s.prec != P_FP32, kd = d.kb && to != P_FP32;
+#define CV(TF, TT) \
+  convert_col<TF, TT>(buf_ptr<TF>(ws, d, q), buf_ptr<TT>(ws, d, qn), d.npad, c, ks, kd)
   if (s.prec == P_FP32 && to == P_FP16) CV(float, _Float16);
   else if (s.prec == P_FP32 && to == P_BF16) CV(float, __bf16);
   else if (s.prec == P_FP16 && to == P_FP32) CV(_Float16, float);
@@ -270,10 +276,11 @@ __device__ void cast_col(const float *M, TI *X, int n, int ld, int c, double mu,
   }
 }
 
-// One wave per column, four consecutive rows per lane (16-byte reads of M).
+// One wave per column, four consecutive rows per lane (16-byte reads of M); kb: the
+// k-blocked layout (four consecutive rows stay adjacent).
 template <typename TI>
 __device__ __forceinline__ void cast_col4(const float *M, TI *X, int n, int ld, int c, double mu,
-                                          double inv_b) {
+                                          double inv_b, bool kb = false) {
   typedef TI v4 __attribute__((ext_vector_type(4)));
   const int lane = threadIdx.x & 63;
   for (int q = lane; q < ld / 4; q += 64) {
@@ -287,7 +294,7 @@ __device__ __forceinline__ void cast_col4(const float *M, TI *X, int n, int ld, 
       if (r + e < n && c < n) v = ((double)mv[e] - (r + e == c ? mu : 0.0)) * inv_b;
       o[e] = from_f64<TI>(v);
     }
-    *reinterpret_cast<v4 *>(X + (int64_t)c * ld + r) = o;
+    *reinterpret_cast<v4 *>(X + (kb ? kb_index(r, c, ld) : (int64_t)c * ld + r)) = o;
   }
 }
 
@@ -306,8 +313,8 @@ __global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ d
     if (c >= d.npad) break;
     if (s.prec == P_FP32) cast_col4<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
     else if (s.prec == P_FP16)
-      cast_col4<_Float16>(M, buf_ptr<_Float16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
-    else cast_col4<__bf16>(M, buf_ptr<__bf16>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+      cast_col4<_Float16>(M, buf_ptr<_Float16>(ws, d, 0), d.n, d.npad, c, mu, inv_b, d.kb != 0);
+    else cast_col4<__bf16>(M, buf_ptr<__bf16>(ws, d, 0), d.n, d.npad, c, mu, inv_b, d.kb != 0);
   }
 }
 
@@ -358,6 +365,55 @@ __global__ void final_status_kernel(SubState *__restrict__ st, int K, int check_
   SubState &s = st[i];
   s.active = 0;
   if (check_conv && s.status == 0 && !s.converged) s.status = NOLSM_ENOCONV;
+}
+
+// After the low-precision phases: the k-blocked FP16/BF16 iterate of every healthy
+// submatrix is copied column major into the next buffer, which becomes current (the
+// panel, trace and restart steps read column-major iterates).  64 x 64 blocks through
+// LDS: 64-byte runs in, 128-byte runs out.
+template <typename TI>
+__device__ void unblock_tile(const TI *X, TI *Y, int ld, int r0, int c0, TI (*t)[65]) {
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 31, c = (e >> 5) & 63, h = e >> 11;      // k-blocked order
+    t[c][32 * h + r] = X[kb_index(r0 + 32 * h + r, c0 + c, ld)];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e & 63, c = e >> 6;
+    Y[(int64_t)(c0 + c) * ld + r0 + r] = t[c][r];
+  }
+}
+
+__global__ __launch_bounds__(256) void unblock_kernel(const SubDesc *__restrict__ desc,
+                                                      SubState *__restrict__ st, char *ws) {
+  const SubDesc d = desc[blockIdx.y];
+  SubState &s = st[blockIdx.y];
+  if (!d.kb || s.status != 0 || s.prec == P_FP32) return;
+  const int nt = d.npad / 64;
+  if ((int)blockIdx.x < nt * nt) {
+    const int r0 = (blockIdx.x % nt) * 64, c0 = (blockIdx.x / nt) * 64;
+    const int q = s.cur, qn = (s.cur + 1) % 3;
+    if (s.prec == P_FP16) {
+      __shared__ _Float16 th[64][65];
+      unblock_tile<_Float16>(buf_ptr<_Float16>(ws, d, q), buf_ptr<_Float16>(ws, d, qn), d.npad,
+                             r0, c0, th);
+    } else {
+      __shared__ __bf16 tb[64][65];
+      unblock_tile<__bf16>(buf_ptr<__bf16>(ws, d, q), buf_ptr<__bf16>(ws, d, qn), d.npad, r0,
+                           c0, tb);
+    }
+  }
+}
+
+// The state moves to the column-major copy (a separate launch: every workgroup of
+// unblock_kernel reads the old current buffer).
+__global__ void unblock_commit_kernel(const SubDesc *__restrict__ desc,
+                                      SubState *__restrict__ st, int K) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  SubState &s = st[i];
+  if (!desc[i].kb || s.status != 0 || s.prec == P_FP32) return;
+  s.cur = (s.cur + 1) % 3;
 }
 
 __global__ void clear_scale_kernel(SubState *__restrict__ st, int K) {
@@ -507,6 +563,10 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     const int scaled = (sch.lower != nullptr || sch.lower_log10 != nullptr) ? 1 : 0;
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0, ph.order == 3 ? 3 : 2);
     launch_phase(desc, st, K, max_npad, ts, ws, ph, scaled, 0, log, flop, literal, s);
+  }
+  if (!literal && ts.n[1] > 0) {          // k-blocked iterates back to column major
+    unblock_kernel<<<dim3((max_npad / 64) * (max_npad / 64), K), 256, 0, s>>>(desc, st, ws);
+    unblock_commit_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K);
   }
   if (sch.fallback_iters > 0) {
     clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count);
