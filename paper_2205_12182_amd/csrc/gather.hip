@@ -13,9 +13,10 @@
 // and the upper triangle is cleared before the inverse.
 //
 // SPLIT_H: T_k(H0) goes straight into the split FP16 operand of the set-up products
-// (row j = column j by symmetry, npad hi parts then npad lo parts, x = hi + 2^-11 lo)
-// instead of the FP64 H buffer.
+// (row j = column j by symmetry, hi parts then lo parts, x = hi + 2^-11 lo, k-blocked
+// as split_index says) instead of the FP64 H buffer.
 #include "common.h"
+#include "ns_gemm_split.h"
 
 namespace nolsm {
 
@@ -65,8 +66,8 @@ __global__ __launch_bounds__(256) void gather_kernel(
       for (int c = n; c < ld; ++c)
         for (int r = threadIdx.x; r < ld; r += blockDim.x) {
           if (SPLIT_H) {
-            Hs[(int64_t)c * 2 * ld + r] = (_Float16)0.0f;
-            Hs[(int64_t)c * 2 * ld + ld + r] = (_Float16)0.0f;
+            Hs[split_index(c, r, ld)] = (_Float16)0.0f;
+            Hs[split_index(c, r, ld) + (int64_t)ld * ld] = (_Float16)0.0f;
           } else {
             Hk[(int64_t)c * ld + r] = 0.0;
           }
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void gather_kernel(
     // ld is a multiple of 64, so every four-row group lies inside the column.
     for (int c = 0; c < dJ; ++c) {
       double *hcol = Hk + (int64_t)(locb + c) * ld;
-      _Float16 *hrow = Hs + (int64_t)(locb + c) * 2 * ld;
+      const int64_t hlo = (int64_t)ld * ld;              // lo part after the hi part
       double *scol = Sk + (int64_t)(locb + c) * ld;
       const int col = locb + c;
       for (int i0 = 4 * threadIdx.x; i0 < ld; i0 += 4 * blockDim.x) {
@@ -124,8 +125,9 @@ __global__ __launch_bounds__(256) void gather_kernel(
             hi[e] = (_Float16)h[e];                      // one rounding from FP64
             lo[e] = (_Float16)((h[e] - (double)hi[e]) * 2048.0);
           }
-          *reinterpret_cast<h4 *>(hrow + i0) = hi;
-          *reinterpret_cast<h4 *>(hrow + ld + i0) = lo;
+          _Float16 *hp = Hs + split_index(locb + c, i0, ld);   // row locb + c, k = i0 .. i0 + 3
+          *reinterpret_cast<h4 *>(hp) = hi;
+          *reinterpret_cast<h4 *>(hp + hlo) = lo;
         } else {
           *reinterpret_cast<double2 *>(hcol + i0) = make_double2(h[0], h[1]);
           *reinterpret_cast<double2 *>(hcol + i0 + 2) = make_double2(h[2], h[3]);

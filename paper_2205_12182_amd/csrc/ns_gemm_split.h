@@ -11,16 +11,18 @@
 // accuracy (FP32 operands carry 2^-24) for three FP16 MFMA passes, which run
 // about five times faster than one pass of FP32 MFMAs.
 //
-// Operand layout: a split matrix is npad rows of 2 npad FP16 values, row r holding
-// hi(X(r, 0 .. npad-1)) and then lo(X(r, 0 .. npad-1)).  The contraction runs over
+// Operand layout: a split matrix holds hi(X) in its first npad^2 FP16 values and
+// lo(X) in the next npad^2, each k-blocked by rows: element k of row r at
+// ((k / 32) npad + r) 32 + k % 32 (split_index), so that 32 k of 256 consecutive rows,
+// one stage of a panel, are one contiguous block (as for the sign iterate, kb_index).  The contraction runs over
 // three segments of k, the two correction products first:
 //   segment 0: hi_A lo_B,  segment 1: lo_A hi_B,  then acc *= 2^-11,  segment 2: hi_A hi_B
 // so the corrections are accumulated at the scale of hi and the final FP32 sum
 // carries no extra rounding from the 2^-11 factor (a power of two).
 //
 // Tiles are 256 x 128 with four waves and two workgroups per CU, staged as in the
-// sign-iteration kernel (direct-to-LDS loads two stages ahead, 64-byte rows with the
-// chunk permutation).
+// sign-iteration kernel (direct-to-LDS loads two stages ahead from contiguous stage
+// blocks, 64-byte rows with the chunk permutation).
 //   SPLIT_FULL: U = H L^-T on every tile; the result is written split (rows of U'
 //               are the columns of U), ready to be the B operand of the next product.
 //               L^-T(k, c) = 0 for k > c, so the contraction stops at the tile's
@@ -37,6 +39,11 @@ namespace nolsm {
 enum { SPLIT_FULL = 0, SPLIT_SYM = 1 };
 constexpr float SPLIT_LO_SCALE = 2048.0f;        // 2^11
 constexpr float SPLIT_LO_UNSCALE = 1.0f / 2048.0f;
+
+// Element k of row r of a split matrix's hi (lo: + npad^2) part.
+__host__ __device__ __forceinline__ int64_t split_index(int r, int k, int np) {
+  return ((int64_t)(k >> 5) * np + r) * 32 + (k & 31);
+}
 
 __device__ __forceinline__ void split_f16(float v, _Float16 &hi, _Float16 &lo) {
   hi = (_Float16)v;
@@ -65,8 +72,8 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
   const int h = lane >> 5, l32 = lane & 31;
   const int nks = kend / KStage<TI>::KS;         // stages per segment
   const int nk = 3 * nks;
-  const int lda = 2 * np;                        // elements per split row
-  const int lo_bytes = np * (int)sizeof(TI);     // byte offset of the lo half of a row
+  const int lo_bytes = np * np * (int)sizeof(TI);   // byte offset of the lo part
+  constexpr unsigned OOB = 0x80000000u;            // past the buffer: reads as zero
 
   int nvr = BM, nvc = BN;
   if (PARTIAL) {
@@ -78,7 +85,7 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
 
   // rows past npad (ragged edge tiles) read as zero; stages past the last one are
   // issued against zero-size resources so every wave issues the same loads
-  const int nrec = np * lda * (int)sizeof(TI);
+  const int nrec = 2 * np * np * (int)sizeof(TI);
   const __amdgpu_buffer_rsrc_t rA = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<TI *>(A), (short)0, nrec, BUFFER_RSRC_WORD3);
   const __amdgpu_buffer_rsrc_t rB = __builtin_amdgcn_make_buffer_rsrc(
@@ -93,13 +100,13 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
   for (int q = 0; q < LA; ++q) {
     const int row = 16 * (4 * q + w) + (lane >> 2);
     const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
-    voA[q] = (unsigned)((i0 + row) * lda) * (unsigned)sizeof(TI) + 16u * ch;
+    voA[q] = i0 + row < np ? (unsigned)(i0 + row) * 64u + 16u * ch : OOB;
   }
 #pragma unroll
   for (int q = 0; q < LB; ++q) {
     const int row = 16 * (4 * q + w) + (lane >> 2);
     const unsigned ch = (unsigned)((lane & 3) ^ chunk_swz(row));
-    voB[q] = (unsigned)((j0 + row) * lda) * (unsigned)sizeof(TI) + 16u * ch;
+    voB[q] = j0 + row < np ? (unsigned)(j0 + row) * 64u + 16u * ch : OOB;
   }
   const int z = chunk_swz(l32);
   const int fa0 = (wm + l32) * 4 + ((2 * h) ^ z), fa1 = (wm + l32) * 4 + ((2 * h + 1) ^ z);
@@ -117,7 +124,7 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
   auto issue = [&](uint4 *slot, int kt) {
     const bool live = kt < nk;
     const int seg = (kt >= nks) + (kt >= 2 * nks);
-    const int kb = 64 * (kt - seg * nks);
+    const int kb = 64 * np * (kt - seg * nks);     // the stage's block
     const __amdgpu_buffer_rsrc_t ra = live ? rA : rA0, rb = live ? rB : rB0;
     const int soa = live ? kb + (seg == 1 ? lo_bytes : 0) : 0;
     const int sob = live ? kb + (seg == 0 ? lo_bytes : 0) : 0;
@@ -195,8 +202,9 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
   int ldv = np;
   asm volatile("" : "+v"(ldv));
   if (EPI == SPLIT_FULL) {
-    // U(r, c) -> row c of U': hi at [c 2np + r], lo at [c 2np + np + r]
+    // U(r, c) -> element r of row c of U': hi at split_index(c, r), lo np^2 after it
     TI *U = reinterpret_cast<TI *>(Out);
+    const int64_t lo_off = (int64_t)ldv * ldv;
     typedef TI v4 __attribute__((ext_vector_type(4)));
 #pragma unroll
     for (int bm = 0; bm < BM; ++bm)
@@ -204,10 +212,10 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
       for (int bn = 0; bn < BN; ++bn) {
         if (PARTIAL && (bm >= nvr || bn >= nvc)) continue;
         const int gc = j0 + wn + 32 * bn + l32;
-        TI *row = U + (int64_t)gc * (2 * ldv) + i0;
 #pragma unroll
         for (int g = 0; g < 4; ++g) {
           const int r0 = wm + 32 * bm + 8 * g + 4 * h;
+          TI *row = U + split_index(gc, i0 + r0, ldv);     // four consecutive k
           v4 hv, lv;
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
@@ -216,8 +224,8 @@ __device__ __forceinline__ void split_gemm_body(const _Float16 *__restrict__ A,
             hv[e] = a;
             lv[e] = b;
           }
-          *reinterpret_cast<v4 *>(row + r0) = hv;
-          *reinterpret_cast<v4 *>(row + ldv + r0) = lv;
+          *reinterpret_cast<v4 *>(row) = hv;
+          *reinterpret_cast<v4 *>(row + lo_off) = lv;
         }
       }
   } else {

@@ -687,8 +687,8 @@ __global__ __launch_bounds__(256) void prep_products_kernel(const SubDesc *__res
 
 
 // Split FP16 operand of the set-up products for L^-1: buffer 0, row r = L^-1(r, :)
-// (through an LDS tile, since L^-1 is stored by columns), npad hi parts then npad lo
-// parts.  (Buffer 1, the rows of H, is written by the gather.)  Every thread
+// (through an LDS tile, since L^-1 is stored by columns), hi parts then lo parts,
+// k-blocked (split_index).  (Buffer 1, the rows of H, is written by the gather.)  Every thread
 // converts four consecutive elements: 8-byte stores of hi and of lo.  Blocks above
 // the diagonal block are zero in L^-1 (its upper triangle is cleared before the
 // inverse), so they are written without being read.
@@ -701,13 +701,13 @@ __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restri
   if ((int)blockIdx.x >= nt * nt) return;
   const int bi = blockIdx.x / nt, bj = blockIdx.x % nt;
   _Float16 *Ls = reinterpret_cast<_Float16 *>(ws + d.off_lo);
-  const int64_t lds = 2 * (int64_t)ld;
+  const int64_t llo = (int64_t)ld * ld;                    // lo part after the hi part
   if (bi < bj) {
     const h4 z = {(_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f, (_Float16)0.0f};
     for (int e = threadIdx.x; e < 64 * 16; e += 256) {
-      _Float16 *lrow = Ls + (int64_t)(bi * 64 + (e >> 4)) * lds + bj * 64 + (e & 15) * 4;
+      _Float16 *lrow = Ls + split_index(bi * 64 + (e >> 4), bj * 64 + (e & 15) * 4, ld);
       *reinterpret_cast<h4 *>(lrow) = z;
-      *reinterpret_cast<h4 *>(lrow + ld) = z;
+      *reinterpret_cast<h4 *>(lrow + llo) = z;
     }
     return;
   }
@@ -730,9 +730,9 @@ __global__ __launch_bounds__(256) void prep_split_kernel(const SubDesc *__restri
       lh[q] = a;
       ll[q] = b;
     }
-    _Float16 *lrow = Ls + (int64_t)(bi * 64 + r) * lds + bj * 64 + c4;
+    _Float16 *lrow = Ls + split_index(bi * 64 + r, bj * 64 + c4, ld);
     *reinterpret_cast<h4 *>(lrow) = lh;
-    *reinterpret_cast<h4 *>(lrow + ld) = ll;
+    *reinterpret_cast<h4 *>(lrow + llo) = ll;
   }
 }
 

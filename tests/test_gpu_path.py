@@ -50,11 +50,14 @@ def print_case(*a):
 
 def split_rows(r, info):
     """The split FP16 rows of H (hi parts, lo parts) the gather writes for the split
-    set-up products: iteration buffer 1, npad rows of 2 npad values."""
+    set-up products: iteration buffer 1, the hi part then the lo part, each k-blocked
+    (element k of row j at ((k // 32) npad + j) 32 + k % 32)."""
     npad = info.npad
-    v = r.ws_view(info.off_lo + 4 * npad * npad, 2 * npad * npad, torch.float16)
-    v = v.reshape(npad, 2 * npad).cpu().numpy()
-    return v[:, :npad], v[:, npad:]
+    v = r.ws_view(info.off_lo + 4 * npad * npad, 2 * npad * npad, torch.float16).cpu().numpy()
+
+    def rows(x):
+        return x.reshape(npad // 32, npad, 32).transpose(1, 0, 2).reshape(npad, npad)
+    return rows(v[:npad * npad]), rows(v[npad * npad:])
 
 
 @pytest.mark.parametrize("setup", [L.SETUP_SPLIT_FP16, L.SETUP_FP32])
