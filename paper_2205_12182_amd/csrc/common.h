@@ -71,9 +71,9 @@ struct Tile { int32_t sub, ti, tj, pad; };
 // chunk of a column is one 64-byte run and the chunks of consecutive columns are
 // adjacent.  The products read both factors as column panels 32 k deep, so a stage of
 // 256 columns is one contiguous 16 KiB block (instead of 256 runs of 64 bytes one
-// column apart).  Every other kernel sees the column-major layout: the iterate is
-// formed k-blocked (cast, precision changes) and turned column-major after the
-// low-precision phases.
+// column apart).  The cast forms the iterate k-blocked, precision changes keep it (an
+// FP32 iterate, on 128 x 128 tiles, is column major), and the panel and trace kernels
+// read it in place.
 __host__ __device__ __forceinline__ int64_t kb_index(int r, int c, int ld) {
   return ((int64_t)(r >> 5) * ld + c) * 32 + (r & 31);
 }

@@ -48,7 +48,7 @@ constexpr int PANEL_K = 64;
 
 template <typename TI>
 __device__ __forceinline__ void panel_load_x(const TI *__restrict__ X, int ld, int i0, int k0,
-                                             float (*sX)[PANEL_ROWS + 4]) {
+                                             float (*sX)[PANEL_ROWS + 4], bool kb) {
   constexpr int EPU = 16 / (int)sizeof(TI);                  // elements per 16-byte load
   constexpr int CPR = PANEL_K / EPU;                         // loads per row
   constexpr int PER_T = PANEL_ROWS * CPR / 256;
@@ -56,8 +56,9 @@ __device__ __forceinline__ void panel_load_x(const TI *__restrict__ X, int ld, i
   for (int q = 0; q < PER_T; ++q) {
     const int idx = threadIdx.x + 256 * q, row = idx / CPR, kc = idx % CPR;
     uint4 v = {0u, 0u, 0u, 0u};
-    if (i0 + row < ld)
-      v = *reinterpret_cast<const uint4 *>(X + (int64_t)(i0 + row) * ld + k0 + kc * EPU);
+    if (i0 + row < ld)     // row i0 + row of X = its column (symmetric), k-blocked or not
+      v = *reinterpret_cast<const uint4 *>(
+          X + (kb ? kb_index(k0 + kc * EPU, i0 + row, ld) : (int64_t)(i0 + row) * ld + k0 + kc * EPU));
     const TI *e = reinterpret_cast<const TI *>(&v);
 #pragma unroll
     for (int j = 0; j < EPU; ++j) sX[kc * EPU + j][row] = to_f32<TI>(e[j]);
@@ -68,7 +69,7 @@ template <typename TI>
 __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict__ P,
                                const float *__restrict__ Q, float *__restrict__ O, int ld, int m,
                                float alpha, float beta, float (*sX)[PANEL_ROWS + 4],
-                               float (*sP)[MAXM]) {
+                               float (*sP)[MAXM], bool kb) {
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * PANEL_ROWS;
   const int ti = tid & 31, tc = tid >> 5;         // rows 4 ti .. 4 ti + 3, columns 4 tc .. + 3
@@ -78,7 +79,7 @@ __device__ void panel_mul_body(const TI *__restrict__ X, const float *__restrict
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[r][c] = 0.0f;
   for (int k0 = 0; k0 < ld; k0 += PANEL_K) {
-    panel_load_x<TI>(X, ld, i0, k0, sX);
+    panel_load_x<TI>(X, ld, i0, k0, sX, kb);
     for (int e = tid; e < PANEL_K * MAXM; e += 256) {
       const int kk = e % PANEL_K, c = e / PANEL_K;
       sP[kk][c] = c < m ? P[(int64_t)c * ld + k0 + kk] : 0.0f;
@@ -129,15 +130,16 @@ __global__ __launch_bounds__(256) void panel_mul_kernel(const SubDesc *__restric
   const float *Q = panel_ptr(ws, d, qq) + co;
   float *O = panel_ptr(ws, d, qo) + co;
   const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
+  const bool kb = d.kb != 0;                     // BF16 here: k-blocked on the large tiles
   if (s.prec == P_FP32)
     panel_mul_body<float>(reinterpret_cast<const float *>(xb), P, Q, O, d.npad, mc, alpha, beta,
-                          sX, sP);
+                          sX, sP, false);
   else if (s.prec == P_FP16)
     panel_mul_body<_Float16>(reinterpret_cast<const _Float16 *>(xb), P, Q, O, d.npad, mc, alpha,
-                             beta, sX, sP);
+                             beta, sX, sP, kb);
   else
     panel_mul_body<__bf16>(reinterpret_cast<const __bf16 *>(xb), P, Q, O, d.npad, mc, alpha,
-                           beta, sX, sP);
+                           beta, sX, sP, kb);
 }
 
 // O = alpha X P + beta Q for submatrices iterating in FP16, on MFMAs.  X is exactly
@@ -178,6 +180,8 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
   const float *Q = panel_ptr(ws, d, qq) + co;
   float *O = panel_ptr(ws, d, qo) + co;
   const bool live = c < m;
+  // row i of X (= its column) at k .. k + 7: k-blocked on the large tiles
+  const bool kb = d.kb != 0;
   const _Float16 *xr = X + (int64_t)(i0 + c) * ld + 8 * h;
   const float *pc = P + (int64_t)(live ? c : 0) * ld + 8 * h;
   pf16 ah[PM_BLK], al[PM_BLK];
@@ -198,7 +202,9 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
     ph8 a[PM_BLK];
 #pragma unroll
     for (int b = 0; b < PM_BLK; ++b)
-      if (b < nb) a[b] = *reinterpret_cast<const ph8 *>(xr + (int64_t)32 * b * ld + k);
+      if (b < nb)
+        a[b] = *reinterpret_cast<const ph8 *>(
+            kb ? X + kb_index(k + 8 * h, i0 + c + 32 * b, ld) : xr + (int64_t)32 * b * ld + k);
     const float pv[8] = {p0.x, p0.y, p0.z, p0.w, p1.x, p1.y, p1.z, p1.w};
     ph8 bh, bl;
 #pragma unroll
@@ -442,9 +448,10 @@ __global__ __launch_bounds__(256) void trace_x_kernel(const SubDesc *__restrict_
   SubState &s = st[blockIdx.x];
   __shared__ float red[4];
   const char *xb = ws + d.off_lo + (int64_t)s.cur * 4 * d.npad * d.npad;
+  const bool kb = d.kb && s.prec != P_FP32;                // k-blocked FP16/BF16 iterate
   float t = 0.0f;
   for (int i = threadIdx.x; i < d.n; i += 256) {
-    const int64_t o = (int64_t)i * d.npad + i;
+    const int64_t o = kb ? kb_index(i, i, d.npad) : (int64_t)i * d.npad + i;
     if (s.prec == P_FP32) t += reinterpret_cast<const float *>(xb)[o];
     else if (s.prec == P_FP16) t += (float)reinterpret_cast<const _Float16 *>(xb)[o];
     else t += (float)reinterpret_cast<const __bf16 *>(xb)[o];

@@ -118,6 +118,103 @@ __device__ __forceinline__ void gemm64_f64(const double *__restrict__ A, int64_t
   }
 }
 
+// The same product on FP32 MFMAs (v_mfma_f32_16x16x4_f32): the FP64 operands are
+// rounded to FP32 as they are staged, FP32 sums (the FP32 factorisation tiles of
+// tile128_f32); D(i, j) sits in lane j + 16 (i / 4), register i % 4.  LDS rows are
+// padded by 16 floats so that the four 16-lane groups of a read hit different banks.
+constexpr int LDPF = 64 + 16;
+
+template <bool TRANSB>
+__device__ __forceinline__ void gemm64_f32(const double *__restrict__ A, int64_t lda,
+                                           const double *__restrict__ B, int64_t ldb, int k0,
+                                           int k1, f4x acc[2][2], float *sA, float *sB) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  double ra[4], rb[4];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
+      ra[q] = A[(int64_t)(k + kk) * lda + m];
+    }
+    if (!TRANSB) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
+        rb[q] = B[(int64_t)nn * ldb + k + kk];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
+        rb[q] = B[(int64_t)(k + kk) * ldb + nn];
+      }
+    }
+  };
+  auto stage = [&](int b) {
+    float *a = sA + b * KS64 * LDPF, *bb = sB + b * KS64 * LDPF;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
+      a[kk * LDPF + m] = (float)ra[q];
+    }
+    if (!TRANSB) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
+        bb[kk * LDPF + nn] = (float)rb[q];
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
+        bb[kk * LDPF + nn] = (float)rb[q];
+      }
+    }
+  };
+  if (k0 >= k1) return;
+  fetch(k0);
+  stage(0);
+  __syncthreads();
+  int b = 0;
+  for (int k = k0; k < k1; k += KS64) {
+    const bool more = k + KS64 < k1;
+    if (more) fetch(k + KS64);
+    const float *a = sA + b * KS64 * LDPF, *bb = sB + b * KS64 * LDPF;
+#pragma unroll
+    for (int kk = 0; kk < KS64; kk += 4) {
+      const int kr = kk + (lane >> 4);
+      float av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = a[kr * LDPF + wm + 16 * t + (lane & 15)];
+        bv[t] = bb[kr * LDPF + wn + 16 * t + (lane & 15)];
+      }
+#pragma unroll
+      for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn)
+          acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bm], bv[bn], acc[bm][bn], 0, 0, 0);
+    }
+    if (more) stage(b ^ 1);
+    __syncthreads();
+    b ^= 1;
+  }
+}
+
+template <typename F>
+__device__ __forceinline__ void acc64f_foreach(f4x acc[2][2], F f) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+#pragma unroll
+  for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        f(wm + 16 * bm + 4 * (lane >> 4) + q, wn + 16 * bn + (lane & 15), (double)acc[bm][bn][q]);
+}
+
 __device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
 #pragma unroll
   for (int bm = 0; bm < 2; ++bm)
@@ -302,6 +399,8 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
 // tj in [cb0, cb1) and ti >= tj (lower tiles only).  blockIdx.x enumerates the
 // rectangle ti in [cb0, nb_max), tj in [cb0, cb1) column by column; tiles above
 // the diagonal or beyond this submatrix exit at once.
+// F32: the product on FP32 MFMAs (gemm64_f32), with the factorisation's FP32 tiles.
+template <bool F32>
 __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restrict__ desc,
                                                           char *ws, int k0, int k1, int cb0,
                                                           int cb1, int rows) {
@@ -310,16 +409,29 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   const int nb = ld / 64;
   if (ti < tj || ti >= nb || tj >= nb || k0 >= ld) return;
   const int r0 = ti * 64, c0 = tj * 64;
-  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
-  d4 acc[2][2];
-  acc_zero(acc);
-  // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
-  gemm64_f64<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0, k1 - k0,
-                   acc, sA, sB);
-  acc_foreach(acc, [&](int r, int c, double v) {
+  auto apply = [&](int r, int c, double v) {
     double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
     *p = *p - v;
-  });
+  };
+  // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
+  if constexpr (F32) {
+    __shared__ float sA[2 * KS64 * LDPF], sB[2 * KS64 * LDPF];
+    f4x acc[2][2];
+#pragma unroll
+    for (int bm = 0; bm < 2; ++bm)
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
+    gemm64_f32<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0,
+                     k1 - k0, acc, sA, sB);
+    acc64f_foreach(acc, apply);
+  } else {
+    __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
+    d4 acc[2][2];
+    acc_zero(acc);
+    gemm64_f64<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0,
+                     k1 - k0, acc, sA, sB);
+    acc_foreach(acc, apply);
+  }
 }
 
 // 128 x 128 FP64 tile product for the blocked set-up steps:
@@ -766,8 +878,8 @@ static void launch_factor(const SubDesc *desc, SubState *st, int K, int max_npad
     for (int jb = J; jb < Jend; ++jb) {
       if (jb > J) {
         const int rows = nbmax - jb;
-        chol_update_kernel<<<dim3(rows, K), 256, 0, s>>>(desc, ws, J * NB, jb * NB, jb, jb + 1,
-                                                         rows);
+        chol_update_kernel<F32><<<dim3(rows, K), 256, 0, s>>>(desc, ws, J * NB, jb * NB, jb,
+                                                              jb + 1, rows);
       }
       chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
       const int rem = nbmax - jb - 1;

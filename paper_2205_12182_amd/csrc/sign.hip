@@ -367,55 +367,6 @@ __global__ void final_status_kernel(SubState *__restrict__ st, int K, int check_
   if (check_conv && s.status == 0 && !s.converged) s.status = NOLSM_ENOCONV;
 }
 
-// After the low-precision phases: the k-blocked FP16/BF16 iterate of every healthy
-// submatrix is copied column major into the next buffer, which becomes current (the
-// panel, trace and restart steps read column-major iterates).  64 x 64 blocks through
-// LDS: 64-byte runs in, 128-byte runs out.
-template <typename TI>
-__device__ void unblock_tile(const TI *X, TI *Y, int ld, int r0, int c0, TI (*t)[65]) {
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int r = e & 31, c = (e >> 5) & 63, h = e >> 11;      // k-blocked order
-    t[c][32 * h + r] = X[kb_index(r0 + 32 * h + r, c0 + c, ld)];
-  }
-  __syncthreads();
-  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
-    const int r = e & 63, c = e >> 6;
-    Y[(int64_t)(c0 + c) * ld + r0 + r] = t[c][r];
-  }
-}
-
-__global__ __launch_bounds__(256) void unblock_kernel(const SubDesc *__restrict__ desc,
-                                                      SubState *__restrict__ st, char *ws) {
-  const SubDesc d = desc[blockIdx.y];
-  SubState &s = st[blockIdx.y];
-  if (!d.kb || s.status != 0 || s.prec == P_FP32) return;
-  const int nt = d.npad / 64;
-  if ((int)blockIdx.x < nt * nt) {
-    const int r0 = (blockIdx.x % nt) * 64, c0 = (blockIdx.x / nt) * 64;
-    const int q = s.cur, qn = (s.cur + 1) % 3;
-    if (s.prec == P_FP16) {
-      __shared__ _Float16 th[64][65];
-      unblock_tile<_Float16>(buf_ptr<_Float16>(ws, d, q), buf_ptr<_Float16>(ws, d, qn), d.npad,
-                             r0, c0, th);
-    } else {
-      __shared__ __bf16 tb[64][65];
-      unblock_tile<__bf16>(buf_ptr<__bf16>(ws, d, q), buf_ptr<__bf16>(ws, d, qn), d.npad, r0,
-                           c0, tb);
-    }
-  }
-}
-
-// The state moves to the column-major copy (a separate launch: every workgroup of
-// unblock_kernel reads the old current buffer).
-__global__ void unblock_commit_kernel(const SubDesc *__restrict__ desc,
-                                      SubState *__restrict__ st, int K) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= K) return;
-  SubState &s = st[i];
-  if (!desc[i].kb || s.status != 0 || s.prec == P_FP32) return;
-  s.cur = (s.cur + 1) % 3;
-}
-
 __global__ void clear_scale_kernel(SubState *__restrict__ st, int K) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
@@ -564,10 +515,7 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     phase_start_kernel<<<nblk(K), 256, 0, s>>>(st, K, scaled, 0, ph.order == 3 ? 3 : 2);
     launch_phase(desc, st, K, max_npad, ts, ws, ph, scaled, 0, log, flop, literal, s);
   }
-  if (!literal && ts.n[1] > 0) {          // k-blocked iterates back to column major
-    unblock_kernel<<<dim3((max_npad / 64) * (max_npad / 64), K), 256, 0, s>>>(desc, st, ws);
-    unblock_commit_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K);
-  }
+
   if (sch.fallback_iters > 0) {
     clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count);
     fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol, ts.fb_count);
