@@ -21,6 +21,8 @@
 // columns use the FP64 L^-1, so the rounding in M (relative ~1e-7 with FP32
 // operands, a few 1e-7 with split FP16 operands) stays far below the FP16
 // rounding of the iteration.
+#include <type_traits>
+
 #include "common.h"
 #include "ns_gemm.h"
 #include "ns_gemm_split.h"
@@ -380,8 +382,13 @@ __global__ __launch_bounds__(256) void chol_diag_kernel(const SubDesc *__restric
   if (tid == 0 && bad) st[blockIdx.y].status = NOLSM_ENOTSPD;
 }
 
+// F32: the rows below the diagonal block also go, rounded to FP32, to the panel copy
+// that the FP32 trailing update reads (column (jb - jb0) 64 + c of the outer block
+// that starts at column block jb0, leading dimension ld, in the iteration arena,
+// which is free during the factorisation).
+template <bool F32>
 __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restrict__ desc,
-                                                         char *ws, int jb) {
+                                                         char *ws, int jb, int jb0) {
   SUB_PTRS
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
@@ -392,7 +399,11 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
   // out(r, c) = sum_s P(r, s) Linv_jj(c, s);  B(k=s, n=c) = Dinv[c + s*64]
   gemm64_f64<true>(Sb + (int64_t)j * ld + i0, ld, Dinv + (int64_t)jb * NB * NB, NB, 0, NB, acc,
                    sA, sB);
-  acc_foreach(acc, [&](int r, int c, double v) { Sb[(int64_t)(j + c) * ld + i0 + r] = v; });
+  float *P32 = reinterpret_cast<float *>(ws + d.off_lo) + (int64_t)(jb - jb0) * NB * ld;
+  acc_foreach(acc, [&](int r, int c, double v) {
+    Sb[(int64_t)(j + c) * ld + i0 + r] = v;
+    if (F32) P32[(int64_t)c * ld + i0 + r] = (float)v;
+  });
 }
 
 // A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s] on the 64 x 64 tiles (ti, tj) with
@@ -544,26 +555,27 @@ constexpr int LDQF = 128 + 16;
 constexpr int KSF = 16;             // k per LDS stage of the FP32 tiles (32 measured no faster)
 typedef float Stage128f[KSF * LDQF];
 
-template <bool TB>
-__device__ __forceinline__ bool tile128_f32(const double *__restrict__ A, int64_t lda,
-                                            const double *__restrict__ B, int64_t ldb, int nA,
+template <bool TB, typename TA, typename TBT>
+__device__ __forceinline__ bool tile128_f32(const TA *__restrict__ A, int64_t lda,
+                                            const TBT *__restrict__ B, int64_t ldb, int nA,
                                             int nB, int k0, int k1, f4x acc[2][4], Stage128f *sA,
                                             Stage128f *sB, bool lower = false) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
   const bool idle = wm >= nA || wn >= nB || (lower && wm + 31 < wn);
   constexpr int NQ = KSF * 128 / T128_THREADS;     // elements per thread per operand and stage
-  double ra[NQ], rb[NQ];
+  TA ra[NQ];
+  TBT rb[NQ];
   auto load = [&](int k) {
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
-      ra[q] = (m < nA && k + kk < k1) ? A[(int64_t)(k + kk) * lda + m] : 0.0;
+      ra[q] = (m < nA && k + kk < k1) ? A[(int64_t)(k + kk) * lda + m] : (TA)0;
       if (!TB) {
-        rb[q] = (m < nB && k + kk < k1) ? B[(int64_t)(k + kk) * ldb + m] : 0.0;
+        rb[q] = (m < nB && k + kk < k1) ? B[(int64_t)(k + kk) * ldb + m] : (TBT)0;
       } else {
         const int kt = idx & (KSF - 1), n = idx / KSF;
-        rb[q] = (n < nB && k + kt < k1) ? B[(int64_t)n * ldb + k + kt] : 0.0;
+        rb[q] = (n < nB && k + kt < k1) ? B[(int64_t)n * ldb + k + kt] : (TBT)0;
       }
     }
   };
@@ -623,10 +635,11 @@ __device__ __forceinline__ void acc128f_foreach(f4x acc[2][4], F f) {
 }
 
 // One 128 x 128 tile product in FP64 or (F32) FP32 MFMAs; f(r, c, value) visits the
-// result unless every wave was idle (then nothing is to be applied).
-template <bool TB, bool F32, typename F>
-__device__ __forceinline__ void tile128(const double *__restrict__ A, int64_t lda,
-                                        const double *__restrict__ B, int64_t ldb, int nA, int nB,
+// result unless every wave was idle (then nothing is to be applied).  FP32 operands
+// (the FP32 copies of the factor's panel and of T) are read only with F32.
+template <bool TB, bool F32, typename TA, typename TBT, typename F>
+__device__ __forceinline__ void tile128(const TA *__restrict__ A, int64_t lda,
+                                        const TBT *__restrict__ B, int64_t ldb, int nA, int nB,
                                         int k0, int k1, bool lower, F f) {
   if constexpr (F32) {
     __shared__ Stage128f sA[2], sB[2];
@@ -638,6 +651,8 @@ __device__ __forceinline__ void tile128(const double *__restrict__ A, int64_t ld
     if (tile128_f32<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
     acc128f_foreach(acc, f);
   } else {
+    static_assert(std::is_same<TA, double>::value && std::is_same<TBT, double>::value,
+                  "FP64 tiles take FP64 operands");
     __shared__ Stage128 sA[2], sB[2];
     d4 acc[2][4];
 #pragma unroll
@@ -664,13 +679,19 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
   if (ti < tj || k0 >= ld) return;
   const int r0 = m0 + ti * 128, c0 = m0 + tj * 128;
   if (r0 >= ld || c0 >= ld) return;
-  tile128<false, F32>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj,
-                      [&](int r, int c, double v) {
-                        if (r0 + r < ld && c0 + c < ld) {
-                          double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
-                          *p = *p - v;
-                        }
-                      });
+  auto apply = [&](int r, int c, double v) {
+    if (r0 + r < ld && c0 + c < ld) {
+      double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
+      *p = *p - v;
+    }
+  };
+  if constexpr (F32) {      // the outer block's columns from their FP32 copy (chol_panel)
+    const float *P32 = reinterpret_cast<const float *>(ws + d.off_lo);
+    tile128<false, true>(P32 + r0, ld, P32 + c0, ld, ld - r0, ld - c0, 0, k1 - k0, ti == tj,
+                         apply);
+  } else {
+    tile128<false, false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj, apply);
+  }
 }
 
 // ------------------------------------------------------------------ L^-1 in place
@@ -735,12 +756,14 @@ void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   const int ti = tile % rows, tj = tile / rows;
   const int r0 = J1 + ti * 128, c0 = tj * 128;
   if (r0 >= ld) return;
-  double *T = reinterpret_cast<double *>(ws + d.off_lo);
   // T[r0 + r, c0 + c] = sum_s L[r0 + r, J0 + s] X_JJ[s, c0 + c];  X_JJ[s, c] = 0 for s < c
-  // (an all-idle tile has no rows below ld: nothing to store)
+  // (an all-idle tile has no rows below ld: nothing to store); FP32 with the FP32 tiles,
+  // which is how trtri_outer_x reads it then
+  typedef typename std::conditional<F32, float, double>::type TT;
+  TT *T = reinterpret_cast<TT *>(ws + d.off_lo);
   tile128<true, F32>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
                      ld - r0, 128, c0, TW, false, [&](int r, int c, double v) {
-                       if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = v;
+                       if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = (TT)v;
                      });
 }
 
@@ -754,7 +777,8 @@ void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   const int ti = tile % rows, tj = tile / rows;
   const int r0 = J1 + ti * 128, c0 = tj * 128;
   if (r0 >= ld) return;
-  const double *T = reinterpret_cast<const double *>(ws + d.off_lo);
+  typedef typename std::conditional<F32, float, double>::type TT;
+  const TT *T = reinterpret_cast<const TT *>(ws + d.off_lo);
   const int kend = (r0 + 128 < ld ? r0 + 128 : ld) - J1;       // X[i, k] = 0 for k > i
   tile128<false, F32>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, false,
                       [&](int r, int c, double v) {
@@ -883,7 +907,7 @@ static void launch_factor(const SubDesc *desc, SubState *st, int K, int max_npad
       }
       chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
       const int rem = nbmax - jb - 1;
-      if (rem > 0) chol_panel_kernel<<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb);
+      if (rem > 0) chol_panel_kernel<F32><<<dim3(rem, K), 256, 0, s>>>(desc, ws, jb, J);
     }
     if (Jend < nbmax) {
       // Jend * 64 is a multiple of 256 here, so the 128-wide tiles start aligned
