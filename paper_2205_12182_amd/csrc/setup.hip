@@ -126,14 +126,29 @@ __device__ __forceinline__ void gemm64_f64(const double *__restrict__ A, int64_t
 // padded by 16 floats so that the four 16-lane groups of a read hit different banks.
 constexpr int LDPF = 64 + 16;
 
-template <bool TRANSB>
-__device__ __forceinline__ void gemm64_f32(const double *__restrict__ A, int64_t lda,
-                                           const double *__restrict__ B, int64_t ldb, int k0,
+// FP32 operands (the FP32 copy of the Cholesky panel) are read 4 rows at a time:
+// thread t takes rows 4 (t % 16) .. + 3 of stage row t / 16 (sA, sB 16-byte aligned).
+template <bool TRANSB, typename T>
+__device__ __forceinline__ void gemm64_f32(const T *__restrict__ A, int64_t lda,
+                                           const T *__restrict__ B, int64_t ldb, int k0,
                                            int k1, f4x acc[2][2], float *sA, float *sB) {
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  double ra[4], rb[4];
+  constexpr bool V4 = std::is_same<T, float>::value;
+  static_assert(!V4 || TRANSB, "4-wide FP32 staging reads B contiguous in n");
+  T ra[4], rb[4];
   auto fetch = [&](int k) {
+    if constexpr (V4) {
+      const int kk = tid >> 4, m4 = (tid & 15) * 4;
+      const f4x va = *reinterpret_cast<const f4x *>(A + (int64_t)(k + kk) * lda + m4);
+      const f4x vb = *reinterpret_cast<const f4x *>(B + (int64_t)(k + kk) * ldb + m4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ra[q] = va[q];
+        rb[q] = vb[q];
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int m = tid & 63, kk = (tid >> 6) + 4 * q;
@@ -155,6 +170,12 @@ __device__ __forceinline__ void gemm64_f32(const double *__restrict__ A, int64_t
   };
   auto stage = [&](int b) {
     float *a = sA + b * KS64 * LDPF, *bb = sB + b * KS64 * LDPF;
+    if constexpr (V4) {
+      const int kk = tid >> 4, m4 = (tid & 15) * 4;
+      *reinterpret_cast<f4x *>(a + kk * LDPF + m4) = f4x{ra[0], ra[1], ra[2], ra[3]};
+      *reinterpret_cast<f4x *>(bb + kk * LDPF + m4) = f4x{rb[0], rb[1], rb[2], rb[3]};
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int m = tid & 63, kk = (tid >> 6) + 4 * q;
@@ -393,17 +414,24 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
   const int j = jb * NB;
   const int i0 = j + NB + blockIdx.x * 64;
   if (i0 >= ld) return;
-  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
+  __shared__ double sm[4 * KS64 * LDP];         // the two stage buffers, then the result
+  static_assert(4 * KS64 * LDP >= NB * LDP, "result tile fits the stage buffers");
   d4 acc[2][2];
   acc_zero(acc);
   // out(r, c) = sum_s P(r, s) Linv_jj(c, s);  B(k=s, n=c) = Dinv[c + s*64]
   gemm64_f64<true>(Sb + (int64_t)j * ld + i0, ld, Dinv + (int64_t)jb * NB * NB, NB, 0, NB, acc,
-                   sA, sB);
+                   sm, sm + 2 * KS64 * LDP);
+  // through LDS (column c at sm[c LDP + r]; the product's last barrier has passed), then
+  // one column of 64 rows per wave and store: 512 contiguous bytes (256 of the copy)
+  acc_foreach(acc, [&](int r, int c, double v) { sm[c * LDP + r] = v; });
+  __syncthreads();
   float *P32 = reinterpret_cast<float *>(ws + d.off_lo) + (int64_t)(jb - jb0) * NB * ld;
-  acc_foreach(acc, [&](int r, int c, double v) {
-    Sb[(int64_t)(j + c) * ld + i0 + r] = v;
-    if (F32) P32[(int64_t)c * ld + i0 + r] = (float)v;
-  });
+  const int lane = threadIdx.x & 63;
+  for (int c = threadIdx.x >> 6; c < NB; c += 4) {
+    const double v = sm[c * LDP + lane];
+    Sb[(int64_t)(j + c) * ld + i0 + lane] = v;
+    if (F32) P32[(int64_t)c * ld + i0 + lane] = (float)v;
+  }
 }
 
 // A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s] on the 64 x 64 tiles (ti, tj) with
@@ -426,15 +454,23 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   };
   // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
   if constexpr (F32) {
-    __shared__ float sA[2 * KS64 * LDPF], sB[2 * KS64 * LDPF];
+    // the columns k0 .. k1 of the outer block from their FP32 copy (chol_panel: column
+    // s - k0, rows below the diagonal block of s, which covers rows r0 and c0 here)
+    __shared__ __align__(16) float sm[4 * KS64 * LDPF];
+    constexpr int LT = 64 + 1;
+    static_assert(4 * KS64 * LDPF >= 64 * LT, "result tile fits the stage buffers");
+    const float *P32 = reinterpret_cast<const float *>(ws + d.off_lo);
     f4x acc[2][2];
 #pragma unroll
     for (int bm = 0; bm < 2; ++bm)
 #pragma unroll
       for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
-    gemm64_f32<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0,
-                     k1 - k0, acc, sA, sB);
-    acc64f_foreach(acc, apply);
+    gemm64_f32<true>(P32 + r0, ld, P32 + c0, ld, 0, k1 - k0, acc, sm, sm + 2 * KS64 * LDPF);
+    // through LDS (column c at sm[c LT + r]), then one 512-byte column per wave and step
+    acc64f_foreach(acc, [&](int r, int c, double v) { sm[c * LT + r] = (float)v; });
+    __syncthreads();
+    const int lane = threadIdx.x & 63;
+    for (int c = threadIdx.x >> 6; c < 64; c += 4) apply(lane, c, (double)sm[c * LT + lane]);
   } else {
     __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
     d4 acc[2][2];
@@ -564,14 +600,36 @@ __device__ __forceinline__ bool tile128_f32(const TA *__restrict__ A, int64_t ld
   const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
   const bool idle = wm >= nA || wn >= nB || (lower && wm + 31 < wn);
   constexpr int NQ = KSF * 128 / T128_THREADS;     // elements per thread per operand and stage
+  // An FP32 operand (not transposed) is read 4 rows at a time: thread t takes rows
+  // 4 (t % 32) .. + 3 of stage row t / 32 (the NQ = 4 elements of one 16-byte load;
+  // its leading dimension and base are multiples of 4 floats).
+  constexpr bool VA = std::is_same<TA, float>::value;
+  constexpr bool VB = std::is_same<TBT, float>::value && !TB;
+  static_assert(!(VA || VB) || NQ == 4, "4-wide FP32 staging needs 4 elements per thread");
   TA ra[NQ];
   TBT rb[NQ];
+  auto load4 = [&](const float *__restrict__ X, int64_t ldx, int nX, int k, float *r) {
+    const int kk = tid >> 5, m4 = (tid & 31) * 4;
+    const bool kin = k + kk < k1;
+    if (kin && m4 + 3 < nX) {
+      const f4x v = *reinterpret_cast<const f4x *>(X + (int64_t)(k + kk) * ldx + m4);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) r[q] = v[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        r[q] = (kin && m4 + q < nX) ? X[(int64_t)(k + kk) * ldx + m4 + q] : 0.0f;
+    }
+  };
   auto load = [&](int k) {
+    if constexpr (VA) load4(A, lda, nA, k, ra);
+    if constexpr (VB) load4(B, ldb, nB, k, rb);
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
-      ra[q] = (m < nA && k + kk < k1) ? A[(int64_t)(k + kk) * lda + m] : (TA)0;
-      if (!TB) {
+      if constexpr (!VA) ra[q] = (m < nA && k + kk < k1) ? A[(int64_t)(k + kk) * lda + m] : (TA)0;
+      if constexpr (VB) {
+      } else if constexpr (!TB) {
         rb[q] = (m < nB && k + kk < k1) ? B[(int64_t)(k + kk) * ldb + m] : (TBT)0;
       } else {
         const int kt = idx & (KSF - 1), n = idx / KSF;
@@ -580,14 +638,21 @@ __device__ __forceinline__ bool tile128_f32(const TA *__restrict__ A, int64_t ld
     }
   };
   auto store = [&](int b) {
+    const int kk4 = tid >> 5, m4 = (tid & 31) * 4;
+    if constexpr (VA)
+      *reinterpret_cast<f4x *>(&sA[b][kk4 * LDQF + m4]) = f4x{ra[0], ra[1], ra[2], ra[3]};
+    if constexpr (VB)
+      *reinterpret_cast<f4x *>(&sB[b][kk4 * LDQF + m4]) = f4x{rb[0], rb[1], rb[2], rb[3]};
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
       const int idx = tid + T128_THREADS * q, m = idx & 127, kk = idx >> 7;
-      sA[b][kk * LDQF + m] = (float)ra[q];
-      if (!TB)
+      if constexpr (!VA) sA[b][kk * LDQF + m] = (float)ra[q];
+      if constexpr (VB) {
+      } else if constexpr (!TB) {
         sB[b][kk * LDQF + m] = (float)rb[q];
-      else
+      } else {
         sB[b][(idx & (KSF - 1)) * LDQF + idx / KSF] = (float)rb[q];
+      }
     }
   };
   if (k0 >= k1) return idle;
@@ -642,7 +707,7 @@ __device__ __forceinline__ void tile128(const TA *__restrict__ A, int64_t lda,
                                         const TBT *__restrict__ B, int64_t ldb, int nA, int nB,
                                         int k0, int k1, bool lower, F f) {
   if constexpr (F32) {
-    __shared__ Stage128f sA[2], sB[2];
+    __shared__ __align__(16) Stage128f sA[2], sB[2];
     f4x acc[2][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -661,6 +726,52 @@ __device__ __forceinline__ void tile128(const TA *__restrict__ A, int64_t lda,
       for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     if (tile128_f64<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
     acc128_foreach(acc, f);
+  }
+}
+
+// The FP32 tile product with its result handed to g(r, c, value) in coalesced order:
+// staged through LDS 64 columns at a time (column c at t[c LT + r]), then each wave
+// takes one column of 128 rows in two 64-lane runs, or with ROWMAJOR one row of 64
+// columns per run.  Every wave takes part in the barriers; a wave with nothing to
+// multiply holds zeros, so g sees every element of the tile (it applies its own
+// bounds).
+template <bool TB, bool ROWMAJOR, typename TA, typename TBT, typename G>
+__device__ __forceinline__ void tile128_f32_staged(const TA *__restrict__ A, int64_t lda,
+                                                   const TBT *__restrict__ B, int64_t ldb,
+                                                   int nA, int nB, int k0, int k1, bool lower,
+                                                   G g) {
+  __shared__ __align__(16) float sm[4 * KSF * LDQF];
+  Stage128f *sA = reinterpret_cast<Stage128f *>(sm), *sB = sA + 2;
+  constexpr int LT = 128 + 4;
+  static_assert(4 * KSF * LDQF >= 64 * LT, "half tile fits the stage buffers");
+  f4x acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
+  tile128_f32<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * 32;
+  for (int h = 0; h < 2; ++h) {
+    __syncthreads();
+    if ((w & 1) == h) {
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            sm[(16 * j + (lane & 15)) * LT + wm + 16 * i + 4 * (lane >> 4) + q] = acc[i][j][q];
+    }
+    __syncthreads();
+    if (!ROWMAJOR) {
+      for (int c = w; c < 64; c += T128_THREADS / 64)
+#pragma unroll
+        for (int rr = lane; rr < 128; rr += 64) g(rr, 64 * h + c, (double)sm[c * LT + rr]);
+    } else {
+      for (int r = w; r < 128; r += T128_THREADS / 64)
+        g(r, 64 * h + lane, (double)sm[lane * LT + r]);
+    }
   }
 }
 
@@ -686,9 +797,12 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
     }
   };
   if constexpr (F32) {      // the outer block's columns from their FP32 copy (chol_panel)
+    // (in a diagonal tile the part above the diagonal is left alone: nothing reads it)
     const float *P32 = reinterpret_cast<const float *>(ws + d.off_lo);
-    tile128<false, true>(P32 + r0, ld, P32 + c0, ld, ld - r0, ld - c0, 0, k1 - k0, ti == tj,
-                         apply);
+    tile128_f32_staged<false, false>(P32 + r0, ld, P32 + c0, ld, ld - r0, ld - c0, 0, k1 - k0,
+                                     ti == tj, [&](int r, int c, double v) {
+                                       if (ti != tj || r >= c) apply(r, c, v);
+                                     });
   } else {
     tile128<false, false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj, apply);
   }
@@ -761,10 +875,16 @@ void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   // which is how trtri_outer_x reads it then
   typedef typename std::conditional<F32, float, double>::type TT;
   TT *T = reinterpret_cast<TT *>(ws + d.off_lo);
-  tile128<true, F32>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
-                     ld - r0, 128, c0, TW, false, [&](int r, int c, double v) {
-                       if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = (TT)v;
-                     });
+  auto put = [&](int r, int c, double v) {
+    if (r0 + r < ld) T[(int64_t)(r0 + r - J1) * TW + c0 + c] = (TT)v;
+  };
+  if constexpr (F32)        // T is row major: stored a row at a time
+    tile128_f32_staged<true, true>(Sb + (int64_t)J0 * ld + r0, ld,
+                                   Sb + (int64_t)(J0 + c0) * ld + J0, ld, ld - r0, 128, c0, TW,
+                                   false, put);
+  else
+    tile128<true, false>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
+                         ld - r0, 128, c0, TW, false, put);
 }
 
 template <bool F32>
@@ -780,10 +900,15 @@ void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
   typedef typename std::conditional<F32, float, double>::type TT;
   const TT *T = reinterpret_cast<const TT *>(ws + d.off_lo);
   const int kend = (r0 + 128 < ld ? r0 + 128 : ld) - J1;       // X[i, k] = 0 for k > i
-  tile128<false, F32>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, false,
-                      [&](int r, int c, double v) {
-                        if (r0 + r < ld) Sb[(int64_t)(J0 + c0 + c) * ld + r0 + r] = -v;
-                      });
+  auto put = [&](int r, int c, double v) {
+    if (r0 + r < ld) Sb[(int64_t)(J0 + c0 + c) * ld + r0 + r] = -v;
+  };
+  if constexpr (F32)
+    tile128_f32_staged<false, false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128,
+                                     0, kend, false, put);
+  else
+    tile128<false, false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend,
+                          false, put);
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restrict__ desc,
