@@ -234,14 +234,20 @@ __global__ __launch_bounds__(256) void panel_mfma_kernel(const SubDesc *__restri
   }
 }
 
-// Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c]) in FP64; the next 64-row
-// chunk of L^-1 and V - W is loaded into registers while the current one is used.
-// The contraction runs on v_mfma_f64_16x16x4_f64: wave w owns rows i0 + 16 w .. + 15
-// and the two 16-column blocks; A(i, k) = L^-1(k, i) comes from lane i + 16 k and
-// B(k, c) from lane c + 16 k, and D(i, c) sits in lane c + 16 (i % 4), register i / 4.
-__global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ desc,
-                                                   const SubState *__restrict__ st, char *ws,
-                                                   int qv, int qw) {
+// Dcol[i, c] = 1/2 sum_{k >= i} Linv[k, i] (V[k, c] - W[k, c]) in FP64 on
+// v_mfma_f64_16x16x4_f64, straight from global memory (no LDS, no barriers): wave w
+// owns rows i0 + 16 w .. + 15 of Dcol and the two 16-column blocks of the chunk.  The
+// instruction takes A(i, k) from lane i + 16 k and B(k, c) from lane c + 16 k; the
+// sum over k may run in any order that A and B share, so within each 32-row chunk
+// of k, k slot j of step s is row k0 + 8 j + s: lane i + 16 j reads 8 consecutive
+// rows of column i of L^-1 (64 contiguous bytes) and lane c + 16 j 8 rows of V and
+// W.  The next chunk is loaded while the current one is multiplied.  D(i, c) sits
+// in lane c + 16 (i % 4), register i / 4.
+constexpr int DCOL_KC = 32;             // rows of k per chunk
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void dcol_kernel(const SubDesc *__restrict__ desc, const SubState *__restrict__ st, char *ws,
+                 int qv, int qw) {
   const SubDesc d = desc[blockIdx.y];
   if (st[blockIdx.y].status != 0) return;
   const int c0 = MAXM * blockIdx.z;              // this workgroup's chunk of own columns
@@ -254,57 +260,61 @@ __global__ __launch_bounds__(256) void dcol_kernel(const SubDesc *__restrict__ d
   const float *V = panel_ptr(ws, d, qv) + co;
   const float *W = panel_ptr(ws, d, qw) + co;
   double *Dc = reinterpret_cast<double *>(ws + d.off_dcol) + co;
-  __shared__ double sL[64][65];     // sL[i][k] = Linv[k0 + k, i0 + i]
-  __shared__ double sU[64][33];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int kq = 8 * (lane >> 4);                // this lane's rows within a chunk
+  // L^-1 is lower triangular: rows k < i0 of these columns are zero, so k starts at i0
+  const double *Lc = Li + (int64_t)(i0 + 16 * w + (lane & 15)) * ld + kq;
+  const float *Vc[2], *Wc[2];
+  bool cin[2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    const int c = 16 * t + (lane & 15);
+    cin[t] = c < m;
+    Vc[t] = V + (int64_t)(cin[t] ? c : 0) * ld + kq;
+    Wc[t] = W + (int64_t)(cin[t] ? c : 0) * ld + kq;
+  }
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  double a[2][8], u[2][2][8];
+  auto fetch = [&](int k0, int b) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const d2 v = *reinterpret_cast<const d2 *>(Lc + k0 + 2 * j);
+      a[b][2 * j] = v.x;
+      a[b][2 * j + 1] = v.y;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        float4 x = {0.0f, 0.0f, 0.0f, 0.0f}, y = x;
+        if (cin[t]) {
+          x = *reinterpret_cast<const float4 *>(Vc[t] + k0 + 4 * j);
+          y = *reinterpret_cast<const float4 *>(Wc[t] + k0 + 4 * j);
+        }
+        u[b][t][4 * j] = (double)x.x - (double)y.x;
+        u[b][t][4 * j + 1] = (double)x.y - (double)y.y;
+        u[b][t][4 * j + 2] = (double)x.z - (double)y.z;
+        u[b][t][4 * j + 3] = (double)x.w - (double)y.w;
+      }
+    }
+  };
   d4 acc[2] = {d4{0.0, 0.0, 0.0, 0.0}, d4{0.0, 0.0, 0.0, 0.0}};
-  double lv[16], uv[8];
-  auto fetch = [&](int k0) {
+  auto mul = [&](int b) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q, kk = e & 63, ii = e >> 6;
-      lv[q] = Li[(int64_t)(i0 + ii) * ld + k0 + kk];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q, kk = e & 63, c = e >> 6;
-      const int64_t x = (int64_t)c * ld + k0 + kk;
-      uv[q] = c < m ? (double)V[x] - (double)W[x] : 0.0;
-    }
-  };
-  auto stage = [&]() {
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;
-      sL[e >> 6][e & 63] = lv[q];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int e = tid + 256 * q;
-      sU[e & 63][e >> 6] = uv[q];
-    }
-  };
-  fetch(i0);
-  stage();
-  __syncthreads();
-  for (int k0 = i0; k0 < ld; k0 += 64) {
-    const bool more = k0 + 64 < ld;
-    if (more) fetch(k0 + 64);
-#pragma unroll
-    for (int kk = 0; kk < 64; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      const double a = sL[16 * w + (lane & 15)][kr];
+    for (int s2 = 0; s2 < 8; ++s2)
 #pragma unroll
       for (int t = 0; t < 2; ++t)
-        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sU[kr][16 * t + (lane & 15)], acc[t],
-                                                       0, 0, 0);
-    }
-    __syncthreads();
-    if (more) {
-      stage();
-      __syncthreads();
-    }
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[b][s2], u[b][t][s2], acc[t], 0, 0, 0);
+  };
+  fetch(i0, 0);
+  int k0 = i0;
+  for (; k0 + DCOL_KC < ld; k0 += 2 * DCOL_KC) {
+    fetch(k0 + DCOL_KC, 1);
+    mul(0);
+    if (k0 + 2 * DCOL_KC < ld) fetch(k0 + 2 * DCOL_KC, 0);
+    mul(1);
   }
+  if (k0 < ld) mul(0);
 #pragma unroll
   for (int t = 0; t < 2; ++t) {
     const int c = 16 * t + (lane & 15);
