@@ -9,8 +9,12 @@
 // Kernels (all batched over the planned submatrices, one launch per block step):
 //   chol_diag    unblocked Cholesky of a 64x64 diagonal block in LDS, plus its inverse
 //   chol_panel   A[j+64:, j] <- A[j+64:, j] L_jj^-T                  (FP64 MFMA)
-//   chol_update  A[j+64:, j+64:] -= P P^T, lower tiles                 (FP64 MFMA)
-//   trtri_*      L^-1 in place, block columns right to left            (FP64 MFMA)
+//   chol_update, chol_update128, chol_trail
+//                A[j+64:, j+64:] -= P P^T, lower tiles: left-looking inside an outer
+//                block, right-looking between blocks (FP32 MFMA tiles on an FP32 copy
+//                of the panel; FP64 MFMA as a plan option)
+//   trtri_*      L^-1 in place, block columns right to left (outer products on FP32
+//                MFMA tiles, the rest FP64 MFMA)
 //   prep_split     L^-1 and H split into FP16 pairs (x = hi + 2^-11 lo), by rows
 //   split_gemm     U = H L^-T, then M = L^-1 U, upper tiles mirrored so that M is
 //                  exactly symmetric; M is kept in FP32 over the H buffer (FP16 MFMA,
@@ -118,124 +122,6 @@ __device__ __forceinline__ void gemm64_f64(const double *__restrict__ A, int64_t
     __syncthreads();
     b ^= 1;
   }
-}
-
-// The same product on FP32 MFMAs (v_mfma_f32_16x16x4_f32): the FP64 operands are
-// rounded to FP32 as they are staged, FP32 sums (the FP32 factorisation tiles of
-// tile128_f32); D(i, j) sits in lane j + 16 (i / 4), register i % 4.  LDS rows are
-// padded by 16 floats so that the four 16-lane groups of a read hit different banks.
-constexpr int LDPF = 64 + 16;
-
-// FP32 operands (the FP32 copy of the Cholesky panel) are read 4 rows at a time:
-// thread t takes rows 4 (t % 16) .. + 3 of stage row t / 16 (sA, sB 16-byte aligned).
-template <bool TRANSB, typename T>
-__device__ __forceinline__ void gemm64_f32(const T *__restrict__ A, int64_t lda,
-                                           const T *__restrict__ B, int64_t ldb, int k0,
-                                           int k1, f4x acc[2][2], float *sA, float *sB) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-  constexpr bool V4 = std::is_same<T, float>::value;
-  static_assert(!V4 || TRANSB, "4-wide FP32 staging reads B contiguous in n");
-  T ra[4], rb[4];
-  auto fetch = [&](int k) {
-    if constexpr (V4) {
-      const int kk = tid >> 4, m4 = (tid & 15) * 4;
-      const f4x va = *reinterpret_cast<const f4x *>(A + (int64_t)(k + kk) * lda + m4);
-      const f4x vb = *reinterpret_cast<const f4x *>(B + (int64_t)(k + kk) * ldb + m4);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        ra[q] = va[q];
-        rb[q] = vb[q];
-      }
-      return;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
-      ra[q] = A[(int64_t)(k + kk) * lda + m];
-    }
-    if (!TRANSB) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
-        rb[q] = B[(int64_t)nn * ldb + k + kk];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
-        rb[q] = B[(int64_t)(k + kk) * ldb + nn];
-      }
-    }
-  };
-  auto stage = [&](int b) {
-    float *a = sA + b * KS64 * LDPF, *bb = sB + b * KS64 * LDPF;
-    if constexpr (V4) {
-      const int kk = tid >> 4, m4 = (tid & 15) * 4;
-      *reinterpret_cast<f4x *>(a + kk * LDPF + m4) = f4x{ra[0], ra[1], ra[2], ra[3]};
-      *reinterpret_cast<f4x *>(bb + kk * LDPF + m4) = f4x{rb[0], rb[1], rb[2], rb[3]};
-      return;
-    }
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int m = tid & 63, kk = (tid >> 6) + 4 * q;
-      a[kk * LDPF + m] = (float)ra[q];
-    }
-    if (!TRANSB) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int kk = tid & 15, nn = (tid >> 4) + 16 * q;
-        bb[kk * LDPF + nn] = (float)rb[q];
-      }
-    } else {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int nn = tid & 63, kk = (tid >> 6) + 4 * q;
-        bb[kk * LDPF + nn] = (float)rb[q];
-      }
-    }
-  };
-  if (k0 >= k1) return;
-  fetch(k0);
-  stage(0);
-  __syncthreads();
-  int b = 0;
-  for (int k = k0; k < k1; k += KS64) {
-    const bool more = k + KS64 < k1;
-    if (more) fetch(k + KS64);
-    const float *a = sA + b * KS64 * LDPF, *bb = sB + b * KS64 * LDPF;
-#pragma unroll
-    for (int kk = 0; kk < KS64; kk += 4) {
-      const int kr = kk + (lane >> 4);
-      float av[2], bv[2];
-#pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = a[kr * LDPF + wm + 16 * t + (lane & 15)];
-        bv[t] = bb[kr * LDPF + wn + 16 * t + (lane & 15)];
-      }
-#pragma unroll
-      for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-        for (int bn = 0; bn < 2; ++bn)
-          acc[bm][bn] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[bm], bv[bn], acc[bm][bn], 0, 0, 0);
-    }
-    if (more) stage(b ^ 1);
-    __syncthreads();
-    b ^= 1;
-  }
-}
-
-template <typename F>
-__device__ __forceinline__ void acc64f_foreach(f4x acc[2][2], F f) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
-#pragma unroll
-  for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-    for (int bn = 0; bn < 2; ++bn)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        f(wm + 16 * bm + 4 * (lane >> 4) + q, wn + 16 * bn + (lane & 15), (double)acc[bm][bn][q]);
 }
 
 __device__ __forceinline__ void acc_zero(d4 acc[2][2]) {
@@ -438,8 +324,7 @@ __global__ __launch_bounds__(256) void chol_panel_kernel(const SubDesc *__restri
 // tj in [cb0, cb1) and ti >= tj (lower tiles only).  blockIdx.x enumerates the
 // rectangle ti in [cb0, nb_max), tj in [cb0, cb1) column by column; tiles above
 // the diagonal or beyond this submatrix exit at once.
-// F32: the product on FP32 MFMAs (gemm64_f32), with the factorisation's FP32 tiles.
-template <bool F32>
+// (FP64 factorisation; with the FP32 tiles chol_update128_kernel does this step.)
 __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restrict__ desc,
                                                           char *ws, int k0, int k1, int cb0,
                                                           int cb1, int rows) {
@@ -448,37 +333,16 @@ __global__ __launch_bounds__(256) void chol_update_kernel(const SubDesc *__restr
   const int nb = ld / 64;
   if (ti < tj || ti >= nb || tj >= nb || k0 >= ld) return;
   const int r0 = ti * 64, c0 = tj * 64;
-  auto apply = [&](int r, int c, double v) {
+  // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
+  __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
+  d4 acc[2][2];
+  acc_zero(acc);
+  gemm64_f64<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0, k1 - k0,
+                   acc, sA, sB);
+  acc_foreach(acc, [&](int r, int c, double v) {
     double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
     *p = *p - v;
-  };
-  // C(r, c) -= sum_s L(r0 + r, s) L(c0 + c, s);  B(k=s, n=c) = S[s*ld + c0 + c]
-  if constexpr (F32) {
-    // the columns k0 .. k1 of the outer block from their FP32 copy (chol_panel: column
-    // s - k0, rows below the diagonal block of s, which covers rows r0 and c0 here)
-    __shared__ __align__(16) float sm[4 * KS64 * LDPF];
-    constexpr int LT = 64 + 1;
-    static_assert(4 * KS64 * LDPF >= 64 * LT, "result tile fits the stage buffers");
-    const float *P32 = reinterpret_cast<const float *>(ws + d.off_lo);
-    f4x acc[2][2];
-#pragma unroll
-    for (int bm = 0; bm < 2; ++bm)
-#pragma unroll
-      for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
-    gemm64_f32<true>(P32 + r0, ld, P32 + c0, ld, 0, k1 - k0, acc, sm, sm + 2 * KS64 * LDPF);
-    // through LDS (column c at sm[c LT + r]), then one 512-byte column per wave and step
-    acc64f_foreach(acc, [&](int r, int c, double v) { sm[c * LT + r] = (float)v; });
-    __syncthreads();
-    const int lane = threadIdx.x & 63;
-    for (int c = threadIdx.x >> 6; c < 64; c += 4) apply(lane, c, (double)sm[c * LT + lane]);
-  } else {
-    __shared__ double sA[2 * KS64 * LDP], sB[2 * KS64 * LDP];
-    d4 acc[2][2];
-    acc_zero(acc);
-    gemm64_f64<true>(Sb + (int64_t)k0 * ld + r0, ld, Sb + (int64_t)k0 * ld + c0, ld, 0,
-                     k1 - k0, acc, sA, sB);
-    acc_foreach(acc, apply);
-  }
+  });
 }
 
 // 128 x 128 FP64 tile product for the blocked set-up steps:
@@ -753,6 +617,7 @@ __device__ __forceinline__ void tile128_f32_staged(const TA *__restrict__ A, int
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 32;
   for (int h = 0; h < 2; ++h) {
+    if (64 * h >= nB) break;           // no live columns in this half (uniform)
     __syncthreads();
     if ((w & 1) == h) {
 #pragma unroll
@@ -806,6 +671,29 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
   } else {
     tile128<false, false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj, apply);
   }
+}
+
+// Left-looking update of column block cb inside an outer block on the FP32 tiles:
+//   A[r, c] -= sum_{k0 <= s < k1} L[r, s] L[c, s],  r >= 64 cb, c in column block cb,
+// in 128-row tiles (rows 64 cb + 128 x .. + 127) of the 8-wave FP32 tile product with
+// 64 live columns (the waves of the other 64 only share the loads), operands from
+// the outer block's FP32 panel copy (chol_panel: column s - k0, rows below the
+// diagonal block of s, which covers every row read here), results through LDS.
+__global__ __launch_bounds__(T128_THREADS) __attribute__((amdgpu_waves_per_eu(4)))
+void chol_update128_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k1, int cb) {
+  int tile, sub;
+  remap_tile_sub(tile, sub);
+  SUB_PTRS_AT(sub)
+  const int c0 = cb * NB, r0 = c0 + tile * 128;
+  if (r0 >= ld || k0 >= ld) return;
+  const float *P32 = reinterpret_cast<const float *>(ws + d.off_lo);
+  tile128_f32_staged<false, false>(P32 + r0, ld, P32 + c0, ld, ld - r0, NB, 0, k1 - k0, false,
+                                   [&](int r, int c, double v) {
+                                     if (c < NB && r0 + r < ld) {
+                                       double *p = Sb + (int64_t)(c0 + c) * ld + r0 + r;
+                                       *p = *p - v;
+                                     }
+                                   });
 }
 
 // ------------------------------------------------------------------ L^-1 in place
@@ -1031,8 +919,12 @@ static void launch_factor(const SubDesc *desc, SubState *st, int K, int max_npad
     for (int jb = J; jb < Jend; ++jb) {
       if (jb > J) {
         const int rows = nbmax - jb;
-        chol_update_kernel<F32><<<dim3(rows, K), 256, 0, s>>>(desc, ws, J * NB, jb * NB, jb,
-                                                              jb + 1, rows);
+        if (F32)
+          chol_update128_kernel<<<dim3((rows * NB + 127) / 128, K), T128_THREADS, 0, s>>>(
+              desc, ws, J * NB, jb * NB, jb);
+        else
+          chol_update_kernel<<<dim3(rows, K), 256, 0, s>>>(desc, ws, J * NB, jb * NB, jb, jb + 1,
+                                                           rows);
       }
       chol_diag_kernel<<<dim3(1, K), 256, 0, s>>>(desc, st, ws, jb);
       const int rem = nbmax - jb - 1;
