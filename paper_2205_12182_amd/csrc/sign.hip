@@ -267,15 +267,6 @@ __global__ void scale_init_kernel(const SubDesc *__restrict__ desc, SubState *__
 }
 
 // X_0 = (M - mu I) / b in the submatrix's precision; zero outside n x n.
-template <typename TI>
-__device__ void cast_col(const float *M, TI *X, int n, int ld, int c, double mu, double inv_b) {
-  for (int r = threadIdx.x; r < ld; r += blockDim.x) {
-    double v = 0.0;
-    if (r < n && c < n) v = ((double)M[(int64_t)c * ld + r] - (r == c ? mu : 0.0)) * inv_b;
-    X[(int64_t)c * ld + r] = from_f64<TI>(v);
-  }
-}
-
 // One wave per column, four consecutive rows per lane (16-byte reads of M); kb: the
 // k-blocked layout (four consecutive rows stay adjacent).
 template <typename TI>
@@ -336,19 +327,23 @@ __global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol,
 
 __global__ void clear_count_kernel(unsigned *__restrict__ cnt) { *cnt = 0u; }
 
-// X_0 of the restarting submatrices: one workgroup per submatrix, all columns;
-// returns at once when nothing restarts.
+// X_0 of the restarting submatrices (FP32, column-major): grid (npad / CAST_FB_COLS,
+// K), a wave per column at a time as in cast_kernel; every workgroup returns at once
+// when nothing restarts.
+constexpr int CAST_FB_COLS = 32;
+
 __global__ __launch_bounds__(256) void cast_fb_kernel(const SubDesc *__restrict__ desc,
                                                       const SubState *__restrict__ st, char *ws,
                                                       double mu, const unsigned *__restrict__ cnt) {
   if (*cnt == 0u) return;
-  const SubDesc d = desc[blockIdx.x];
-  const SubState &s = st[blockIdx.x];
+  const SubDesc d = desc[blockIdx.y];
+  const SubState &s = st[blockIdx.y];
   if (s.status != 0 || !s.fell_back) return;
   const float *M = reinterpret_cast<const float *>(ws + d.off_h);      // FP32 M
   const double inv_b = 1.0 / s.scale;
-  for (int c = 0; c < d.npad; ++c)
-    cast_col<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
+  for (int c = blockIdx.x * CAST_FB_COLS + (threadIdx.x >> 6);
+       c < (blockIdx.x + 1) * CAST_FB_COLS && c < d.npad; c += 4)
+    cast_col4<float>(M, buf_ptr<float>(ws, d, 0), d.n, d.npad, c, mu, inv_b);
 }
 
 __global__ void fb_finish_kernel(SubState *__restrict__ st, int K) {
@@ -521,7 +516,8 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
     fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol, ts.fb_count);
     scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, nullptr, 0.0f,
                                               P_FP32, 1);
-    cast_fb_kernel<<<K, 256, 0, s>>>(desc, st, ws, mu, ts.fb_count);
+    cast_fb_kernel<<<dim3((max_npad + CAST_FB_COLS - 1) / CAST_FB_COLS, K), 256, 0, s>>>(
+        desc, st, ws, mu, ts.fb_count);
     if (literal) launch_lit_transpose(desc, st, K, max_npad, ws, 2, 0, ts.fb_count, s);
     nolsm_phase fb;
     fb.prec = P_FP32;
