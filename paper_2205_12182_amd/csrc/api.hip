@@ -63,7 +63,8 @@ struct nolsm_plan {
   size_t tab_bytes = 0;
   // workspace (bytes from the workspace base)
   size_t off_counter = 0;       // unsigned long long: executed sign-GEMM work (FLOP_UNIT),
-                                // then an unsigned count of FP32 restarts
+                                // then two unsigned: FP32 restarts, and of those the
+                                // ones still iterating
   size_t bytes = 0;
   char *tab = nullptr;          // table buffer the tables were last uploaded to
   char *tab_ws = nullptr;       // workspace of the last upload (persist plans: the uploaded
@@ -309,7 +310,7 @@ static nolsm_status plan_build(const nolsm_pattern *pat, const int32_t *grp_ptr,
   // arenas are laid out in the plan's own buffer instead.
   off = 0;
   p->off_counter = off;
-  off = align256(off + sizeof(unsigned long long) + sizeof(unsigned));
+  off = align256(off + sizeof(unsigned long long) + 2 * sizeof(unsigned));
   size_t poff = 0;
   for (int i = 0; i < K; ++i) {
     SubDesc &d = p->desc[i];
@@ -471,6 +472,7 @@ static TileSet tile_set(const nolsm_plan *p, const Tile *tiles) {
   }
   ts.flop_units = reinterpret_cast<unsigned long long *>(p->ws + p->off_counter);
   ts.fb_count = reinterpret_cast<unsigned *>(p->ws + p->off_counter + sizeof(unsigned long long));
+  ts.fb_live = ts.fb_count + 1;
   return ts;
 }
 

@@ -90,6 +90,7 @@ struct TileSet {
   int n[NTILELIST];
   unsigned long long *flop_units;   // executed MFMA work of active tiles, in FLOP_UNIT
   unsigned *fb_count;               // submatrices selected for the FP32 restart
+  unsigned *fb_live;                // of those, the ones still iterating (gates its products)
 };
 // 2 * 16 * 16 * 64 flops: one 16 x 16 output block over 64 k (tile edges and npad
 // are multiples of these, so the count is exact)

@@ -401,8 +401,8 @@ __global__ __launch_bounds__(256) void ns_gemm_kernel(const Tile *__restrict__ t
 
 // FP32 products of the restart phase.  Usually no submatrix restarts, so the
 // launches are gated: a small grid (at most FB_GRID workgroups, two per CU) walks
-// the tile list in rounds and every workgroup returns at once when the restart
-// count is zero.  Within a round, consecutive tiles go to one XCD as above.
+// the tile list in rounds and every workgroup returns at once when no restarting
+// submatrix is still iterating (the count the stop decisions decrement).  Within a round, consecutive tiles go to one XCD as above.
 constexpr int FB_GRID = 512;
 
 template <int EPI>

@@ -41,6 +41,7 @@ namespace nolsm {
 struct PhaseArgs {
   int prec, t, iters, extra, use_lower, order;
   float tol;
+  unsigned *live;     // the FP32 restart phase: restarting submatrices still iterating
 };
 
 // Coefficients (c1, c3) of the third-order step's two SQUARE epilogues.
@@ -107,6 +108,7 @@ __global__ void ns_check_kernel(const SubDesc *__restrict__ desc, SubState *__re
   }
   if (!go) {
     s.active = 0;
+    if (p.live) atomicSub(p.live, 1u);
   } else if (p.order == 3) {      // the next product squares W
     s.cur = (s.cur + 1) % 3;
     s.c1 = O3_Z_C1;
@@ -127,7 +129,7 @@ __global__ void ns_shift_kernel(SubState *__restrict__ st, int K, int prec) {
 
 // rotate = 0 (the literal form, literal.hip): the buffers keep fixed roles.
 __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, int use_lower,
-                                  int fallback, int order, int rotate) {
+                                  int fallback, int order, int rotate, unsigned *live) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -140,6 +142,7 @@ __global__ void ns_advance_kernel(SubState *__restrict__ st, int K, int prec, in
     // the stop decision already taken (the residual on record stays the last one
     // measured, which met the tolerance)
     s.active = 0;
+    if (live) atomicSub(live, 1u);
     return;
   }
   if (use_lower && s.lower < 1.0) {
@@ -311,9 +314,10 @@ __global__ __launch_bounds__(256) void cast_kernel(const SubDesc *__restrict__ d
 
 // Fallback selection: not converged in a tolerance phase and residual above tol
 // (or non-finite) -> restart from X_0 in FP32 with the Gershgorin scale.
-// The selected submatrices are counted in *cnt (cleared by clear_count_kernel).
+// The selected submatrices are counted in *cnt and in *live (both cleared by
+// clear_count_kernel); the restart phase takes each one off *live as it stops.
 __global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol,
-                                 unsigned *__restrict__ cnt) {
+                                 unsigned *__restrict__ cnt, unsigned *__restrict__ live) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
   SubState &s = st[i];
@@ -322,10 +326,14 @@ __global__ void fb_select_kernel(SubState *__restrict__ st, int K, float tol,
   if (!s.converged && !(s.resid <= tol)) {
     s.fell_back = 1;
     atomicAdd(cnt, 1u);
+    atomicAdd(live, 1u);
   }
 }
 
-__global__ void clear_count_kernel(unsigned *__restrict__ cnt) { *cnt = 0u; }
+__global__ void clear_count_kernel(unsigned *__restrict__ cnt, unsigned *__restrict__ live) {
+  *cnt = 0u;
+  *live = 0u;
+}
 
 // X_0 of the restarting submatrices (FP32, column-major): grid (npad / CAST_FB_COLS,
 // K), a wave per column at a time as in cast_kernel; every workgroup returns at once
@@ -423,10 +431,10 @@ static void gated_gemm(int epi, const TileSet &ts, const SubDesc *desc, SubState
     const int grid = ts.n[l] < FB_GRID ? ts.n[l] : FB_GRID;
     if (epi == EPI_SQUARE)
       ns_gemm_gated_kernel<EPI_SQUARE><<<grid, 256, 0, s>>>(ts.t[l], ts.n[l], desc, st, ws,
-                                                            ts.fb_count, ts.flop_units);
+                                                            ts.fb_live, ts.flop_units);
     else
       ns_gemm_gated_kernel<EPI_UPDATE><<<grid, 256, 0, s>>>(ts.t[l], ts.n[l], desc, st, ws,
-                                                            ts.fb_count, ts.flop_units);
+                                                            ts.fb_live, ts.flop_units);
   }
 }
 
@@ -465,6 +473,7 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, int max_npad, const 
   p.tol = ph.tol;
   p.use_lower = use_lower;
   p.order = ph.order == 3 ? 3 : 2;
+  p.live = fallback ? ts.fb_live : nullptr;
   const int last = (ph.tol > 0.0f) ? ph.iters : ph.iters - 1;
   for (int t = 0; t <= last; ++t) {
     p.t = t;
@@ -479,7 +488,7 @@ void launch_phase(const SubDesc *desc, SubState *st, int K, int max_npad, const 
     // end a submatrix's iteration
     if (literal) launch_lit_transpose(desc, st, K, max_npad, ws, 1, ph.prec, nullptr, s);
     ns_advance_kernel<<<nblk(K), 256, 0, s>>>(st, K, ph.prec, use_lower, fallback, p.order,
-                                              literal ? 0 : 1);
+                                              literal ? 0 : 1, p.live);
   }
   phase_end_kernel<<<nblk(K), 256, 0, s>>>(st, K);
 }
@@ -512,8 +521,8 @@ void launch_sign(const SubDesc *desc, SubState *st, int K, int max_npad, const T
   }
 
   if (sch.fallback_iters > 0) {
-    clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count);
-    fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol, ts.fb_count);
+    clear_count_kernel<<<1, 1, 0, s>>>(ts.fb_count, ts.fb_live);
+    fb_select_kernel<<<nblk(K), 256, 0, s>>>(st, K, sch.fallback_tol, ts.fb_count, ts.fb_live);
     scale_init_kernel<<<nblk(K), 256, 0, s>>>(desc, st, K, nullptr, nullptr, nullptr, 0.0f,
                                               P_FP32, 1);
     cast_fb_kernel<<<dim3((max_npad + CAST_FB_COLS - 1) / CAST_FB_COLS, K), 256, 0, s>>>(
