@@ -550,55 +550,29 @@ __device__ __forceinline__ bool tile128_f32(const TA *__restrict__ A, int64_t ld
   return idle;
 }
 
-template <typename F>
-__device__ __forceinline__ void acc128f_foreach(f4x acc[2][4], F f) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wm = (w >> 1) * 32, wn = (w & 1) * 64;
+// One 128 x 128 tile product on FP64 MFMAs (the FP64 factorisation option; the FP32
+// tiles go through tile128_f32_staged); f(r, c, value) visits the result unless every
+// wave was idle (then nothing is to be applied).
+template <bool TB, typename F>
+__device__ __forceinline__ void tile128(const double *__restrict__ A, int64_t lda,
+                                        const double *__restrict__ B, int64_t ldb, int nA, int nB,
+                                        int k0, int k1, bool lower, F f) {
+  __shared__ Stage128 sA[2], sB[2];
+  d4 acc[2][4];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        f(wm + 16 * i + 4 * (lane >> 4) + q, wn + 16 * j + (lane & 15), (double)acc[i][j][q]);
-}
-
-// One 128 x 128 tile product in FP64 or (F32) FP32 MFMAs; f(r, c, value) visits the
-// result unless every wave was idle (then nothing is to be applied).  FP32 operands
-// (the FP32 copies of the factor's panel and of T) are read only with F32.
-template <bool TB, bool F32, typename TA, typename TBT, typename F>
-__device__ __forceinline__ void tile128(const TA *__restrict__ A, int64_t lda,
-                                        const TBT *__restrict__ B, int64_t ldb, int nA, int nB,
-                                        int k0, int k1, bool lower, F f) {
-  if constexpr (F32) {
-    __shared__ __align__(16) Stage128f sA[2], sB[2];
-    f4x acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = f4x{0.0f, 0.0f, 0.0f, 0.0f};
-    if (tile128_f32<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
-    acc128f_foreach(acc, f);
-  } else {
-    static_assert(std::is_same<TA, double>::value && std::is_same<TBT, double>::value,
-                  "FP64 tiles take FP64 operands");
-    __shared__ Stage128 sA[2], sB[2];
-    d4 acc[2][4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    if (tile128_f64<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
-    acc128_foreach(acc, f);
-  }
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  if (tile128_f64<TB>(A, lda, B, ldb, nA, nB, k0, k1, acc, sA, sB, lower)) return;
+  acc128_foreach(acc, f);
 }
 
 // The FP32 tile product with its result handed to g(r, c, value) in coalesced order:
 // staged through LDS 64 columns at a time (column c at t[c LT + r]), then each wave
 // takes one column of 128 rows in two 64-lane runs, or with ROWMAJOR one row of 64
 // columns per run.  Every wave takes part in the barriers; a wave with nothing to
-// multiply holds zeros, so g sees every element of the tile (it applies its own
-// bounds).
+// multiply holds zeros, so g sees every element of the tile's column halves that
+// hold live columns (c < nB; it applies its own bounds).
 template <bool TB, bool ROWMAJOR, typename TA, typename TBT, typename G>
 __device__ __forceinline__ void tile128_f32_staged(const TA *__restrict__ A, int64_t lda,
                                                    const TBT *__restrict__ B, int64_t ldb,
@@ -669,7 +643,7 @@ void chol_trail_kernel(const SubDesc *__restrict__ desc, char *ws, int k0, int k
                                        if (ti != tj || r >= c) apply(r, c, v);
                                      });
   } else {
-    tile128<false, false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj, apply);
+    tile128<false>(Sb + r0, ld, Sb + c0, ld, ld - r0, ld - c0, k0, k1, ti == tj, apply);
   }
 }
 
@@ -771,8 +745,8 @@ void trtri_outer_t_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
                                    Sb + (int64_t)(J0 + c0) * ld + J0, ld, ld - r0, 128, c0, TW,
                                    false, put);
   else
-    tile128<true, false>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
-                         ld - r0, 128, c0, TW, false, put);
+    tile128<true>(Sb + (int64_t)J0 * ld + r0, ld, Sb + (int64_t)(J0 + c0) * ld + J0, ld,
+                  ld - r0, 128, c0, TW, false, put);
 }
 
 template <bool F32>
@@ -795,8 +769,8 @@ void trtri_outer_x_kernel(const SubDesc *__restrict__ desc, char *ws, int J0, in
     tile128_f32_staged<false, false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128,
                                      0, kend, false, put);
   else
-    tile128<false, false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend,
-                          false, put);
+    tile128<false>(Sb + (int64_t)J1 * ld + r0, ld, T + c0, TW, ld - r0, 128, 0, kend, false,
+                   put);
 }
 
 __global__ __launch_bounds__(256) void zero_upper_kernel(const SubDesc *__restrict__ desc,
