@@ -189,10 +189,11 @@ nolsm_status nolsm_plan_create(const nolsm_pattern *pattern_host, const int32_t 
  * (nolsm_sign_batched returns NOLSM_EINVAL otherwise); it serves to check the
  * identity of the two forms and is not tuned for speed.
  * factor_tiles: the large tile products of the Cholesky factorisation of T_k(S)
- * (trailing updates) and of L^-1 (outer block products); L and L^-1 are stored in
- * FP64 either way.  0 (default): FP32 MFMAs on operands rounded to FP32, FP32 sums
- * (L^-1 S L^-T - I of a few 1e-7, density columns within about 1e-7 of the FP64
- * factor's).  1: FP64 MFMAs throughout.  Other values: NOLSM_EINVAL. */
+ * (trailing and left-looking updates) and of L^-1 (outer block products); L and
+ * L^-1 are stored in FP64 either way.  0 (default): FP32 MFMAs on operands rounded
+ * to FP32 (FP32 copies of the panels, in the iteration arena during the set-up),
+ * FP32 sums (L^-1 S L^-T - I of a few 1e-7, density columns within about 1e-7 of
+ * the FP64 factor's).  1: FP64 MFMAs throughout.  Other values: NOLSM_EINVAL. */
 typedef struct {
   int32_t big_tile_min_npad;
   int32_t setup_products;
